@@ -1,0 +1,287 @@
+"""Pins of the oracle's two potentials against what mathematics fixes independently of
+the code: closed forms of the radial pieces, Legendre addition for the angular moments,
+symmetries (translation, rotation, permutation of atoms and of hidden channels),
+locality and receptive field, and central finite differences of the energy."""
+
+import math
+
+import numpy as np
+import pytest
+from scipy.special import expit
+
+from oracle import potentials as P
+from paper_2510_06562_amd import synth
+
+
+def _model(kind, cutoff=None, K=None, F=None, D=16, seed=5, scale=0.01):
+    cutoff = cutoff or (3.5 if kind == 0 else 5.2)
+    K = K or (16 if kind == 0 else 32)
+    F = F or (64 if kind == 0 else 128)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in P._layout(kind, K, F, D, 5):
+        fan_in = 5 if name == "emb" else shape[-1]
+        parts.append(rng.standard_normal(int(np.prod(shape))) / math.sqrt(fan_in))
+    w = np.concatenate(parts).astype(np.float32)
+    return P.make_model(kind, cutoff, K, F, w, emb_dim=D, energy_scale=scale)
+
+
+SMALL = P.make_model(0, 3.5, 16, 64, synth.model_weights(synth.SMALL, synth.SMALL_SEED))
+LARGE = P.make_model(1, 5.2, 32, 128, synth.model_weights(synth.LARGE, synth.LARGE_SEED))
+
+
+def _cluster(n, seed, spread=2.2):
+    rng = np.random.default_rng(seed)
+    pos = rng.normal(scale=spread, size=(n, 3))
+    sp = rng.integers(0, 5, size=n).astype(np.int32)
+    return pos, sp
+
+
+# ------------------------------------------------------------------ radial pieces
+def test_cutoff_closed_form():
+    rc = 3.5
+    r = np.array([0.0, rc / 2, rc, rc * (1 - 1e-9), 4.0])
+    fc, dfc = P.cosine_cutoff(r, rc)
+    assert fc[0] == 1.0 and dfc[0] == 0.0
+    assert fc[1] == pytest.approx(0.5, abs=1e-15)
+    assert dfc[1] == pytest.approx(-math.pi / (2 * rc), rel=1e-15)
+    assert fc[2] == 0.0 and dfc[2] == 0.0          # strict r < rc
+    assert abs(fc[3]) < 1e-15 and abs(dfc[3]) < 1e-8
+    assert fc[4] == 0.0
+
+
+def test_rbf_closed_form():
+    rc, K = 5.2, 32
+    mu = np.arange(K) * rc / (K - 1)
+    b, db = P.rbf(mu, rc, K)
+    np.testing.assert_allclose(np.diag(b), 1.0, rtol=0, atol=1e-15)   # peak at its centre
+    np.testing.assert_allclose(np.diag(db), 0.0, atol=1e-12)
+    # neighbouring centres are one sigma apart: exp(-1/2)
+    np.testing.assert_allclose(np.diag(b, 1), math.exp(-0.5), rtol=1e-14)
+    # derivative against a central difference
+    r = np.array([1.234, 2.5])
+    h = 1e-6
+    fd = (P.rbf(r + h, rc, K)[0] - P.rbf(r - h, rc, K)[0]) / (2 * h)
+    np.testing.assert_allclose(P.rbf(r, rc, K)[1], fd, atol=1e-8)
+
+
+def test_silu_matches_logistic():
+    t = np.linspace(-30, 30, 241)
+    np.testing.assert_allclose(P.silu(t), t * expit(t), rtol=1e-14, atol=1e-300)
+    h = 1e-6
+    np.testing.assert_allclose(P.dsilu(t), (P.silu(t + h) - P.silu(t - h)) / (2 * h), atol=1e-8)
+    assert P.silu(np.array([0.0]))[0] == 0.0 and P.dsilu(np.array([0.0]))[0] == 0.5
+
+
+# ------------------------------------------------------------------ special cases
+@pytest.mark.parametrize("model", [SMALL, LARGE], ids=["small", "large"])
+def test_isolated_atoms_have_zero_energy(model):
+    pos = np.array([[0.0, 0, 0], [20.0, 0, 0], [0, 20.0, 0]])
+    E, F, Ea = P.energy_forces(model, pos, np.array([0, 3, 4]), 0.0)
+    assert E[0] == 0.0 and np.all(F == 0.0) and np.all(Ea == 0.0)
+
+
+def test_small_dimer_closed_form_width_one():
+    """A one-channel model on a dimer is a scalar expression evaluated with math.*."""
+    m = _model(0, cutoff=3.5, K=4, F=1, D=2, seed=9, scale=0.7)
+    w = m.w
+    r = 2.1
+    z = (0, 3)   # H receiver first
+    mu = [k * 3.5 / 3 for k in range(4)]
+    sig = 3.5 / 3
+    b = [math.exp(-(r - mk) ** 2 / (2 * sig * sig)) for mk in mu]
+    fc = 0.5 * (math.cos(math.pi * r / 3.5) + 1)
+    silu = lambda t: t / (1 + math.exp(-t))  # noqa: E731
+    Wp = w["W_pair"][0]
+    E_ref = 0.0
+    for rec, snd in ((z[0], z[1]), (z[1], z[0])):
+        a = sum(Wp[k] * b[k] for k in range(4))
+        a += sum(Wp[4 + e] * w["emb"][rec, e] for e in range(2))
+        a += sum(Wp[6 + e] * w["emb"][snd, e] for e in range(2))
+        hval = fc * silu(a)
+        E_ref += 0.7 * w["w_atom2"][0] * silu(w["W_atom1"][0, 0] * hval)
+    pos = np.array([[0.0, 0, 0], [r, 0, 0]])
+    E, _, _ = P.energy_forces(m, pos, np.array(z), 0.0)
+    assert E[0] == pytest.approx(E_ref, rel=1e-13)
+
+
+def test_large_angular_invariants_follow_legendre_addition():
+    """For a centre with two neighbours u, w at angle theta:
+       |m1 u + m2 w|^2 = m1^2|u|^2 + m2^2|w|^2 + 2 m1 m2 |u||w| P1(cos theta)
+       ||m1 Y2(u) + m2 Y2(w)||^2 = 2/3 (m1^2|u|^4 + m2^2|w|^4 + 2 m1 m2 |u|^2|w|^2 P2(cos theta))
+    with P1(c) = c, P2(c) = (3c^2 - 1)/2.  The per-neighbour message m comes from the
+    centre's M0 in the two dimers."""
+    model = LARGE
+    F = model.width
+    r1, r2, theta = 1.7, 2.9, 1.1
+    x1 = np.array([r1, 0.0, 0.0])
+    x2 = r2 * np.array([math.cos(theta), math.sin(theta), 0.0])
+    sp = np.array([3, 0, 1])
+    q_a = P.large_layer1_invariants(model, np.array([[0, 0, 0], x1]), sp[:2], 0.0)[0]
+    q_b = P.large_layer1_invariants(model, np.array([[0, 0, 0], x2]), sp[[0, 2]], 0.0)[0]
+    q = P.large_layer1_invariants(model, np.array([[0, 0, 0], x1, x2]), sp, 0.0)[0]
+    m1, m2 = q_a[:F], q_b[:F]
+    u1, u2 = r1 / 5.2, r2 / 5.2
+    c = math.cos(theta)
+    np.testing.assert_allclose(q[:F], m1 + m2, rtol=1e-13, atol=1e-15)
+    p1 = m1**2 * u1**2 + m2**2 * u2**2 + 2 * m1 * m2 * u1 * u2 * c
+    p2 = (2.0 / 3.0) * (m1**2 * u1**4 + m2**2 * u2**4
+                        + 2 * m1 * m2 * u1**2 * u2**2 * (3 * c * c - 1) / 2)
+    np.testing.assert_allclose(q[F:2 * F], p1, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(q[2 * F:], p2, rtol=1e-12, atol=1e-16)
+
+
+# ------------------------------------------------------------------ locality
+@pytest.mark.parametrize("model", [SMALL, LARGE], ids=["small", "large"])
+def test_separated_clusters_are_additive(model):
+    pa, sa = _cluster(12, 1)
+    pb, sb = _cluster(9, 2)
+    pb = pb + np.array([40.0, 0, 0])
+    Ea, Fa, _ = P.energy_forces(model, pa, sa, 0.0)
+    Eb, Fb, _ = P.energy_forces(model, pb, sb, 0.0)
+    E, F, _ = P.energy_forces(model, np.vstack([pa, pb]), np.concatenate([sa, sb]), 0.0)
+    assert E[0] == pytest.approx(Ea[0] + Eb[0], rel=1e-13, abs=1e-16)
+    np.testing.assert_allclose(F, np.vstack([Fa, Fb]), atol=1e-15)
+
+
+def test_receptive_field_one_vs_two_interactions():
+    """Chain A-B-C with |AB|, |BC| < rc < |AC|: moving C changes the energy of A only when
+    there are two interactions (information flows C -> B -> A)."""
+    def energy_of_A(model, xc):
+        pos = np.array([[0.0, 0, 0], [0.6 * model.cutoff, 0, 0], [xc, 0.3, 0]])
+        return P.energy_forces(model, pos, np.array([3, 1, 2]), 0.0)[2][0]
+    for model, changes in ((SMALL, False), (LARGE, True)):
+        x1 = 1.3 * model.cutoff
+        e1, e2 = energy_of_A(model, x1), energy_of_A(model, x1 + 0.2)
+        assert (abs(e1 - e2) > 1e-9) == changes
+
+
+# ------------------------------------------------------------------ symmetries
+@pytest.mark.parametrize("model", [SMALL, LARGE], ids=["small", "large"])
+def test_translation_invariance_periodic(model):
+    sy = synth.water_192()
+    E0, F0, _ = P.energy_forces(model, sy.pos, sy.species, sy.box)
+    shift = np.array([7.3, -11.9, 30.1])                   # wraps through the faces
+    E1, F1, _ = P.energy_forces(model, sy.pos + shift, sy.species, sy.box)
+    assert E1[0] == pytest.approx(E0[0], rel=1e-12)
+    np.testing.assert_allclose(F1, F0, atol=1e-12 * np.abs(F0).max())
+
+
+@pytest.mark.parametrize("model", [SMALL, LARGE], ids=["small", "large"])
+def test_rotation_invariance_open(model):
+    pos, sp = _cluster(25, 3)
+    R = synth.random_rotation(17)
+    E0, F0, _ = P.energy_forces(model, pos, sp, 0.0)
+    E1, F1, _ = P.energy_forces(model, pos @ R.T, sp, 0.0)
+    assert E1[0] == pytest.approx(E0[0], rel=1e-12)
+    np.testing.assert_allclose(F1, F0 @ R.T, atol=1e-12 * np.abs(F0).max())
+
+
+@pytest.mark.parametrize("model", [SMALL, LARGE], ids=["small", "large"])
+def test_permutation_invariance(model):
+    pos, sp = _cluster(25, 4)
+    perm = np.random.default_rng(0).permutation(25)
+    E0, F0, Ea0 = P.energy_forces(model, pos, sp, 0.0)
+    E1, F1, Ea1 = P.energy_forces(model, pos[perm], sp[perm], 0.0)
+    assert E1[0] == pytest.approx(E0[0], rel=1e-12)
+    np.testing.assert_allclose(F1, F0[perm], atol=1e-13)
+    np.testing.assert_allclose(Ea1, Ea0[perm], atol=1e-15)
+
+
+@pytest.mark.parametrize("model", [SMALL, LARGE], ids=["small", "large"])
+def test_net_force_vanishes(model):
+    sy = synth.water_192()
+    _, F, _ = P.energy_forces(model, sy.pos, sy.species, sy.box)
+    assert np.all(np.abs(F.sum(0)) <= 1e-12 * np.abs(F).sum())
+
+
+def test_hidden_channel_permutation_invariance():
+    """Relabelling hidden channels consistently leaves E unchanged; a transposed use of any
+    square weight matrix would break this."""
+    pos, sp = _cluster(20, 6)
+    E0 = P.energy_forces(SMALL, pos, sp, 0.0)[0][0]
+    p = np.random.default_rng(1).permutation(64)
+    s = P.Model(**{**SMALL.__dict__, "w": dict(SMALL.w)})
+    s.w["W_pair"] = SMALL.w["W_pair"][p]
+    s.w["W_atom1"] = SMALL.w["W_atom1"][:, p]
+    E1 = P.energy_forces(s, pos, sp, 0.0)[0][0]
+    assert E1 == pytest.approx(E0, rel=1e-12)
+    q = np.random.default_rng(2).permutation(64)        # readout hidden layer
+    s.w["W_atom1"] = s.w["W_atom1"][q]
+    s.w["w_atom2"] = SMALL.w["w_atom2"][q]
+    assert P.energy_forces(s, pos, sp, 0.0)[0][0] == pytest.approx(E0, rel=1e-12)
+
+    E0 = P.energy_forces(LARGE, pos, sp, 0.0)[0][0]
+    p = np.random.default_rng(3).permutation(128)
+    L = P.Model(**{**LARGE.__dict__, "w": dict(LARGE.w)})
+    P3 = np.concatenate([p, 128 + p, 256 + p])
+    # permute the message channels of interaction 1 (rows of W_pair1, q-blocks of U1)
+    L.w["W_pair1"] = LARGE.w["W_pair1"][p]
+    L.w["U1"] = LARGE.w["U1"][:, P3]
+    assert P.energy_forces(L, pos, sp, 0.0)[0][0] == pytest.approx(E0, rel=1e-12)
+    # permute the atom features h (rows of U1 and U2, the h blocks of W_pair2, W_out1)
+    L.w["U1"] = L.w["U1"][p]
+    L.w["U2"] = LARGE.w["U2"][p]
+    cols = np.concatenate([np.arange(32), 32 + p, 160 + p])
+    L.w["W_pair2"] = LARGE.w["W_pair2"][:, cols]
+    L.w["W_out1"] = LARGE.w["W_out1"][:, p]
+    assert P.energy_forces(L, pos, sp, 0.0)[0][0] == pytest.approx(E0, rel=1e-12)
+
+
+# ------------------------------------------------------------------ gradients
+def _fd(model, pos, sp, box, comps, h=1e-4):
+    out = []
+    for a, c in comps:
+        xp = pos.copy()
+        xp[a, c] += h
+        xm = pos.copy()
+        xm[a, c] -= h
+        ep = P.energy_forces(model, xp, sp, box)[0][0]
+        em = P.energy_forces(model, xm, sp, box)[0][0]
+        out.append(-(ep - em) / (2 * h))
+    return np.array(out)
+
+
+def test_small_forces_match_central_differences_all_components_water192():
+    sy = synth.water_192()
+    _, F, _ = P.energy_forces(SMALL, sy.pos, sy.species, sy.box)
+    comps = [(a, c) for a in range(sy.n_atoms) for c in range(3)]
+    fd = _fd(SMALL, sy.pos, sy.species, sy.box, comps)
+    Fa = np.array([F[a, c] for a, c in comps])
+    # central differences at h = 1e-4 carry O(h^2 F''') truncation error
+    assert np.linalg.norm(fd - Fa) / np.linalg.norm(Fa) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_large_forces_match_central_differences_cluster(seed):
+    pos, sp = _cluster(18, seed, spread=1.8)
+    model = _model(1, scale=1.0, seed=seed)
+    _, F, _ = P.energy_forces(model, pos, sp, 0.0)
+    comps = [(a, c) for a in range(18) for c in range(3)]
+    fd = _fd(model, pos, sp, 0.0, comps)
+    Fa = np.array([F[a, c] for a, c in comps])
+    assert np.linalg.norm(fd - Fa) / np.linalg.norm(Fa) < 1e-6
+
+
+def test_large_forces_match_central_differences_water192_sample():
+    sy = synth.water_192()
+    _, F, _ = P.energy_forces(LARGE, sy.pos, sy.species, sy.box)
+    rng = np.random.default_rng(3)
+    comps = [(int(rng.integers(192)), int(rng.integers(3))) for _ in range(8)]
+    fd = _fd(LARGE, sy.pos, sy.species, sy.box, comps)
+    Fa = np.array([F[a, c] for a, c in comps])
+    np.testing.assert_allclose(fd, Fa, rtol=1e-5, atol=1e-9)
+
+
+def test_periodic_self_image_consistency():
+    """A box replicated 2x along each axis has 8x the energy and the same forces on the
+    replicas (the minimum-image pair set of the doubled box is the same graph)."""
+    sy = synth.water_192()
+    L = sy.box
+    E1, F1, _ = P.energy_forces(SMALL, sy.pos, sy.species, L)
+    shifts = np.array([[a, b, c] for a in (0, 1) for b in (0, 1) for c in (0, 1)]) * L
+    pos2 = np.concatenate([sy.pos + s for s in shifts])
+    sp2 = np.tile(sy.species, 8)
+    E2, F2, _ = P.energy_forces(SMALL, pos2, sp2, 2 * L)
+    assert E2[0] == pytest.approx(8 * E1[0], rel=1e-12)
+    np.testing.assert_allclose(F2[:192], F1, atol=1e-14)

@@ -1,0 +1,51 @@
+"""Input generators: determinism and the shapes the workloads call for."""
+
+import numpy as np
+
+from oracle import neighbors as NB
+from paper_2510_06562_amd import synth
+
+
+def test_generators_are_deterministic():
+    a, b = synth.water_4500(), synth.water_4500()
+    assert np.array_equal(a.pos, b.pos) and np.array_equal(a.species, b.species)
+    assert np.array_equal(synth.model_weights(synth.LARGE, 102), synth.model_weights(synth.LARGE, 102))
+    m1, m2 = synth.molecule_batch(8, 3), synth.molecule_batch(8, 3)
+    assert np.array_equal(m1.pos, m2.pos)
+
+
+def test_water_geometry():
+    sy = synth.water_box(27, 9.3, seed=5, jitter=0.0)
+    o, h1, h2 = sy.pos[0::3], sy.pos[1::3], sy.pos[2::3]
+    np.testing.assert_allclose(np.linalg.norm(h1 - o, axis=1), 0.96, rtol=1e-12)
+    cosang = np.einsum("ij,ij->i", h1 - o, h2 - o) / 0.96**2
+    np.testing.assert_allclose(np.degrees(np.arccos(cosang)), 104.5, rtol=1e-10)
+    assert sy.n_atoms == 81
+
+
+def test_workload_sizes():
+    assert synth.water_192().n_atoms == 192
+    assert synth.water_4500().n_atoms == 4500
+    b = synth.molecule_batch(256, 3)
+    sizes = np.diff(b.sys_offsets)
+    assert b.n_sys == 256 and sizes.min() >= 20 and sizes.max() <= 120
+    assert abs(b.n_atoms - 17920) < 1200
+
+
+def test_batch_chains_are_self_avoiding():
+    b = synth.molecule_batch(4, 9)
+    for m in range(4):
+        p = b.pos[b.sys_offsets[m]:b.sys_offsets[m + 1]]
+        bonds = np.linalg.norm(np.diff(p, axis=0), axis=1)
+        assert bonds.min() >= 1.1 - 1e-12 and bonds.max() <= 1.5 + 1e-12
+        i, j, _ = NB.pairs_bruteforce(p, 0.0, 1.1 - 1e-9)
+        assert np.all(np.abs(i - j) == 1) or len(i) == 0
+
+
+def test_weight_blob_sizes_and_scale():
+    ws = synth.model_weights(synth.SMALL, 101)
+    wl = synth.model_weights(synth.LARGE, 102)
+    assert ws.dtype == np.float32 and ws.size == 80 + 64 * 48 + 64 * 64 + 64
+    assert wl.size == 80 + 128 * 64 + 128 * 384 + 128 * 288 + 128 * 384 + 128 * 128 + 128
+    u = synth.unpack_weights(synth.LARGE, wl)
+    assert abs(u["U1"].std() * np.sqrt(384) - 1.0) < 0.02
