@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the DMTS hot path on one MI355X.
+
+Workload (default): 1,500 H2O (4,500 atoms) in a 35.5 A periodic cube; the one-interaction
+fast model (r_c 3.5 A) at a 1 fs inner step and the two-interaction reference model
+(r_c 5.2 A) at a 4 fs outer step, FP32 model arithmetic, FP64 integration, NVE.
+
+One timed step = one outer step of Algorithm 1 (4 fs of simulated time): 4 fast-model and
+1 reference-model energy+force evaluations, each with its neighbor-list build, plus all
+kicks and drifts.  The single-time-step baseline (velocity Verlet, 1 fs, reference model)
+is timed on the same GPU over the same simulated time.
+
+Prints one JSON line.  `value` is DMTS ns/day on the one GPU; the line also carries
+atom-steps/s (1 step = 1 fs), the Verlet rate and speedup, the force error of both models
+against the FP64 oracle, the roofline of the dominant kernel (timed live with HIP events)
+and the oracle's own rate on this host's cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DMTS ns/day & atom-steps/s vs 1 fs Verlet, same GPU; force RMSE vs FP64"
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+# Algorithmic FP32 work per real pair of each pair kernel (kernel table):
+# dense contractions at 2 flops per multiply-add plus the per-channel elementwise chain.
+#   pair2_backward: F (4 K + 40)  with K = 32, F = 128  -> 21,504
+#   pair2_forward:  F (2 K + 44)                        -> 13,824
+#   small_backward: F (4 K + 56)  with K = 16, F = 64   ->  7,680 (both directions)
+PAIR_FLOPS = {"pair2_backward": 128 * (4 * 32 + 40), "pair1_backward": 128 * (4 * 32 + 40),
+              "pair2_forward": 128 * (2 * 32 + 44), "pair1_forward": 128 * (2 * 32 + 44),
+              "small_backward": 64 * (4 * 16 + 56), "small_forward": 64 * (2 * 16 + 14)}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed outer steps (4 fs each)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="water4500", choices=["water4500", "water192"])
+    ap.add_argument("--n-inner", type=int, default=4)
+    ap.add_argument("--dt-inner", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verlet", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_oracle(sy, ws, wl, n_inner, dt_inner):
+    """Time the FP64 oracle on this host: one fast-model and one reference-model
+    evaluation of the workload (the bounded sample), extrapolated to DMTS ns/day."""
+    from oracle import potentials as OP
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    ms = OP.make_model(0, 3.5, 16, 64, ws)
+    ml = OP.make_model(1, 5.2, 32, 128, wl)
+    t0 = time.perf_counter()
+    Es, Fs, _ = OP.energy_forces(ms, sy.pos, sy.species, sy.box)
+    t1 = time.perf_counter()
+    El, Fl, _ = OP.energy_forces(ml, sy.pos, sy.species, sy.box)
+    t2 = time.perf_counter()
+    t_s, t_l = t1 - t0, t2 - t1
+    outer_fs = n_inner * dt_inner
+    wall = n_inner * t_s + t_l
+    return dict(t_small=t_s, t_large=t_l, cores=cores,
+                ns_per_day=0.0864 * outer_fs / wall,
+                Es=Es, Fs=Fs, El=El, Fl=Fl)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
+              "single-GPU in this build (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_06562_amd import api, synth
+
+    torch.cuda.set_device(0)
+    sy = synth.water_4500() if args.workload == "water4500" else synth.water_192()
+    ws = synth.model_weights(synth.SMALL, synth.SMALL_SEED)
+    wl = synth.model_weights(synth.LARGE, synth.LARGE_SEED)
+    small = api.Model.from_spec(synth.SMALL, ws)
+    large = api.Model.from_spec(synth.LARGE, wl)
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201)
+    n_inner, dt_in = args.n_inner, args.dt_inner
+    dt_out = n_inner * dt_in
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------------- GPU forces for the error
+    pot_s = api.Potential(small, sy.n_atoms, sy.box, 64)
+    pot_l = api.Potential(large, sy.n_atoms, sy.box, 128)
+    x0 = api.to_soa(sy.pos)
+    Es_gpu, Fs_gpu = pot_s(x0, sp)
+    El_gpu, Fl_gpu = pot_l(x0, sp)
+    offs, nbr, _ = pot_l.nlist.download(sy.n_atoms)
+    pairs_large = int(np.sum(nbr >= 0))
+    offs_s, nbr_s, _ = pot_s.nlist.download(sy.n_atoms)
+    pairs_small = int(np.sum(nbr_s >= 0))
+
+    # ---------------------------------------------------------------- DMTS timed region
+    st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_out, n_inner, 64, 128)
+    x, v = api.to_soa(sy.pos), api.to_soa(v0)
+    st.step(x, v, small, large, max(args.warmup, 1))
+    torch.cuda.synchronize()
+    # kernel census (all classes timed) to find the dominant pair kernel
+    api.prof_reset()
+    api.prof_enable(None)
+    st.step(x, v, small, large, 2)
+    census = api.prof_read()
+    api.prof_enable(())
+    api.prof_reset()
+    timed = {k: census[k] for k in PAIR_FLOPS if census[k][1] > 0}
+    dom = max(timed, key=lambda k: timed[k][0]) if timed else None
+    torch.cuda.synchronize()
+    H_start = st.energies[3].item()
+    api.prof_enable([dom] if dom else ())
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    st.step(x, v, small, large, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    api.prof_enable(())
+    prof = api.prof_read()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_step = max(gpu_ms, wall * 1e3) / args.steps
+    H_end = st.energies[3].item()
+    sim_fs = dt_out
+    ns_day = 0.0864 * sim_fs / (ms_step * 1e-3)
+    atom_steps = sy.n_atoms * (sim_fs / dt_in) / (ms_step * 1e-3)
+
+    # ---------------------------------------------------------------- Verlet, same GPU
+    vv = None
+    if not args.no_verlet:
+        st_v = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_in, 1, 64, 128)
+        xv, vvel = api.to_soa(sy.pos), api.to_soa(v0)
+        st_v.step(xv, vvel, None, large, max(args.warmup, 1))
+        torch.cuda.synchronize()
+        n_vv = args.steps * n_inner
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        st_v.step(xv, vvel, None, large, n_vv)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall_v = time.perf_counter() - t0
+        ms_vv = max(ev0.elapsed_time(ev1), wall_v * 1e3) / n_vv
+        vv = dict(ns_per_day=0.0864 * dt_in / (ms_vv * 1e-3), ms_per_step=ms_vv)
+
+    # ---------------------------------------------------------------- dominant kernel roofline
+    roofline = None
+    if dom and prof[dom][1] > 0:
+        tot_ms, launches = prof[dom]
+        avg_s = tot_ms / launches * 1e-3
+        pairs = pairs_small if dom.startswith("small") else pairs_large
+        flops = PAIR_FLOPS[dom] * pairs
+        achieved = flops / avg_s / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                    "avg_launch_us": round(avg_s * 1e6, 2), "pairs_per_launch": pairs,
+                    "flops_per_pair": PAIR_FLOPS[dom]}
+
+    # ---------------------------------------------------------------- CPU oracle
+    cpu = None
+    errors = None
+    if not args.no_cpu_baseline:
+        c = cpu_oracle(sy, ws, wl, n_inner, dt_in)
+        cpu = {"value": round(c["ns_per_day"], 6), "unit": "ns/day", "cores": c["cores"],
+               "kind": "oracle",
+               "sample": (f"one fast-model ({c['t_small']:.2f} s) and one reference-model "
+                          f"({c['t_large']:.2f} s) FP64 energy+force evaluation of the "
+                          f"{sy.n_atoms}-atom box, extrapolated to one {dt_out:g} fs outer "
+                          f"step ({n_inner} fast + 1 reference evaluation)")}
+        Fs_np, Fl_np = api.from_soa(Fs_gpu), api.from_soa(Fl_gpu)
+        errors = {
+            "force_rel_rmse_small": float(np.linalg.norm(Fs_np - c["Fs"]) / np.linalg.norm(c["Fs"])),
+            "force_rel_rmse_large": float(np.linalg.norm(Fl_np - c["Fl"]) / np.linalg.norm(c["Fl"])),
+            "energy_err_per_atom_small": abs(Es_gpu.item() - c["Es"][0]) / sy.n_atoms,
+            "energy_err_per_atom_large": abs(El_gpu.item() - c["El"][0]) / sy.n_atoms,
+        }
+
+    kernels = {k: {"ms_per_outer_step": round(t / 2, 4), "launches": n, "us_avg": round(1e3 * t / n, 2)}
+               for k, (t, n) in census.items() if n > 0}
+    out = {
+        "metric": METRIC,
+        "value": round(ns_day, 4),
+        "unit": "ns/day",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": sy.n_atoms, "box_A": sy.box,
+                   "dt_inner_fs": dt_in, "dt_outer_fs": dt_out,
+                   "fast_model": "1 interaction, rc 3.5 A, K 16, F 64",
+                   "reference_model": "2 interactions, rc 5.2 A, K 32, F 128, l<=2",
+                   "integration": "f64", "ensemble": "NVE"},
+        "atom_steps_per_s": round(atom_steps, 1),
+        "verlet_ns_per_day": round(vv["ns_per_day"], 4) if vv else None,
+        "verlet_ms_per_step": round(vv["ms_per_step"], 5) if vv else None,
+        "speedup_vs_verlet": round(ns_day / vv["ns_per_day"], 3) if vv else None,
+        "errors_vs_fp64": errors,
+        "energy_drift_per_atom": (H_end - H_start) / sy.n_atoms,
+        "pairs": {"fast": pairs_small, "reference": pairs_large},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * dmts.h -- C ABI of the MI355X (gfx950) library for the hot path of distilled
+ * multi-time-step (DMTS) molecular dynamics with neural network potentials.
+ *
+ * The method (the paper's Methods section and Algorithm 1): a cheap one-interaction
+ * potential with a 3.5 A cutoff is integrated at a short inner step; every n_slow inner
+ * steps the outer level applies the slow correction F_large - F_small of an expensive
+ * two-interaction potential as a half-kick on both sides of the inner loop.
+ *
+ * Conventions for every entry point
+ *   - Units: Angstrom, femtosecond, atomic mass unit, electron-volt; forces eV/A,
+ *     velocities A/fs.
+ *   - Array arguments are DEVICE pointers owned by the caller, unless the name says
+ *     "host_".  Coordinate-like arrays are structure-of-arrays [3][n_atoms] (all x, then
+ *     all y, then all z), contiguous.
+ *   - species: int32 codes 0..n_species-1 (H=0, C=1, N=2, O=3, S=4 for the 5-species
+ *     models).  box: edge of a periodic cube, or 0.0 for open boundaries.
+ *   - sys_offsets (optional, device, int32 [n_sys+1]): CSR ranges of independent
+ *     molecules of a batch.  With open boundaries pairs never cross molecules; with a
+ *     periodic box sys_offsets must be NULL.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Every call only
+ *     enqueues work on that stream; none synchronizes the host unless documented.
+ *   - Handles are opaque, not thread-safe, and must be used from one stream at a time.
+ *     The library owns their internal device memory; it never frees, reallocates or
+ *     retains caller arrays beyond the enqueued work.
+ *   - Errors: every call returns a dmts_status.  Argument and shape errors are detected
+ *     on the host before anything is enqueued and leave all state unchanged; the
+ *     message is available from dmts_last_error() (thread-local).  Conditions found on
+ *     the device (neighbor capacity overflow, non-finite values) set bits in a device
+ *     flag word of the handle, read back by nnp_nlist_flags() and dmts_state_flags(),
+ *     and reported by dmts_step() when it returns.  No C++ exception crosses the ABI.
+ */
+#ifndef DMTS_H
+#define DMTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmts_status;
+enum {
+  DMTS_OK = 0,
+  DMTS_E_ARG = 1,        /* bad argument, unsupported shape, NULL pointer          */
+  DMTS_E_BOX = 2,        /* cutoff >= box/2 for a periodic box                      */
+  DMTS_E_CAPACITY = 3,   /* a neighbor list overflowed its capacity                 */
+  DMTS_E_NONFINITE = 4,  /* NaN/Inf met in positions, energies or forces            */
+  DMTS_E_HIP = 5,        /* a HIP runtime call failed                               */
+  DMTS_E_OOM = 6,        /* device allocation failed                                */
+  DMTS_E_STATE = 7       /* handle used inconsistently (sizes changed, ...)         */
+};
+
+/* Device flag bits. */
+#define DMTS_FLAG_NBR_OVERFLOW 0x1u
+#define DMTS_FLAG_NONFINITE 0x2u
+
+/* Model kinds (see nnp_model_create). */
+#define NNP_KIND_ONE_INTERACTION 0
+#define NNP_KIND_TWO_INTERACTION 1
+/* Arithmetic of the dense (MLP) contractions. */
+#define NNP_PREC_FP32 0
+#define NNP_PREC_BF16 1
+
+typedef struct nnp_model nnp_model;
+typedef struct nnp_nlist nnp_nlist;
+typedef struct dmts_state dmts_state;
+
+typedef struct {
+  int32_t kind;          /* NNP_KIND_*                                               */
+  int32_t n_rbf;         /* Gaussian radial functions K (16 or 32)                   */
+  int32_t width;         /* hidden width F (64 for kind 0, 128 for kind 1)           */
+  int32_t emb_dim;       /* species embedding width (16)                             */
+  int32_t n_species;     /* rows of the embedding table (<= 8)                       */
+  int32_t precision;     /* NNP_PREC_*                                               */
+  double cutoff;         /* r_c in A                                                 */
+  double energy_scale;   /* s_E in eV (0.01 for the synthetic models)                */
+} nnp_model_desc;
+
+/* ---------------------------------------------------------------- errors, version */
+const char* dmts_last_error(void);
+const char* dmts_version(void);
+
+/* ---------------------------------------------------------------- models
+ * The two potentials that stand in for the paper's fast distilled model (one
+ * message-passing interaction, short cutoff) and its reference model (two
+ * interactions) (Methods: neural network architectures).
+ *
+ * kind 0 (fast level):   a_ij = W_pair [b(r_ij); e_zi; e_zj],  m_ij = f_c(r_ij) SiLU(a_ij),
+ *                        h_i = sum_j m_ij,  E_i = s_E w_atom2 . SiLU(W_atom1 h_i).
+ * kind 1 (reference):    two interactions with messages m^t_ij = f_c SiLU(W_pair_t
+ *                        [b; s^t_i; s^t_j]) (s^1 = e_z, s^2 = h^1), l <= 2 Cartesian moments
+ *                        of u_ij = d_ij/r_c, invariants q = [M0; |M1|^2; |M2|^2] per
+ *                        channel, h^1 = SiLU(U1 q^1), h^2 = h^1 + SiLU(U2 q^2),
+ *                        E_i = s_E w_out2 . SiLU(W_out1 h^2).
+ * with Gaussian radial functions b_k(r) = exp(-(r - k r_c/(K-1))^2 / (2 (r_c/(K-1))^2)),
+ * cosine cutoff f_c(r) = (cos(pi r / r_c) + 1)/2 for r < r_c, and no biases.
+ *
+ * host_weights: float32 blob of n_weights entries, row-major tensors in this order
+ *   kind 0: emb [Z][D], W_pair [F][K+2D], W_atom1 [F][F], w_atom2 [F]
+ *   kind 1: emb [Z][D], W_pair1 [F][K+2D], U1 [F][3F], W_pair2 [F][K+2F], U2 [F][3F],
+ *           W_out1 [F][F], w_out2 [F]
+ * The blob is copied; the caller keeps ownership.  Supported shapes: kind 0 with
+ * (K, F) = (16, 64); kind 1 with (K, F) = (32, 128); D = 16; n_species <= 8.
+ * Blocking: synchronizes the device once (weight upload).  Returns DMTS_E_ARG for an
+ * unsupported shape or a wrong n_weights.
+ */
+dmts_status nnp_model_create(const nnp_model_desc* desc, const float* host_weights,
+                             int64_t n_weights, nnp_model** out);
+void nnp_model_destroy(nnp_model* model);
+
+/* ---------------------------------------------------------------- neighbor lists
+ * A full (both directions) list of ordered pairs {(i, j): j != i, |d_ij| < cutoff},
+ * d_ij = x_j - x_i under the minimum-image convention of the cube (or plain difference
+ * for open boundaries, restricted to one molecule when sys_offsets is given).  The
+ * paper does not describe its neighbor search; this is the pair set its message
+ * passing sums over.
+ *
+ * Storage is CSR with each row padded to a multiple of row_align (1, 16 or 32) with
+ * entries -1; rev[p] is the position of the reverse pair (j, i) for every real entry.
+ * Rows are filled in a fixed order, so the list is bitwise reproducible.
+ *
+ * nnp_nlist_create: capacity for max_atoms atoms and max_pairs padded entries.
+ *   Blocking (allocates).
+ * nnp_build_neighbors: rebuilds the list for pos ([3][n_atoms] float64).  A periodic box
+ *   needs cutoff < box/2 (else DMTS_E_BOX).  A list that would exceed max_pairs sets
+ *   DMTS_FLAG_NBR_OVERFLOW on the device and is then incomplete.  Asynchronous.
+ * nnp_nlist_flags: synchronizes the stream, returns the flag word in *host_flags and
+ *   clears it.
+ * nnp_nlist_download: synchronizes, copies offs [n_atoms+1], nbr and rev [offs[n]] to
+ *   host arrays of capacity host_cap entries (DMTS_E_CAPACITY if too small); a test
+ *   and debugging aid.  *n_entries receives offs[n_atoms].
+ */
+dmts_status nnp_nlist_create(int32_t max_atoms, int64_t max_pairs, int32_t row_align,
+                             nnp_nlist** out);
+void nnp_nlist_destroy(nnp_nlist* nl);
+dmts_status nnp_build_neighbors(nnp_nlist* nl, const double* pos, int32_t n_atoms,
+                                double box, const int32_t* sys_offsets, int32_t n_sys,
+                                double cutoff, void* stream);
+dmts_status nnp_nlist_flags(nnp_nlist* nl, void* stream, uint32_t* host_flags);
+dmts_status nnp_nlist_download(nnp_nlist* nl, void* stream, int32_t* host_offs,
+                               int32_t* host_nbr, int32_t* host_rev, int64_t host_cap,
+                               int64_t* n_entries);
+
+/* ---------------------------------------------------------------- energy and forces
+ * Energy per system (float64, device [n_sys]) and forces F = -dE/dx (float32, device
+ * [3][n_atoms], or NULL for energy only) of one model on the pairs of nl, which must
+ * have been built from the same pos with cutoff >= the model's cutoff.  Pairs beyond
+ * the model's cutoff contribute zero.  Per-atom energies (float32, device [n_atoms]) are
+ * written to atom_energy when it is not NULL.  n_sys = 1 and sys_offsets = NULL for one
+ * system.  Asynchronous; the model's workspace grows (blocking) when a larger system or
+ * list than before is seen.
+ */
+dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos,
+                              const int32_t* species, int32_t n_atoms, double box,
+                              const int32_t* sys_offsets, int32_t n_sys, double* energy,
+                              float* forces, float* atom_energy, void* stream);
+
+/* ---------------------------------------------------------------- the RESPA loop
+ * Algorithm 1 (BAOAB-RESPA with force splitting), with the thermostat of its middle
+ * step off (gamma = 0: NVE).  One outer step of length dt_outer:
+ *   v += dt/2 (F - F_small)/m;
+ *   n_inner times: v += h/2 F_small/m; x += h/2 v; x += h/2 v; F_small <- small(x);
+ *                  v += h/2 F_small/m          (h = dt_outer / n_inner);
+ *   F <- large(x); v += dt/2 (F - F_small)/m.
+ * Both forces are evaluated on the first step only and carried between calls
+ * afterwards.  With small == NULL the call runs the single-time-step baseline instead:
+ * velocity Verlet with the large model at dt_outer (n_inner is ignored).
+ *
+ * dmts_state_create: n_atoms atoms in a periodic cube `box` (open boundaries: 0.0),
+ *   species (device [n_atoms], borrowed for the life of the state), masses per species
+ *   (host, copied).  max_nbrs_* bound the average number of neighbors per atom within
+ *   each model's cutoff (the lists are sized n_atoms * max_nbrs).  Blocking.
+ * dmts_step: advances x and v (device float64 [3][n_atoms], updated in place) by
+ *   n_outer outer steps.  energies_out (device float64 [4], optional) receives
+ *   {E_large, E_small, kinetic, E_large + kinetic} at the final positions.  Checks the
+ *   device flags once at the end (one host synchronization) and returns
+ *   DMTS_E_CAPACITY or DMTS_E_NONFINITE if set.
+ * dmts_state_reset: forget the carried forces (call after changing x outside
+ *   dmts_step).
+ * dmts_state_forces: device pointers to the carried F_large and F_small (float32
+ *   [3][n_atoms]) for inspection.
+ */
+dmts_status dmts_state_create(int32_t n_atoms, double box, const int32_t* species,
+                              const double* host_mass_by_species, int32_t n_species,
+                              double dt_outer_fs, int32_t n_inner, int32_t max_nbrs_small,
+                              int32_t max_nbrs_large, dmts_state** out);
+void dmts_state_destroy(dmts_state* st);
+dmts_status dmts_step(dmts_state* st, double* x, double* v, nnp_model* small,
+                      nnp_model* large, int32_t n_outer, double* energies_out,
+                      void* stream);
+dmts_status dmts_state_reset(dmts_state* st);
+dmts_status dmts_state_forces(dmts_state* st, const float** f_large, const float** f_small);
+dmts_status dmts_state_flags(dmts_state* st, void* stream, uint32_t* host_flags);
+
+/* ---------------------------------------------------------------- kernel timing
+ * Optional HIP-event timing of individual kernel classes, for measurement harnesses.
+ * dmts_prof_enable takes a bit mask (bit k = class k, 0 = off, the default).  Each launch
+ * of an enabled class is bracketed by two hipEventRecord calls on its stream (a few
+ * microseconds of overhead per launch); disabled classes cost nothing.  dmts_prof_read synchronizes on the recorded events and returns the summed
+ * duration in milliseconds and the number of launches of one class since the last reset.
+ */
+enum {
+  DMTS_K_SMALL_FORWARD = 0,
+  DMTS_K_SMALL_BACKWARD = 1,
+  DMTS_K_PAIR1_FORWARD = 2,
+  DMTS_K_PAIR2_FORWARD = 3,
+  DMTS_K_PAIR2_BACKWARD = 4,
+  DMTS_K_PAIR1_BACKWARD = 5,
+  DMTS_K_NEIGHBORS = 6,      /* a whole neighbor-list build (all its kernels)          */
+  DMTS_K_ATOM_GEMM = 7,      /* each per-atom MFMA GEMM                                */
+  DMTS_K_GATHER = 8,         /* sender and force gathers                               */
+  DMTS_K_INTEGRATE = 9,      /* fused kick/drift launches                              */
+  DMTS_K_COUNT = 10
+};
+dmts_status dmts_prof_enable(uint32_t class_mask);
+dmts_status dmts_prof_reset(void);
+dmts_status dmts_prof_read(int32_t kernel_class, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMTS_H */

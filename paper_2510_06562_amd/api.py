@@ -1,0 +1,348 @@
+"""ctypes binding of ``libdmts.so`` (argument marshalling only; every step of the path runs
+in the library's HIP kernels).
+
+PyTorch supplies device memory and streams: arrays are CUDA(HIP) tensors whose data
+pointers are passed straight to the C ABI together with the current stream.  Positions and
+velocities are float64 in the library's structure-of-arrays layout [3][N]; helpers convert
+from the usual (N, 3) layout.
+
+The library must be built (``python -m paper_2510_06562_amd.build``).  Loading fails
+loudly when it is missing; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmts.so")
+
+OK, E_ARG, E_BOX, E_CAPACITY, E_NONFINITE, E_HIP, E_OOM, E_STATE = range(8)
+FLAG_NBR_OVERFLOW = 0x1
+FLAG_NONFINITE = 0x2
+KIND_ONE = 0
+KIND_TWO = 1
+PREC_FP32 = 0
+PREC_BF16 = 1
+
+_STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_BOX", 3: "E_CAPACITY", 4: "E_NONFINITE",
+                 5: "E_HIP", 6: "E_OOM", 7: "E_STATE"}
+
+
+class DmtsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_rbf", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("emb_dim", ctypes.c_int32), ("n_species", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("cutoff", ctypes.c_double),
+                ("energy_scale", ctypes.c_double)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+_SIGS = {
+    "dmts_last_error": ([], ctypes.c_char_p),
+    "dmts_version": ([], ctypes.c_char_p),
+    "nnp_model_create": ([ctypes.POINTER(_Desc), _P, _I64, ctypes.POINTER(_P)], _I32),
+    "nnp_model_destroy": ([_P], None),
+    "nnp_nlist_create": ([_I32, _I64, _I32, ctypes.POINTER(_P)], _I32),
+    "nnp_nlist_destroy": ([_P], None),
+    "nnp_build_neighbors": ([_P, _P, _I32, _D, _P, _I32, _D, _P], _I32),
+    "nnp_nlist_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
+    "nnp_nlist_download": ([_P, _P, _P, _P, _P, _I64, ctypes.POINTER(_I64)], _I32),
+    "nnp_energy_forces": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _P, _P, _P, _P], _I32),
+    "dmts_state_create": ([_I32, _D, _P, _P, _I32, _D, _I32, _I32, _I32, ctypes.POINTER(_P)], _I32),
+    "dmts_state_destroy": ([_P], None),
+    "dmts_step": ([_P, _P, _P, _P, _P, _I32, _P, _P], _I32),
+    "dmts_state_reset": ([_P], _I32),
+    "dmts_state_forces": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I32),
+    "dmts_state_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
+    "dmts_prof_enable": ([ctypes.c_uint32], _I32),
+    "dmts_prof_reset": ([], _I32),
+    "dmts_prof_read": ([_I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I32),
+}
+
+KERNEL_CLASSES = ("small_forward", "small_backward", "pair1_forward", "pair2_forward",
+                  "pair2_backward", "pair1_backward", "neighbors", "atom_gemm", "gather",
+                  "integrate")
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load the shared library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2510_06562_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise DmtsError(status, lib().dmts_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_check(t: torch.Tensor, dtype, shape=None, name="array"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+
+
+def to_soa(a: np.ndarray | torch.Tensor, device="cuda") -> torch.Tensor:
+    """(N, 3) -> contiguous float64 device tensor [3, N]."""
+    t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+    return t.to(device=device, dtype=torch.float64).t().contiguous()
+
+
+def from_soa(t: torch.Tensor) -> np.ndarray:
+    """[3, N] device tensor -> (N, 3) float64 NumPy array."""
+    return t.detach().to("cpu", torch.float64).t().contiguous().numpy()
+
+
+# ------------------------------------------------------------------ models
+@dataclass(frozen=True)
+class ModelDesc:
+    kind: int
+    cutoff: float
+    n_rbf: int
+    width: int
+    emb_dim: int = 16
+    n_species: int = 5
+    energy_scale: float = 0.01
+    precision: int = PREC_FP32
+
+    def c(self) -> _Desc:
+        return _Desc(self.kind, self.n_rbf, self.width, self.emb_dim, self.n_species,
+                     self.precision, self.cutoff, self.energy_scale)
+
+
+class Model:
+    """A potential on the device: ``Model(desc, weights)`` with a flat float32 blob."""
+
+    def __init__(self, desc: ModelDesc, weights: np.ndarray):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        h = ctypes.c_void_p()
+        _check(lib().nnp_model_create(ctypes.byref(desc.c()), w.ctypes.data_as(ctypes.c_void_p),
+                                      w.size, ctypes.byref(h)))
+        self.desc = desc
+        self._h = h
+
+    @classmethod
+    def from_spec(cls, spec, weights, precision=PREC_FP32, energy_scale=None):
+        """From a ``synth.ModelSpec``."""
+        d = ModelDesc(kind=spec.kind, cutoff=spec.cutoff, n_rbf=spec.n_rbf, width=spec.width,
+                      emb_dim=spec.emb_dim, n_species=spec.n_species,
+                      energy_scale=spec.energy_scale if energy_scale is None else energy_scale,
+                      precision=precision)
+        return cls(d, weights)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.nnp_model_destroy(self._h)
+            self._h = None
+
+
+class NeighborList:
+    def __init__(self, max_atoms: int, max_pairs: int, row_align: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().nnp_nlist_create(max_atoms, max_pairs, row_align, ctypes.byref(h)))
+        self._h = h
+        self.max_atoms = max_atoms
+        self.max_pairs = max_pairs
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, pos_soa: torch.Tensor, box: float, cutoff: float,
+              sys_offsets: Optional[torch.Tensor] = None, stream=None):
+        n = pos_soa.shape[1]
+        _dev_check(pos_soa, torch.float64, (3, n), "pos")
+        n_sys = 1
+        if sys_offsets is not None:
+            _dev_check(sys_offsets, torch.int32, None, "sys_offsets")
+            n_sys = sys_offsets.numel() - 1
+        _check(lib().nnp_build_neighbors(self._h, _ptr(pos_soa), n, float(box), _ptr(sys_offsets),
+                                         n_sys, float(cutoff), _stream(stream)))
+
+    def flags(self, stream=None) -> int:
+        f = ctypes.c_uint32()
+        _check(lib().nnp_nlist_flags(self._h, _stream(stream), ctypes.byref(f)))
+        return f.value
+
+    def download(self, n_atoms: int, stream=None):
+        """(offs, nbr, rev) as NumPy int32 arrays (synchronizes)."""
+        offs = np.zeros(n_atoms + 1, dtype=np.int32)
+        cap = self.max_pairs + 4
+        nbr = np.zeros(cap, dtype=np.int32)
+        rev = np.zeros(cap, dtype=np.int32)
+        P = ctypes.c_int64()
+        _check(lib().nnp_nlist_download(self._h, _stream(stream), offs.ctypes.data_as(_P),
+                                        nbr.ctypes.data_as(_P), rev.ctypes.data_as(_P), cap,
+                                        ctypes.byref(P)))
+        return offs, nbr[:P.value].copy(), rev[:P.value].copy()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.nnp_nlist_destroy(self._h)
+            self._h = None
+
+
+def energy_forces(model: Model, nlist: NeighborList, pos_soa: torch.Tensor,
+                  species: torch.Tensor, box: float, sys_offsets: Optional[torch.Tensor] = None,
+                  want_forces: bool = True, atom_energy: bool = False, stream=None):
+    """Energies per system (float64 [n_sys]), forces (float32 [3, N]) and optionally the
+    per-atom energies, on the pairs of ``nlist`` (built from the same positions)."""
+    n = pos_soa.shape[1]
+    _dev_check(pos_soa, torch.float64, (3, n), "pos")
+    _dev_check(species, torch.int32, (n,), "species")
+    n_sys = 1 if sys_offsets is None else sys_offsets.numel() - 1
+    E = torch.empty(n_sys, dtype=torch.float64, device=pos_soa.device)
+    F = torch.empty((3, n), dtype=torch.float32, device=pos_soa.device) if want_forces else None
+    Ea = torch.empty(n, dtype=torch.float32, device=pos_soa.device) if atom_energy else None
+    _check(lib().nnp_energy_forces(model.handle, nlist.handle, _ptr(pos_soa), _ptr(species), n,
+                                   float(box), _ptr(sys_offsets), n_sys, _ptr(E), _ptr(F),
+                                   _ptr(Ea), _stream(stream)))
+    return (E, F, Ea) if atom_energy else (E, F)
+
+
+class Potential:
+    """A model with its own neighbor list: ``pot(pos_soa) -> (E, F)``."""
+
+    def __init__(self, model: Model, max_atoms: int, box: float, max_nbrs: int = 128,
+                 sys_offsets: Optional[torch.Tensor] = None):
+        self.model = model
+        self.box = box
+        self.sys_offsets = sys_offsets
+        self.nlist = NeighborList(max_atoms, max_atoms * (max_nbrs + 4), 4)
+
+    def __call__(self, pos_soa: torch.Tensor, species: torch.Tensor, want_forces=True,
+                 atom_energy=False, stream=None):
+        self.nlist.build(pos_soa, self.box, self.model.desc.cutoff, self.sys_offsets, stream)
+        return energy_forces(self.model, self.nlist, pos_soa, species, self.box,
+                             self.sys_offsets, want_forces, atom_energy, stream)
+
+
+class NNPEnergy(torch.autograd.Function):
+    """E = NNPEnergy.apply(pos_soa, potential, species): forward returns the energy per
+    system; backward returns -F * grad_E (the library's analytic forces)."""
+
+    @staticmethod
+    def forward(ctx, pos_soa, potential: Potential, species):
+        E, F = potential(pos_soa.detach(), species, want_forces=True)
+        ctx.save_for_backward(F)
+        return E
+
+    @staticmethod
+    def backward(ctx, grad_E):
+        (F,) = ctx.saved_tensors
+        g = grad_E.sum().to(torch.float64) if grad_E.numel() > 1 else grad_E.reshape(()).to(torch.float64)
+        return -(F.to(torch.float64) * g), None, None
+
+
+# ------------------------------------------------------------------ dynamics
+class DMTS:
+    """Algorithm 1 (BAOAB-RESPA, gamma = 0) or, with small=None, velocity Verlet."""
+
+    def __init__(self, n_atoms: int, box: float, species: torch.Tensor, masses_by_species,
+                 dt_outer: float, n_inner: int, max_nbrs_small: int = 48,
+                 max_nbrs_large: int = 128):
+        _dev_check(species, torch.int32, (n_atoms,), "species")
+        m = np.ascontiguousarray(np.asarray(masses_by_species, dtype=np.float64))
+        h = ctypes.c_void_p()
+        _check(lib().dmts_state_create(n_atoms, float(box), _ptr(species),
+                                       m.ctypes.data_as(_P), m.size, float(dt_outer), n_inner,
+                                       max_nbrs_small, max_nbrs_large, ctypes.byref(h)))
+        self._h = h
+        self.species = species   # keep the borrowed array alive
+        self.n = n_atoms
+        self.energies = torch.zeros(4, dtype=torch.float64, device=species.device)
+
+    def step(self, x_soa: torch.Tensor, v_soa: torch.Tensor, small: Optional[Model],
+             large: Model, n_outer: int = 1, stream=None):
+        _dev_check(x_soa, torch.float64, (3, self.n), "x")
+        _dev_check(v_soa, torch.float64, (3, self.n), "v")
+        _check(lib().dmts_step(self._h, _ptr(x_soa), _ptr(v_soa),
+                               small.handle if small is not None else None, large.handle,
+                               n_outer, _ptr(self.energies), _stream(stream)))
+        return self.energies
+
+    def reset(self):
+        _check(lib().dmts_state_reset(self._h))
+
+    def forces(self):
+        fl, fs = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().dmts_state_forces(self._h, ctypes.byref(fl), ctypes.byref(fs)))
+        return fl.value, fs.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dmts_state_destroy(self._h)
+            self._h = None
+
+
+# ------------------------------------------------------------------ kernel timing
+def prof_enable(classes=None):
+    """Time the given kernel classes (names from KERNEL_CLASSES; None = all, () = off)."""
+    if classes is None:
+        mask = (1 << len(KERNEL_CLASSES)) - 1
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << KERNEL_CLASSES.index(c)
+    _check(lib().dmts_prof_enable(mask))
+
+
+def prof_reset():
+    _check(lib().dmts_prof_reset())
+
+
+def prof_read() -> dict:
+    """{class: (total_ms, launches)} for every timed kernel class (synchronizes)."""
+    out = {}
+    for k, name in enumerate(KERNEL_CLASSES):
+        t, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().dmts_prof_read(k, ctypes.byref(t), ctypes.byref(n)))
+        out[name] = (t.value, n.value)
+    return out

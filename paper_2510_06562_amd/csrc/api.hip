@@ -1,0 +1,343 @@
+// Library glue: error reporting, device buffers, model creation (weight re-layout) and the
+// energy/force entry point.
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace dmts {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+dmts_status DevBuf::reserve(size_t need, hipStream_t s) {
+  if (need <= bytes) return DMTS_OK;
+  if (ptr) {
+    if (hipStreamSynchronize(s) != hipSuccess) return DMTS_E_HIP;
+    (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  size_t want = need + need / 4;
+  if (hipMalloc(&ptr, want) != hipSuccess) {
+    ptr = nullptr;
+    set_error("hipMalloc of %zu bytes failed", want);
+    return DMTS_E_OOM;
+  }
+  bytes = want;
+  return DMTS_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------ kernel timing
+namespace {
+uint32_t g_prof_mask = 0;
+struct ProfRec {
+  hipEvent_t a, b;
+};
+std::vector<ProfRec> g_prof[DMTS_K_COUNT];
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t get_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+ProfScope::ProfScope(int kernel_class, hipStream_t stream) : kid(kernel_class), s(stream) {
+  if (!((g_prof_mask >> kid) & 1u)) return;
+  a = get_event();
+  if (a) (void)hipEventRecord(a, s);
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = get_event();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  g_prof[kid].push_back({a, b});
+}
+
+namespace {
+
+constexpr int kReduceThreads = 256;
+
+// energy[s] = sum of atom_e over system s, float64, fixed reduction tree.
+__global__ void __launch_bounds__(kReduceThreads)
+k_reduce_energy(const float* __restrict__ atom_e, int n, const int32_t* __restrict__ offs,
+                double* __restrict__ energy) {
+  __shared__ double part[kReduceThreads];
+  const int sys = blockIdx.x;
+  const int lo = offs ? max(0, offs[sys]) : 0;
+  const int hi = offs ? min(n, offs[sys + 1]) : n;
+  double acc = 0.0;
+  for (int k = lo + threadIdx.x; k < hi; k += kReduceThreads) acc += (double)atom_e[k];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) energy[sys] = part[0];
+}
+
+}  // namespace
+
+dmts_status reduce_energy(const float* atom_e, int32_t n, const int32_t* sys_offsets,
+                          int32_t n_sys, double* energy, hipStream_t s) {
+  const int ns = sys_offsets ? n_sys : 1;
+  if (ns <= 0) return DMTS_OK;
+  k_reduce_energy<<<ns, kReduceThreads, 0, s>>>(atom_e, n, sys_offsets, energy);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+}  // namespace dmts
+
+using dmts::Model;
+using dmts::NList;
+
+namespace {
+
+// Weight tensors of the flat blob, row-major, in the documented order.
+struct Blob {
+  const float* p;
+  size_t o = 0;
+  const float* take(size_t n) {
+    const float* r = p + o;
+    o += n;
+    return r;
+  }
+};
+
+void append(std::vector<float>& dst, size_t& off, const std::vector<float>& src) {
+  off = dst.size();
+  dst.insert(dst.end(), src.begin(), src.end());
+  while (dst.size() % 64) dst.push_back(0.f);   // keep every tensor 256-byte aligned
+}
+
+// (rows x cols) row-major -> (cols x rows) row-major, for the column range [c0, c0+nc).
+std::vector<float> transpose_block(const float* W, int rows, int cols, int c0, int nc) {
+  std::vector<float> t((size_t)nc * rows);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < nc; ++c) t[(size_t)c * rows + r] = W[(size_t)r * cols + c0 + c];
+  return t;
+}
+
+// Species tables: T[z][c] = sum_e W[c][c0 + e] emb[z][e]  (float64 accumulation)
+std::vector<float> species_table(const float* W, int F, int cols, int c0, const float* emb,
+                                 int Z, int D) {
+  std::vector<float> t((size_t)Z * F);
+  for (int z = 0; z < Z; ++z)
+    for (int c = 0; c < F; ++c) {
+      double acc = 0.0;
+      for (int e = 0; e < D; ++e) acc += (double)W[(size_t)c * cols + c0 + e] * emb[z * D + e];
+      t[(size_t)z * F + c] = (float)acc;
+    }
+  return t;
+}
+
+}  // namespace
+
+
+extern "C" const char* dmts_last_error(void) { return dmts::g_err; }
+
+extern "C" const char* dmts_version(void) { return "dmts-mi355x 0.1 (gfx950)"; }
+
+extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float* host_weights,
+                                        int64_t n_weights, nnp_model** out) {
+  DMTS_REQUIRE(desc && host_weights && out, DMTS_E_ARG, "nnp_model_create: null argument");
+  *out = nullptr;
+  const nnp_model_desc d = *desc;
+  const int K = d.n_rbf, F = d.width, D = d.emb_dim, Z = d.n_species;
+  DMTS_REQUIRE(d.kind == NNP_KIND_ONE_INTERACTION || d.kind == NNP_KIND_TWO_INTERACTION,
+               DMTS_E_ARG, "nnp_model_create: unknown kind %d", d.kind);
+  DMTS_REQUIRE(d.precision == NNP_PREC_FP32 || d.precision == NNP_PREC_BF16, DMTS_E_ARG,
+               "nnp_model_create: unknown precision %d", d.precision);
+  DMTS_REQUIRE(D == 16 && Z >= 1 && Z <= 8, DMTS_E_ARG,
+               "nnp_model_create: need emb_dim 16 and 1..8 species (got %d, %d)", D, Z);
+  if (d.kind == NNP_KIND_ONE_INTERACTION)
+    DMTS_REQUIRE(K == 16 && F == 64, DMTS_E_ARG,
+                 "nnp_model_create: one-interaction model supports K=16, F=64 (got %d, %d)", K, F);
+  else
+    DMTS_REQUIRE(K == 32 && F == 128, DMTS_E_ARG,
+                 "nnp_model_create: two-interaction model supports K=32, F=128 (got %d, %d)", K, F);
+  DMTS_REQUIRE(d.cutoff > 0.0 && d.cutoff < 1e3, DMTS_E_ARG, "nnp_model_create: bad cutoff");
+  size_t expect;
+  if (d.kind == NNP_KIND_ONE_INTERACTION)
+    expect = (size_t)Z * D + (size_t)F * (K + 2 * D) + (size_t)F * F + F;
+  else
+    expect = (size_t)Z * D + (size_t)F * (K + 2 * D) + 2 * (size_t)F * 3 * F +
+             (size_t)F * (K + 2 * F) + (size_t)F * F + F;
+  DMTS_REQUIRE((size_t)n_weights == expect, DMTS_E_ARG,
+               "nnp_model_create: %lld weights given, %zu expected", (long long)n_weights, expect);
+
+  Model* m = new Model();
+  m->desc = d;
+  m->K = K;
+  m->F = F;
+  m->D = D;
+  m->Z = Z;
+  m->rc = (float)d.cutoff;
+  m->sigma = (float)(d.cutoff / (K - 1));
+  m->escale = (float)d.energy_scale;
+  Blob b{host_weights};
+  std::vector<float> P;
+  const float* emb = b.take((size_t)Z * D);
+  if (d.kind == NNP_KIND_ONE_INTERACTION) {
+    const int cols = K + 2 * D;
+    const float* Wp = b.take((size_t)F * cols);
+    const float* W1 = b.take((size_t)F * F);
+    const float* w2 = b.take(F);
+    append(P, m->o_WbT, transpose_block(Wp, F, cols, 0, K));
+    append(P, m->o_Td, species_table(Wp, F, cols, K, emb, Z, D));
+    append(P, m->o_Ts, species_table(Wp, F, cols, K + D, emb, Z, D));
+    append(P, m->o_W1, std::vector<float>(W1, W1 + (size_t)F * F));
+    append(P, m->o_W1T, transpose_block(W1, F, F, 0, F));
+    append(P, m->o_w2, std::vector<float>(w2, w2 + F));
+  } else {
+    const int cols1 = K + 2 * D, cols2 = K + 2 * F, Q = 3 * F;
+    const float* Wp1 = b.take((size_t)F * cols1);
+    const float* U1 = b.take((size_t)F * Q);
+    const float* Wp2 = b.take((size_t)F * cols2);
+    const float* U2 = b.take((size_t)F * Q);
+    const float* Wo = b.take((size_t)F * F);
+    const float* wo = b.take(F);
+    append(P, m->o_WbT, transpose_block(Wp1, F, cols1, 0, K));
+    append(P, m->o_Td, species_table(Wp1, F, cols1, K, emb, Z, D));
+    append(P, m->o_Ts, species_table(Wp1, F, cols1, K + D, emb, Z, D));
+    append(P, m->o_W2bT, transpose_block(Wp2, F, cols2, 0, K));
+    append(P, m->o_U1T, transpose_block(U1, F, Q, 0, Q));
+    append(P, m->o_U1, std::vector<float>(U1, U1 + (size_t)F * Q));
+    append(P, m->o_U2T, transpose_block(U2, F, Q, 0, Q));
+    append(P, m->o_U2, std::vector<float>(U2, U2 + (size_t)F * Q));
+    // [A | B] projection: B[k][n] = W_pair2[n][K+F+k] (sender) for n < F,
+    //                              W_pair2[n-F][K+k]  (receiver) otherwise.
+    std::vector<float> W2hT((size_t)F * 2 * F), W2hs((size_t)2 * F * F);
+    for (int k = 0; k < F; ++k)
+      for (int n = 0; n < 2 * F; ++n)
+        W2hT[(size_t)k * 2 * F + n] = n < F ? Wp2[(size_t)n * cols2 + K + F + k]
+                                            : Wp2[(size_t)(n - F) * cols2 + K + k];
+    // reverse pass: dh[e] = sum_c R[c] W_pair2[c][K+e] + sum_c S[c] W_pair2[c][K+F+e]
+    for (int k = 0; k < 2 * F; ++k)
+      for (int e = 0; e < F; ++e)
+        W2hs[(size_t)k * F + e] = k < F ? Wp2[(size_t)k * cols2 + K + e]
+                                        : Wp2[(size_t)(k - F) * cols2 + K + F + e];
+    append(P, m->o_W2hT, W2hT);
+    append(P, m->o_W2hs, W2hs);
+    append(P, m->o_WoT, transpose_block(Wo, F, F, 0, F));
+    append(P, m->o_Wo, std::vector<float>(Wo, Wo + (size_t)F * F));
+    append(P, m->o_wo, std::vector<float>(wo, wo + F));
+  }
+  if (m->params.reserve(P.size() * sizeof(float), nullptr) != DMTS_OK) {
+    delete m;
+    return DMTS_E_OOM;
+  }
+  hipError_t e = hipMemcpy(m->params.ptr, P.data(), P.size() * sizeof(float),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    dmts::set_error("nnp_model_create: %s", hipGetErrorString(e));
+    m->params.release();
+    delete m;
+    return DMTS_E_HIP;
+  }
+  *out = reinterpret_cast<nnp_model*>(m);
+  return DMTS_OK;
+}
+
+extern "C" void nnp_model_destroy(nnp_model* h) {
+  Model* m = reinterpret_cast<Model*>(h);
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  m->params.release();
+  m->atom_ws.release();
+  m->pair_ws.release();
+  m->sys_ws.release();
+  delete m;
+}
+
+namespace dmts {
+dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
+                          int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
+                          double* energy, float* forces, float* atom_energy, hipStream_t s) {
+  DMTS_REQUIRE(m && nl && pos && species, DMTS_E_ARG, "nnp_energy_forces: null argument");
+  DMTS_REQUIRE(n == nl->n_atoms, DMTS_E_STATE,
+               "nnp_energy_forces: list built for %d atoms, called with %d", nl->n_atoms, n);
+  DMTS_REQUIRE(box == nl->box, DMTS_E_STATE, "nnp_energy_forces: list built for another box");
+  DMTS_REQUIRE(nl->cutoff >= (double)m->desc.cutoff, DMTS_E_STATE,
+               "nnp_energy_forces: list cutoff %g below the model cutoff %g", nl->cutoff,
+               m->desc.cutoff);
+  DMTS_REQUIRE(sys_offsets == nullptr || n_sys >= 1, DMTS_E_ARG,
+               "nnp_energy_forces: n_sys must be >= 1 with sys_offsets");
+  DMTS_REQUIRE(m->desc.precision == NNP_PREC_FP32, DMTS_E_ARG,
+               "nnp_energy_forces: this build evaluates FP32 models only");
+  if (m->desc.kind == NNP_KIND_ONE_INTERACTION)
+    return small_energy_forces(m, nl, pos, species, n, box, sys_offsets, n_sys, energy, forces,
+                               atom_energy, s);
+  return large_energy_forces(m, nl, pos, species, n, box, sys_offsets, n_sys, energy, forces,
+                             atom_energy, s);
+}
+}  // namespace dmts
+
+extern "C" dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos,
+                                         const int32_t* species, int32_t n_atoms, double box,
+                                         const int32_t* sys_offsets, int32_t n_sys,
+                                         double* energy, float* forces, float* atom_energy,
+                                         void* stream) {
+  return dmts::energy_forces(reinterpret_cast<Model*>(model), reinterpret_cast<NList*>(nl), pos,
+                             species, n_atoms, box, sys_offsets, n_sys, energy, forces,
+                             atom_energy, static_cast<hipStream_t>(stream));
+}
+
+extern "C" dmts_status dmts_prof_enable(uint32_t class_mask) {
+  dmts::g_prof_mask = class_mask;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_prof_reset(void) {
+  for (auto& v : dmts::g_prof) {
+    for (auto& r : v) {
+      (void)hipEventSynchronize(r.b);
+      dmts::g_event_pool.push_back(r.a);
+      dmts::g_event_pool.push_back(r.b);
+    }
+    v.clear();
+  }
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_prof_read(int32_t kernel_class, double* total_ms, int64_t* launches) {
+  DMTS_REQUIRE(kernel_class >= 0 && kernel_class < DMTS_K_COUNT && total_ms && launches,
+               DMTS_E_ARG, "dmts_prof_read: bad argument");
+  double t = 0.0;
+  for (auto& r : dmts::g_prof[kernel_class]) {
+    DMTS_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    DMTS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int64_t)dmts::g_prof[kernel_class].size();
+  return DMTS_OK;
+}

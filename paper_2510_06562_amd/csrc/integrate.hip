@@ -1,0 +1,360 @@
+// The RESPA loop of Algorithm 1 (BAOAB-RESPA with force splitting) and the
+// single-time-step baseline, in float64 on the device.
+//
+// Kicks and drifts are per-atom streaming work (x, v float64 [3][N], forces float32).
+// Consecutive kicks/drifts between two force evaluations are fused into one launch that
+// applies them in the algorithm's order with exactly the arithmetic of separate steps,
+// so fusion never changes a bit of the trajectory:
+//   kick:  v <- v + (tau * KAPPA / m) * F      (F = F_small, F_large or F_large - F_small)
+//   drift: x <- x + tau * v
+// KAPPA converts eV/(A amu) into A/fs^2.
+#include "common.h"
+
+namespace dmts {
+
+namespace {
+
+// 1 eV / (A amu) in A / fs^2 from the CODATA 2018 elementary charge and atomic mass
+// constant.
+constexpr double kKappa = 1.602176634e-19 / (1.0e-10 * 1.66053906660e-27) * 1.0e-20;
+
+enum Op : int { kKickSlow = 0, kKickFast = 1, kKickLarge = 2, kDrift = 3 };
+constexpr int kMaxOps = 8;
+
+struct Prog {
+  int nops;
+  int op[kMaxOps];
+  double c[kMaxOps];   // kicks: tau * KAPPA; drifts: tau
+};
+
+__global__ void __launch_bounds__(256)
+k_apply(Prog prog, int n, double* __restrict__ x, double* __restrict__ v,
+        const float* __restrict__ FL, const float* __restrict__ Fs,
+        const int32_t* __restrict__ species, const double* __restrict__ inv_mass,
+        uint32_t* __restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double im = inv_mass[species[i]];
+  double vv[3], xx[3];
+  bool moved = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) vv[d] = v[(size_t)d * n + i];
+  for (int k = 0; k < prog.nops; ++k) {
+    const int op = prog.op[k];
+    const double c = prog.c[k];
+    if (op == kDrift) {
+      if (!moved) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xx[d] = x[(size_t)d * n + i];
+        moved = true;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xx[d] = xx[d] + c * vv[d];
+    } else {
+      const double ci = c * im;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double f;
+        if (op == kKickSlow) f = (double)FL[(size_t)d * n + i] - (double)Fs[(size_t)d * n + i];
+        else if (op == kKickFast) f = (double)Fs[(size_t)d * n + i];
+        else f = (double)FL[(size_t)d * n + i];
+        vv[d] = vv[d] + ci * f;
+      }
+    }
+  }
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    v[(size_t)d * n + i] = vv[d];
+    bad |= !isfinite(vv[d]);
+  }
+  if (moved) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[(size_t)d * n + i] = xx[d];
+      bad |= !isfinite(xx[d]);
+    }
+  }
+  if (bad) atomicOr(flags, DMTS_FLAG_NONFINITE);
+}
+
+// Kinetic energy sum(m v^2)/2 / KAPPA in eV (single work-group, fixed tree), then
+// out = {E_large, E_small, KE, E_large + KE}.
+__global__ void __launch_bounds__(256)
+k_energies(int n, const double* __restrict__ v, const int32_t* __restrict__ species,
+           const double* __restrict__ mass, const double* __restrict__ e_models,
+           double* __restrict__ out, uint32_t* __restrict__ flags) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double m = mass[species[i]];
+    const double a = v[i], b = v[(size_t)n + i], c = v[2 * (size_t)n + i];
+    acc += m * (a * a + b * b + c * c);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ke = 0.5 * part[0] / kKappa;
+    const double el = e_models[0], es = e_models[1];
+    if (out) {
+      out[0] = el;
+      out[1] = es;
+      out[2] = ke;
+      out[3] = el + ke;
+    }
+    if (!isfinite(el) || !isfinite(es) || !isfinite(ke)) atomicOr(flags, DMTS_FLAG_NONFINITE);
+  }
+}
+
+__global__ void k_merge_flags(uint32_t* dst, const uint32_t* a, const uint32_t* b) {
+  if (threadIdx.x == 0) {
+    uint32_t f = *a | *b;
+    if (f) atomicOr(dst, f);
+  }
+}
+
+}  // namespace
+
+struct State {
+  int32_t n = 0;
+  double box = 0.0;
+  const int32_t* species = nullptr;
+  double dt = 0.0;
+  int32_t n_inner = 1;
+  bool first = true;
+  NList* nl_small = nullptr;
+  NList* nl_large = nullptr;
+  float* FL = nullptr;      // [3][n]
+  float* Fs = nullptr;      // [3][n]
+  double* mass = nullptr;   // [Z]
+  double* inv_mass = nullptr;
+  double* e_models = nullptr;   // {E_large, E_small}
+  uint32_t* flags = nullptr;
+  // models the carried forces belong to
+  Model* last_small = nullptr;
+  Model* last_large = nullptr;
+};
+
+namespace {
+
+struct Runner {
+  State* st;
+  double* x;
+  double* v;
+  hipStream_t s;
+  Prog pending{};
+
+  dmts_status flush() {
+    if (pending.nops == 0) return DMTS_OK;
+    ProfScope ps(DMTS_K_INTEGRATE, s);
+    k_apply<<<ceil_div(st->n, 256), 256, 0, s>>>(pending, st->n, x, v, st->FL, st->Fs,
+                                                 st->species, st->inv_mass, st->flags);
+    DMTS_CHECK_LAUNCH();
+    pending.nops = 0;
+    return DMTS_OK;
+  }
+  dmts_status push(int op, double c) {
+    if (pending.nops == kMaxOps) {
+      dmts_status r = flush();
+      if (r != DMTS_OK) return r;
+    }
+    pending.op[pending.nops] = op;
+    pending.c[pending.nops] = c;
+    ++pending.nops;
+    return DMTS_OK;
+  }
+  dmts_status eval(Model* m, NList* nl, float* F, double* e) {
+    dmts_status r = flush();
+    if (r != DMTS_OK) return r;
+    r = build_neighbors(nl, x, st->n, st->box, nullptr, 1, (double)m->desc.cutoff, s);
+    if (r != DMTS_OK) return r;
+    return energy_forces(m, nl, x, st->species, st->n, st->box, nullptr, 1, e, F, nullptr, s);
+  }
+};
+
+}  // namespace
+
+}  // namespace dmts
+
+using dmts::Model;
+using dmts::NList;
+using dmts::State;
+
+extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int32_t* species,
+                                         const double* host_mass_by_species, int32_t n_species,
+                                         double dt_outer_fs, int32_t n_inner,
+                                         int32_t max_nbrs_small, int32_t max_nbrs_large,
+                                         dmts_state** out) {
+  DMTS_REQUIRE(out && species && host_mass_by_species, DMTS_E_ARG,
+               "dmts_state_create: null argument");
+  *out = nullptr;
+  DMTS_REQUIRE(n_atoms >= 1 && n_species >= 1 && n_species <= 8, DMTS_E_ARG,
+               "dmts_state_create: bad sizes (%d atoms, %d species)", n_atoms, n_species);
+  DMTS_REQUIRE(dt_outer_fs > 0.0 && n_inner >= 1, DMTS_E_ARG,
+               "dmts_state_create: need dt > 0 and n_inner >= 1");
+  DMTS_REQUIRE(max_nbrs_small >= 1 && max_nbrs_large >= 1, DMTS_E_ARG,
+               "dmts_state_create: neighbor bounds must be positive");
+  DMTS_REQUIRE(box >= 0.0, DMTS_E_ARG, "dmts_state_create: negative box");
+  for (int z = 0; z < n_species; ++z)
+    DMTS_REQUIRE(host_mass_by_species[z] > 0.0, DMTS_E_ARG,
+                 "dmts_state_create: mass of species %d must be positive", z);
+  State* st = new State();
+  st->n = n_atoms;
+  st->box = box;
+  st->species = species;
+  st->dt = dt_outer_fs;
+  st->n_inner = n_inner;
+  dmts_status r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_small + 4), 4,
+                                   reinterpret_cast<nnp_nlist**>(&st->nl_small));
+  if (r == DMTS_OK)
+    r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 4), 4,
+                         reinterpret_cast<nnp_nlist**>(&st->nl_large));
+  double hm[16] = {0}, him[16] = {0};
+  for (int z = 0; z < n_species; ++z) {
+    hm[z] = host_mass_by_species[z];
+    him[z] = 1.0 / host_mass_by_species[z];
+  }
+  hipError_t e = hipSuccess;
+  if (r == DMTS_OK) {
+    e = hipMalloc(&st->FL, sizeof(float) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&st->Fs, sizeof(float) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&st->mass, sizeof(double) * 16);
+    if (e == hipSuccess) e = hipMalloc(&st->inv_mass, sizeof(double) * 16);
+    if (e == hipSuccess) e = hipMalloc(&st->e_models, sizeof(double) * 4);
+    if (e == hipSuccess) e = hipMalloc(&st->flags, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(st->mass, hm, sizeof(hm), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st->inv_mass, him, sizeof(him), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(st->e_models, 0, sizeof(double) * 4);
+    if (e == hipSuccess) e = hipMemset(st->flags, 0, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      dmts::set_error("dmts_state_create: %s", hipGetErrorString(e));
+      r = DMTS_E_OOM;
+    }
+  }
+  if (r != DMTS_OK) {
+    dmts_state_destroy(reinterpret_cast<dmts_state*>(st));
+    return r;
+  }
+  *out = reinterpret_cast<dmts_state*>(st);
+  return DMTS_OK;
+}
+
+extern "C" void dmts_state_destroy(dmts_state* h) {
+  State* st = reinterpret_cast<State*>(h);
+  if (!st) return;
+  (void)hipDeviceSynchronize();
+  nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_small));
+  nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large));
+  (void)hipFree(st->FL);
+  (void)hipFree(st->Fs);
+  (void)hipFree(st->mass);
+  (void)hipFree(st->inv_mass);
+  (void)hipFree(st->e_models);
+  (void)hipFree(st->flags);
+  delete st;
+}
+
+extern "C" dmts_status dmts_state_reset(dmts_state* h) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_reset: null state");
+  st->first = true;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_forces(dmts_state* h, const float** f_large,
+                                         const float** f_small) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_forces: null state");
+  if (f_large) *f_large = st->FL;
+  if (f_small) *f_small = st->Fs;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_flags(dmts_state* h, void* stream, uint32_t* host_flags) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st && host_flags, DMTS_E_ARG, "dmts_state_flags: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dmts::k_merge_flags<<<1, 64, 0, s>>>(st->flags, st->nl_small->flags, st->nl_large->flags);
+  DMTS_CHECK_LAUNCH();
+  DMTS_HIP(hipMemcpyAsync(host_flags, st->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  DMTS_HIP(hipStreamSynchronize(s));
+  dmts_status r = dmts::fill_u32(st->flags, 0u, 1, s);
+  if (r == DMTS_OK) r = dmts::fill_u32(st->nl_small->flags, 0u, 1, s);
+  if (r == DMTS_OK) r = dmts::fill_u32(st->nl_large->flags, 0u, 1, s);
+  if (r != DMTS_OK) return r;
+  DMTS_HIP(hipStreamSynchronize(s));
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model* small_h,
+                                 nnp_model* large_h, int32_t n_outer, double* energies_out,
+                                 void* stream) {
+  State* st = reinterpret_cast<State*>(h);
+  Model* small = reinterpret_cast<Model*>(small_h);
+  Model* large = reinterpret_cast<Model*>(large_h);
+  DMTS_REQUIRE(st && x && v && large, DMTS_E_ARG, "dmts_step: null argument");
+  DMTS_REQUIRE(n_outer >= 0, DMTS_E_ARG, "dmts_step: n_outer must be >= 0");
+  DMTS_REQUIRE(large->desc.cutoff < 0.5 * st->box || st->box == 0.0, DMTS_E_BOX,
+               "dmts_step: cutoff %g must be below half the box edge", large->desc.cutoff);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (small != st->last_small || large != st->last_large) st->first = true;
+  st->last_small = small;
+  st->last_large = large;
+  dmts::Runner R{st, x, v, s};
+  dmts_status r;
+  const double kappa = dmts::kKappa;
+  double* eL = st->e_models;
+  double* eS = st->e_models + 1;
+  if (!small) {
+    // single-time-step baseline: velocity Verlet (BAOAB with the O-step off)
+    const double dt = st->dt;
+    if (st->first) {
+      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
+      st->first = false;
+    }
+    for (int o = 0; o < n_outer; ++o) {
+      R.push(dmts::kKickLarge, 0.5 * dt * kappa);
+      R.push(dmts::kDrift, 0.5 * dt);
+      R.push(dmts::kDrift, 0.5 * dt);
+      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
+      R.push(dmts::kKickLarge, 0.5 * dt * kappa);
+    }
+  } else {
+    const double dt = st->dt;
+    const int n = st->n_inner;
+    const double h_in = dt / n;
+    if (st->first) {
+      if ((r = R.eval(small, st->nl_small, st->Fs, eS)) != DMTS_OK) return r;
+      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
+      st->first = false;
+    }
+    for (int o = 0; o < n_outer; ++o) {
+      R.push(dmts::kKickSlow, 0.5 * dt * kappa);
+      for (int k = 0; k < n; ++k) {
+        R.push(dmts::kKickFast, 0.5 * h_in * kappa);
+        R.push(dmts::kDrift, 0.5 * h_in);
+        R.push(dmts::kDrift, 0.5 * h_in);
+        if ((r = R.eval(small, st->nl_small, st->Fs, eS)) != DMTS_OK) return r;
+        R.push(dmts::kKickFast, 0.5 * h_in * kappa);
+      }
+      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
+      R.push(dmts::kKickSlow, 0.5 * dt * kappa);
+    }
+  }
+  if ((r = R.flush()) != DMTS_OK) return r;
+  dmts::k_energies<<<1, 256, 0, s>>>(st->n, v, st->species, st->mass, st->e_models,
+                                     energies_out, st->flags);
+  DMTS_CHECK_LAUNCH();
+  uint32_t f = 0;
+  if ((r = dmts_state_flags(h, stream, &f)) != DMTS_OK) return r;
+  DMTS_REQUIRE(!(f & DMTS_FLAG_NBR_OVERFLOW), DMTS_E_CAPACITY,
+               "dmts_step: a neighbor list overflowed; raise max_nbrs");
+  DMTS_REQUIRE(!(f & DMTS_FLAG_NONFINITE), DMTS_E_NONFINITE,
+               "dmts_step: non-finite positions, velocities or energies");
+  return DMTS_OK;
+}

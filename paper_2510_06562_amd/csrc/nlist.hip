@@ -1,0 +1,446 @@
+// Neighbor lists for the message-passing sums of both potentials.
+//
+// The pair set is {(i, j): j != i, |d_ij| < r_c} with d_ij = x_j - x_i under the
+// minimum-image convention of a cube (plain difference for open boundaries, restricted
+// to one molecule for a batch).  The paper leaves the search unspecified; this is a
+// cell list: atoms are binned into cells of edge >= r_c, each receiver scans the 27
+// surrounding cells.  Every receiver is handled by one wavefront whose lanes walk the
+// candidate stream of those cells; a ballot compacts the accepted senders, so each row
+// comes out in candidate order (stencil order, then ascending atom index inside a cell)
+// and the whole list is bitwise reproducible.  Rows are padded with -1 to a multiple of
+// the list's row alignment.  rev[p] locates the reverse pair of every real entry.
+#include "common.h"
+
+namespace dmts {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kMaxCellsPerDim = 64;
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Exclusive scan of in[0..n) into out[0..n]; single work-group.  When the total exceeds
+// `cap` the list would not fit: every offset is set to 0 (all rows empty) and the
+// overflow flag is raised, so no consumer can index past the capacity.
+__global__ void __launch_bounds__(kScanThreads) k_scan(const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ out,
+                                                      int32_t* __restrict__ copy_to,
+                                                      int32_t n, int64_t cap,
+                                                      uint32_t* __restrict__ flags) {
+  __shared__ int64_t part[kScanThreads];
+  __shared__ int64_t total_s;
+  const int t = threadIdx.x;
+  const int per = (n + kScanThreads - 1) / kScanThreads;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  int64_t s = 0;
+  for (int k = lo; k < hi; ++k) s += in[k];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread sums
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int64_t add = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  if (t == kScanThreads - 1) total_s = part[t];
+  __syncthreads();
+  const int64_t total = total_s;
+  const bool overflow = total > cap;
+  int64_t run = (t == 0) ? 0 : part[t - 1];
+  for (int k = lo; k < hi; ++k) {
+    int32_t o = overflow ? 0 : static_cast<int32_t>(run);
+    out[k] = o;
+    if (copy_to) copy_to[k] = o;
+    run += in[k];
+  }
+  if (t == 0) {
+    out[n] = overflow ? 0 : static_cast<int32_t>(total);
+    if (overflow && flags) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+  }
+}
+
+__device__ __forceinline__ int cell_coord(double x, double box, double inv_cell, int nc) {
+  double w = x - box * floor(x / box);   // wrap into [0, box)
+  if (!(w >= 0.0 && w < box)) w = 0.0;    // non-finite input: any in-range cell
+  int c = static_cast<int>(w * inv_cell);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ void k_cell_assign(const double* __restrict__ pos, int32_t n, double box,
+                              double inv_cell, int nc, int32_t* __restrict__ cell_of,
+                              int32_t* __restrict__ cell_count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int cx = cell_coord(pos[i], box, inv_cell, nc);
+  int cy = cell_coord(pos[n + i], box, inv_cell, nc);
+  int cz = cell_coord(pos[2 * n + i], box, inv_cell, nc);
+  int c = (cz * nc + cy) * nc + cx;
+  cell_of[i] = c;
+  atomicAdd(&cell_count[c], 1);
+}
+
+__global__ void k_cell_scatter(const int32_t* __restrict__ cell_of, int32_t n,
+                               int32_t* __restrict__ cursor, int32_t* __restrict__ cell_atoms) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int slot = atomicAdd(&cursor[cell_of[i]], 1);
+  cell_atoms[slot] = i;
+}
+
+// Members of each cell in ascending atom order (undoes the arbitrary order of the
+// atomic scatter).
+__global__ void k_cell_sort(const int32_t* __restrict__ cell_start, int32_t n_cells,
+                            int32_t* __restrict__ cell_atoms) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const int lo = cell_start[c], hi = cell_start[c + 1];
+  for (int a = lo + 1; a < hi; ++a) {
+    int v = cell_atoms[a];
+    int b = a - 1;
+    while (b >= lo && cell_atoms[b] > v) {
+      cell_atoms[b + 1] = cell_atoms[b];
+      --b;
+    }
+    cell_atoms[b + 1] = v;
+  }
+}
+
+struct Geo {
+  const double* pos;
+  int32_t n;
+  double box, inv_box, rc2;
+};
+
+__device__ __forceinline__ bool within(const Geo& g, double xi, double yi, double zi, int j) {
+  double dx = minimage(g.pos[j] - xi, g.box, g.inv_box);
+  double dy = minimage(g.pos[g.n + j] - yi, g.box, g.inv_box);
+  double dz = minimage(g.pos[2 * g.n + j] - zi, g.box, g.inv_box);
+  return dx * dx + dy * dy + dz * dz < g.rc2;
+}
+
+// Candidate stream of receiver i.  Cell mode: the 27 cells around i's cell, in stencil
+// order, each cell's members ascending.  Range mode: atoms lo..hi-1 (its molecule, or all
+// atoms).  `visit(t_base, j, valid)` is called wave-uniformly once per 64 candidates
+// with each lane's candidate.
+struct CellCtx {
+  const int32_t* cell_start;
+  const int32_t* cell_atoms;
+  const int32_t* cell_of;
+  int nc;
+};
+
+template <bool kCells, class Visit>
+__device__ __forceinline__ void walk_candidates(int i, int lo, int hi, const CellCtx& cc,
+                                                int32_t* s_pref, int32_t* s_first,
+                                                Visit&& visit) {
+  const int lane = threadIdx.x & 63;
+  if (!kCells) {
+    for (int base = lo; base < hi; base += 64) {
+      int j = base + lane;
+      bool ok = j < hi && j != i;
+      visit(ok ? j : -1, ok);
+    }
+    return;
+  }
+  // per-lane stencil cell (lanes 0..26)
+  const int nc = cc.nc;
+  const int ci = cc.cell_of[i];
+  const int cx = ci % nc, cy = (ci / nc) % nc, cz = ci / (nc * nc);
+  int count = 0, first = 0;
+  if (lane < 27) {
+    int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+    int x = (cx + dx + nc) % nc, y = (cy + dy + nc) % nc, z = (cz + dz + nc) % nc;
+    int c = (z * nc + y) * nc + x;
+    first = cc.cell_start[c];
+    count = cc.cell_start[c + 1] - first;
+  }
+  // inclusive scan of counts over lanes
+  int incl = count;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane < 27) {
+    s_pref[lane] = incl - count;
+    s_first[lane] = first;
+  }
+  const int total = __shfl(incl, 26, 64);
+  wave_sync();
+  for (int base = 0; base < total; base += 64) {
+    int t = base + lane;
+    int j = -1;
+    if (t < total) {
+      int k = 0;
+      while (k < 26 && s_pref[k + 1] <= t) ++k;
+      j = cc.cell_atoms[s_first[k] + (t - s_pref[k])];
+    }
+    bool ok = j >= 0 && j != i;
+    visit(j, ok);
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ void molecule_range(const int32_t* sys_offsets, int32_t n_sys,
+                                               int i, int n, int& lo, int& hi) {
+  if (!sys_offsets) {
+    lo = 0;
+    hi = n;
+    return;
+  }
+  int a = 0, b = n_sys;  // find s with offs[s] <= i < offs[s+1]
+  while (b - a > 1) {
+    int mid = (a + b) >> 1;
+    if (sys_offsets[mid] <= i) a = mid; else b = mid;
+  }
+  lo = max(0, sys_offsets[a]);
+  hi = min(n, sys_offsets[a + 1]);
+}
+
+constexpr int kNbWaves = 4;
+
+template <bool kCells>
+__global__ void __launch_bounds__(kNbWaves * 64)
+k_count(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys,
+        int32_t align, int32_t* __restrict__ cnt) {
+  __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kNbWaves + w;
+  if (i >= g.n) return;
+  const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
+  int lo = 0, hi = 0;
+  if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
+  int total = 0;
+  walk_candidates<kCells>(i, lo, hi, cc, s_pref[w], s_first[w], [&](int j, bool ok) {
+    bool acc = ok && within(g, xi, yi, zi, j);
+    total += __popcll(__ballot(acc));
+  });
+  if ((threadIdx.x & 63) == 0) cnt[i] = (total + align - 1) / align * align;
+}
+
+template <bool kCells>
+__global__ void __launch_bounds__(kNbWaves * 64)
+k_fill(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys,
+       const int32_t* __restrict__ offs, int32_t* __restrict__ nbr) {
+  __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNbWaves + w;
+  if (i >= g.n) return;
+  const int row0 = offs[i], row1 = offs[i + 1];
+  if (row1 == row0) return;  // empty row, or the list overflowed (all offsets zero)
+  const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
+  int lo = 0, hi = 0;
+  if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
+  int run = 0;
+  walk_candidates<kCells>(i, lo, hi, cc, s_pref[w], s_first[w], [&](int j, bool ok) {
+    bool acc = ok && within(g, xi, yi, zi, j);
+    uint64_t mask = __ballot(acc);
+    int before = __popcll(mask & ((1ull << lane) - 1ull));
+    int p = row0 + run + before;
+    if (acc && p < row1) nbr[p] = j;
+    run += __popcll(mask);
+  });
+  for (int p = row0 + run + lane; p < row1; p += 64) nbr[p] = -1;
+}
+
+// rev[p] for p = (i, j): position of i in row j (rows are at least 4-aligned).
+__global__ void __launch_bounds__(kNbWaves * 64)
+k_rev(int32_t n, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
+      int32_t* __restrict__ rev) {
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNbWaves + w;
+  if (i >= n) return;
+  const int row0 = offs[i], row1 = offs[i + 1];
+  for (int p = row0 + lane; p < row1; p += 64) {
+    int j = nbr[p];
+    int found = -1;
+    if (j >= 0) {
+      const int q0 = offs[j], q1 = offs[j + 1];
+      for (int q = q0; q < q1 && found < 0; q += 4) {
+        int4 v = *reinterpret_cast<const int4*>(nbr + q);
+        if (v.x == i) found = q;
+        else if (v.y == i) found = q + 1;
+        else if (v.z == i) found = q + 2;
+        else if (v.w == i) found = q + 3;
+        else if (v.w < 0) break;
+      }
+    }
+    rev[p] = found;
+  }
+}
+
+}  // namespace
+
+dmts_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return DMTS_OK;
+  k_fill_u32<<<ceil_div(n, 256), 256, 0, s>>>(p, v, n);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
+                            const int32_t* sys_offsets, int32_t n_sys, double cutoff,
+                            hipStream_t s) {
+  DMTS_REQUIRE(nl && pos, DMTS_E_ARG, "build_neighbors: null argument");
+  DMTS_REQUIRE(n >= 0 && n <= nl->max_atoms, DMTS_E_ARG,
+               "build_neighbors: n_atoms %d outside [0, %d]", n, nl->max_atoms);
+  DMTS_REQUIRE(cutoff > 0.0, DMTS_E_ARG, "build_neighbors: cutoff must be positive");
+  DMTS_REQUIRE(box >= 0.0, DMTS_E_ARG, "build_neighbors: negative box");
+  DMTS_REQUIRE(box == 0.0 || cutoff < 0.5 * box, DMTS_E_BOX,
+               "build_neighbors: cutoff %g must be below half the box edge %g", cutoff, box);
+  DMTS_REQUIRE(box == 0.0 || sys_offsets == nullptr, DMTS_E_ARG,
+               "build_neighbors: batched molecules need open boundaries");
+  DMTS_REQUIRE(sys_offsets == nullptr || n_sys >= 1, DMTS_E_ARG,
+               "build_neighbors: n_sys must be >= 1 with sys_offsets");
+  nl->n_atoms = n;
+  nl->box = box;
+  nl->cutoff = cutoff;
+  ProfScope ps(DMTS_K_NEIGHBORS, s);
+  if (n == 0) {
+    return fill_u32(reinterpret_cast<uint32_t*>(nl->offs), 0u, 1, s);
+  }
+  Geo g{pos, n, box, box > 0.0 ? 1.0 / box : 0.0, cutoff * cutoff};
+  CellCtx cc{nullptr, nullptr, nullptr, 0};
+  int nc = box > 0.0 ? static_cast<int>(floor(box / cutoff)) : 0;
+  const bool cells = nc >= 3;
+  if (cells) {
+    nc = nc > kMaxCellsPerDim ? kMaxCellsPerDim : nc;
+    const int n_cells = nc * nc * nc;
+    DMTS_REQUIRE(nl->cell_buf.reserve(sizeof(int32_t) * (3 * (size_t)n_cells + 2), s) == DMTS_OK,
+                 DMTS_E_OOM, "build_neighbors: cell buffer allocation failed");
+    int32_t* cell_count = nl->cell_buf.as<int32_t>();
+    int32_t* cell_start = cell_count + n_cells;
+    int32_t* cursor = cell_start + n_cells + 1;
+    dmts_status st = fill_u32(reinterpret_cast<uint32_t*>(cell_count), 0u, n_cells, s);
+    if (st != DMTS_OK) return st;
+    const double inv_cell = nc / box;
+    k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
+                                                   cell_count);
+    DMTS_CHECK_LAUNCH();
+    k_scan<<<1, kScanThreads, 0, s>>>(cell_count, cell_start, cursor, n_cells, INT64_MAX,
+                                      nullptr);
+    DMTS_CHECK_LAUNCH();
+    k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms);
+    DMTS_CHECK_LAUNCH();
+    k_cell_sort<<<ceil_div(n_cells, 128), 128, 0, s>>>(cell_start, n_cells, nl->cell_atoms);
+    DMTS_CHECK_LAUNCH();
+    cc = CellCtx{cell_start, nl->cell_atoms, nl->cell_of, nc};
+  }
+  const int blocks = ceil_div(n, kNbWaves);
+  if (cells)
+    k_count<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align, nl->cnt);
+  else
+    k_count<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align, nl->cnt);
+  DMTS_CHECK_LAUNCH();
+  k_scan<<<1, kScanThreads, 0, s>>>(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags);
+  DMTS_CHECK_LAUNCH();
+  if (cells)
+    k_fill<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->offs, nl->nbr);
+  else
+    k_fill<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->offs, nl->nbr);
+  DMTS_CHECK_LAUNCH();
+  k_rev<<<blocks, kNbWaves * 64, 0, s>>>(n, nl->offs, nl->nbr, nl->rev);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+}  // namespace dmts
+
+// ------------------------------------------------------------------ C ABI
+using dmts::NList;
+
+extern "C" dmts_status nnp_nlist_create(int32_t max_atoms, int64_t max_pairs,
+                                        int32_t row_align, nnp_nlist** out) {
+  DMTS_REQUIRE(out, DMTS_E_ARG, "nnp_nlist_create: out is NULL");
+  *out = nullptr;
+  DMTS_REQUIRE(max_atoms >= 1 && max_pairs >= 1 && max_pairs < (int64_t(1) << 31),
+               DMTS_E_ARG, "nnp_nlist_create: bad capacity (%d atoms, %lld pairs)",
+               max_atoms, (long long)max_pairs);
+  DMTS_REQUIRE(row_align == 4 || row_align == 16 || row_align == 32 || row_align == 64,
+               DMTS_E_ARG, "nnp_nlist_create: row_align must be 4, 16, 32 or 64");
+  NList* nl = new NList();
+  nl->max_atoms = max_atoms;
+  nl->max_pairs = (max_pairs + 3) / 4 * 4;
+  nl->row_align = row_align;
+  size_t a = (size_t)max_atoms;
+  hipError_t e = hipSuccess;
+  e = e == hipSuccess ? hipMalloc(&nl->offs, sizeof(int32_t) * (a + 1)) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->cnt, sizeof(int32_t) * a) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->cell_of, sizeof(int32_t) * a) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->cell_atoms, sizeof(int32_t) * a) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->nbr, sizeof(int32_t) * nl->max_pairs) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->rev, sizeof(int32_t) * nl->max_pairs) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->flags, sizeof(uint32_t)) : e;
+  e = e == hipSuccess ? hipMemset(nl->flags, 0, sizeof(uint32_t)) : e;
+  e = e == hipSuccess ? hipMemset(nl->offs, 0, sizeof(int32_t) * (a + 1)) : e;
+  e = e == hipSuccess ? hipDeviceSynchronize() : e;
+  if (e != hipSuccess) {
+    dmts::set_error("nnp_nlist_create: %s", hipGetErrorString(e));
+    nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(nl));
+    return DMTS_E_OOM;
+  }
+  *out = reinterpret_cast<nnp_nlist*>(nl);
+  return DMTS_OK;
+}
+
+extern "C" void nnp_nlist_destroy(nnp_nlist* h) {
+  NList* nl = reinterpret_cast<NList*>(h);
+  if (!nl) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(nl->offs);
+  (void)hipFree(nl->cnt);
+  (void)hipFree(nl->cell_of);
+  (void)hipFree(nl->cell_atoms);
+  (void)hipFree(nl->nbr);
+  (void)hipFree(nl->rev);
+  (void)hipFree(nl->flags);
+  nl->cell_buf.release();
+  delete nl;
+}
+
+extern "C" dmts_status nnp_build_neighbors(nnp_nlist* h, const double* pos, int32_t n_atoms,
+                                           double box, const int32_t* sys_offsets,
+                                           int32_t n_sys, double cutoff, void* stream) {
+  return dmts::build_neighbors(reinterpret_cast<NList*>(h), pos, n_atoms, box, sys_offsets,
+                               n_sys, cutoff, static_cast<hipStream_t>(stream));
+}
+
+extern "C" dmts_status nnp_nlist_flags(nnp_nlist* h, void* stream, uint32_t* host_flags) {
+  NList* nl = reinterpret_cast<NList*>(h);
+  DMTS_REQUIRE(nl && host_flags, DMTS_E_ARG, "nnp_nlist_flags: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DMTS_HIP(hipMemcpyAsync(host_flags, nl->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  DMTS_HIP(hipStreamSynchronize(s));
+  dmts_status st = dmts::fill_u32(nl->flags, 0u, 1, s);
+  if (st != DMTS_OK) return st;
+  DMTS_HIP(hipStreamSynchronize(s));
+  return DMTS_OK;
+}
+
+extern "C" dmts_status nnp_nlist_download(nnp_nlist* h, void* stream, int32_t* host_offs,
+                                          int32_t* host_nbr, int32_t* host_rev,
+                                          int64_t host_cap, int64_t* n_entries) {
+  NList* nl = reinterpret_cast<NList*>(h);
+  DMTS_REQUIRE(nl && host_offs && n_entries, DMTS_E_ARG, "nnp_nlist_download: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = nl->n_atoms;
+  DMTS_HIP(hipMemcpyAsync(host_offs, nl->offs, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  DMTS_HIP(hipStreamSynchronize(s));
+  const int64_t P = host_offs[n];
+  *n_entries = P;
+  DMTS_REQUIRE(P <= host_cap, DMTS_E_CAPACITY, "nnp_nlist_download: %lld entries, host capacity %lld",
+               (long long)P, (long long)host_cap);
+  if (P > 0 && host_nbr)
+    DMTS_HIP(hipMemcpyAsync(host_nbr, nl->nbr, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+  if (P > 0 && host_rev)
+    DMTS_HIP(hipMemcpyAsync(host_rev, nl->rev, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+  DMTS_HIP(hipStreamSynchronize(s));
+  return DMTS_OK;
+}
