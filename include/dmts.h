@@ -178,6 +178,15 @@ dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos
  *   DMTS_E_CAPACITY or DMTS_E_NONFINITE if set.
  * dmts_state_reset: forget the carried forces (call after changing x outside
  *   dmts_step).
+ * dmts_state_fallbacks: number of dmts_step calls that had to be redone because an atom
+ *   moved farther than the shared neighbor list allows (see the neighbor-list note).
+ *
+ * Neighbor-list note: each reference evaluation builds one list at
+ * max(r_c,large, r_c,small + 1 A); the fast model of the next inner steps reuses it, which
+ * is exact while every atom stays within half the gap to the fast cutoff of where the
+ * list was built.  The device checks that bound at every drift; when it fails, the call
+ * restores its starting x, v and carried forces and repeats with fresh lists for every
+ * evaluation (same results, slower).
  * dmts_state_forces: device pointers to the carried F_large and F_small (float32
  *   [3][n_atoms]) for inspection.
  */
@@ -190,6 +199,7 @@ dmts_status dmts_step(dmts_state* st, double* x, double* v, nnp_model* small,
                       nnp_model* large, int32_t n_outer, double* energies_out,
                       void* stream);
 dmts_status dmts_state_reset(dmts_state* st);
+dmts_status dmts_state_fallbacks(dmts_state* st, int64_t* n_calls);
 dmts_status dmts_state_forces(dmts_state* st, const float** f_large, const float** f_small);
 dmts_status dmts_state_flags(dmts_state* st, void* stream, uint32_t* host_flags);
 

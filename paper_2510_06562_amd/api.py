@@ -70,6 +70,7 @@ _SIGS = {
     "dmts_state_destroy": ([_P], None),
     "dmts_step": ([_P, _P, _P, _P, _P, _I32, _P, _P], _I32),
     "dmts_state_reset": ([_P], _I32),
+    "dmts_state_fallbacks": ([_P, ctypes.POINTER(_I64)], _I32),
     "dmts_state_forces": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I32),
     "dmts_state_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
     "dmts_prof_enable": ([ctypes.c_uint32], _I32),
@@ -310,6 +311,13 @@ class DMTS:
 
     def reset(self):
         _check(lib().dmts_state_reset(self._h))
+
+    @property
+    def fallbacks(self) -> int:
+        """Calls redone with exact neighbor lists (an atom outran the shared list)."""
+        n = ctypes.c_int64()
+        _check(lib().dmts_state_fallbacks(self._h, ctypes.byref(n)))
+        return n.value
 
     def forces(self):
         fl, fs = ctypes.c_void_p(), ctypes.c_void_p()

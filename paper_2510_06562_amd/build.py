@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmts.so")
-SOURCES = ["api.hip", "nlist.hip", "gemm.hip", "small.hip", "large.hip", "integrate.hip"]
+SOURCES = ["api.hip", "nlist.hip", "atom_mlp.hip", "small.hip", "large.hip", "integrate.hip"]
 
 
 def hipcc() -> str:

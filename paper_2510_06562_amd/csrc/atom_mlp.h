@@ -1,0 +1,29 @@
+// Fused per-atom MLP chains of the reference potential (internal).
+#pragma once
+
+#include "common.h"
+
+namespace dmts {
+
+// Weight views (row-major [K x N], K = input width, N = output width).
+struct AtomMlpParams {
+  const float* U1T;   // [384][128]  z1 = U1 q1
+  const float* W2hT;  // [128][256]  [A | B] = [W_s | W_r] h1
+  const float* U2T;   // [384][128]
+  const float* WoT;   // [128][128]  y = W_o h2
+  const float* wo;    // [128]
+  const float* Wo;    // [128][128]  dh2 = W_o^T dy
+  const float* U2;    // [128][384]  dq2 = U2^T dz2
+  const float* W2hs;  // [256][128]  dh1 = W_r^T R + W_s^T S
+  const float* U1;    // [128][384]  dq1 = U1^T dz1
+};
+
+dmts_status atom_chain1(const AtomMlpParams& P, int M, const float* q1, float* z1, float* h1,
+                        float* P2, hipStream_t s);
+dmts_status atom_chain2(const AtomMlpParams& P, int M, const float* q2, const float* h1,
+                        float escale, float* atom_e, float* dh2, float* dq2, bool backward,
+                        hipStream_t s);
+dmts_status atom_chain3(const AtomMlpParams& P, int M, const float* RS, const float* dh2,
+                        const float* z1, float* dq1, hipStream_t s);
+
+}  // namespace dmts

@@ -1,0 +1,192 @@
+// Per-atom dense layers of the reference potential as fused MFMA chains.
+//
+// Every per-atom layer is a row-local contraction [rows x K] * [K x N], so the whole chain
+// of layers between two pair kernels runs in one launch: a work-group owns a tile of 16
+// atoms, keeps the activations of the tile in LDS between layers and streams the weights
+// (at most 384 x 384 floats, L2-resident) from global memory.  Contractions use
+// v_mfma_f32_16x16x4_f32; the four waves of the work-group split the output columns in
+// blocks of 16.
+//
+//   chain 1 (after interaction 1):  z1 = U1 q1, h1 = SiLU(z1), [A|B] = [W_s|W_r] h1
+//   chain 2 (after interaction 2):  z2 = U2 q2, h2 = h1 + SiLU(z2), y = W_o h2,
+//                                   E = s_E w_o . SiLU(y), dy = s_E w_o SiLU'(y),
+//                                   dh2 = W_o^T dy, dz2 = dh2 SiLU'(z2), dq2 = U2^T dz2
+//   chain 3 (after the sender sums): dh1 = dh2 + W_r^T R + W_s^T S, dz1 = dh1 SiLU'(z1),
+//                                   dq1 = U1^T dz1
+//
+// MFMA 16x16x4 f32 register layout:
+//   A operand: lane l holds A[l % 16][k0 + l / 16]
+//   B operand: lane l holds B[k0 + l / 16][l % 16]
+//   D: lane l, register r holds D[4 (l / 16) + r][l % 16]
+#include "atom_mlp.h"
+
+namespace dmts {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRows = 16;
+constexpr int kThreads = 256;
+constexpr int kLd = 388;     // LDS row stride (floats) for activations up to 384 wide
+
+// acc[16 x 16] block = X[16 x K] (LDS, stride kLd) * B[K x ...] (global, stride ldb),
+// columns n0 .. n0+15.
+__device__ __forceinline__ f32x4 mfma_block(const float* X, int K, const float* __restrict__ B,
+                                            int ldb, int n0, int lane) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int r = lane & 15, kk = lane >> 4;
+  const float* xp = X + r * kLd + kk;
+  const float* bp = B + (size_t)kk * ldb + n0 + r;
+#pragma unroll 8
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xp[k0], bp[(size_t)k0 * ldb], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Runs one layer: for every 16-column block of N assigned to this wave, calls
+// epi(row, col, value) for the lane's four outputs.
+template <class Epi>
+__device__ __forceinline__ void layer(const float* X, int K, const float* __restrict__ B, int N,
+                                      Epi&& epi) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int nb = wave; nb < N / 16; nb += kThreads / 64) {
+    f32x4 acc = mfma_block(X, K, B, N, nb * 16, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) epi(4 * (lane >> 4) + r, nb * 16 + (lane & 15), acc[r]);
+  }
+}
+
+// Stage rows [m0, m0+16) of a global row-major array (ld floats, K used) into LDS.
+__device__ __forceinline__ void stage_rows(float* X, const float* __restrict__ G, int ld, int K,
+                                           int m0, int M) {
+  for (int e = threadIdx.x; e < kRows * K; e += kThreads) {
+    const int r = e / K, k = e - r * K;
+    X[r * kLd + k] = (m0 + r) < M ? G[(size_t)(m0 + r) * ld + k] : 0.f;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict__ z1,
+         float* __restrict__ h1, float* __restrict__ P2) {
+  __shared__ float X[kRows * kLd];
+  __shared__ float H[kRows * kLd];
+  const int m0 = blockIdx.x * kRows;
+  stage_rows(X, q1, 384, 384, m0, M);
+  __syncthreads();
+  layer(X, 384, P.U1T, 128, [&](int r, int c, float v) {
+    const float h = silu_f(v);
+    H[r * kLd + c] = h;
+    if (m0 + r < M) {
+      z1[(size_t)(m0 + r) * 128 + c] = v;
+      h1[(size_t)(m0 + r) * 128 + c] = h;
+    }
+  });
+  __syncthreads();
+  layer(H, 128, P.W2hT, 256, [&](int r, int c, float v) {
+    if (m0 + r < M) P2[(size_t)(m0 + r) * 256 + c] = v;
+  });
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __restrict__ h1,
+         float escale, float* __restrict__ atom_e, float* __restrict__ dh2_out,
+         float* __restrict__ dq2, bool backward) {
+  __shared__ float X[kRows * kLd];     // q2, later dz2
+  __shared__ float H[kRows * kLd];     // h2, later dy
+  __shared__ float Z[kRows * 128];     // z2
+  __shared__ float E[kRows * 128];     // per-column energy terms of y
+  const int m0 = blockIdx.x * kRows;
+  stage_rows(X, q2, 384, 384, m0, M);
+  __syncthreads();
+  layer(X, 384, P.U2T, 128, [&](int r, int c, float v) {
+    Z[r * 128 + c] = v;
+    const float hp = (m0 + r) < M ? h1[(size_t)(m0 + r) * 128 + c] : 0.f;
+    H[r * kLd + c] = hp + silu_f(v);
+  });
+  __syncthreads();
+  // y = W_o h2; energy terms and dy (dy overwrites the X buffer)
+  layer(H, 128, P.WoT, 128, [&](int r, int c, float v) {
+    float s, ds;
+    silu_and_grad(v, s, ds);
+    const float w = P.wo[c];
+    E[r * 128 + c] = w * s;
+    X[r * kLd + c] = escale * w * ds;
+  });
+  __syncthreads();
+  // per-atom energy: fixed-order sum of 128 terms (one wave, 4 lanes per row)
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x >> 2, part = threadIdx.x & 3;
+    float s = 0.f;
+    for (int c = part * 32; c < part * 32 + 32; ++c) s += E[r * 128 + c];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (part == 0 && m0 + r < M) atom_e[m0 + r] = s * escale;
+  }
+  if (!backward) return;
+  // dh2 = W_o^T dy, dz2 = dh2 SiLU'(z2)   (dz2 goes to H)
+  layer(X, 128, P.Wo, 128, [&](int r, int c, float v) {
+    if (m0 + r < M) dh2_out[(size_t)(m0 + r) * 128 + c] = v;
+    H[r * kLd + c] = v * dsilu_f(Z[r * 128 + c]);
+  });
+  __syncthreads();
+  layer(H, 128, P.U2, 384, [&](int r, int c, float v) {
+    if (m0 + r < M) dq2[(size_t)(m0 + r) * 384 + c] = v;
+  });
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __restrict__ dh2,
+         const float* __restrict__ z1, float* __restrict__ dq1) {
+  __shared__ float X[kRows * kLd];
+  __shared__ float H[kRows * kLd];
+  const int m0 = blockIdx.x * kRows;
+  stage_rows(X, RS, 256, 256, m0, M);
+  __syncthreads();
+  layer(X, 256, P.W2hs, 128, [&](int r, int c, float v) {
+    float dz = 0.f;
+    if (m0 + r < M) {
+      const size_t o = (size_t)(m0 + r) * 128 + c;
+      dz = (v + dh2[o]) * dsilu_f(z1[o]);
+    }
+    H[r * kLd + c] = dz;
+  });
+  __syncthreads();
+  layer(H, 128, P.U1, 384, [&](int r, int c, float v) {
+    if (m0 + r < M) dq1[(size_t)(m0 + r) * 384 + c] = v;
+  });
+}
+
+}  // namespace
+
+dmts_status atom_chain1(const AtomMlpParams& P, int M, const float* q1, float* z1, float* h1,
+                        float* P2, hipStream_t s) {
+  if (M <= 0) return DMTS_OK;
+  ProfScope ps(DMTS_K_ATOM_GEMM, s);
+  k_chain1<<<ceil_div(M, kRows), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+dmts_status atom_chain2(const AtomMlpParams& P, int M, const float* q2, const float* h1,
+                        float escale, float* atom_e, float* dh2, float* dq2, bool backward,
+                        hipStream_t s) {
+  if (M <= 0) return DMTS_OK;
+  ProfScope ps(DMTS_K_ATOM_GEMM, s);
+  k_chain2<<<ceil_div(M, kRows), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2, dq2,
+                                                   backward);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+dmts_status atom_chain3(const AtomMlpParams& P, int M, const float* RS, const float* dh2,
+                        const float* z1, float* dq1, hipStream_t s) {
+  if (M <= 0) return DMTS_OK;
+  ProfScope ps(DMTS_K_ATOM_GEMM, s);
+  k_chain3<<<ceil_div(M, kRows), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+}  // namespace dmts

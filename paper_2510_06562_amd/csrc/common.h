@@ -49,6 +49,7 @@ constexpr int kWave = 64;
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 // ------------------------------------------------------------------ neighbor list
+constexpr int kNlistRowCap = 256;   // most neighbors one atom may have
 struct NList {
   int32_t max_atoms = 0;
   int64_t max_pairs = 0;
@@ -63,6 +64,8 @@ struct NList {
   int32_t* rev = nullptr;    // [max_pairs]
   int32_t* cnt = nullptr;    // [max_atoms] padded row lengths
   uint32_t* flags = nullptr; // [1]
+  int32_t* len = nullptr;    // [max_atoms] real row lengths
+  int32_t* ell = nullptr;    // [max_atoms][kNlistRowCap] sorted rows before compaction
   // cell list scratch
   int32_t* cell_of = nullptr;    // [max_atoms]
   int32_t* cell_atoms = nullptr; // [max_atoms]
@@ -83,7 +86,7 @@ struct Model {
   // offsets (in floats) into params
   size_t o_WbT = 0, o_Td = 0, o_Ts = 0;                  // pair block, species tables
   size_t o_W1 = 0, o_W1T = 0, o_w2 = 0;                   // kind 0 readout
-  size_t o_W2bT = 0, o_T2pad = 0;                         // kind 1 second interaction
+  size_t o_W2bT = 0;                                      // kind 1 second interaction
   size_t o_U1T = 0, o_U1 = 0, o_U2T = 0, o_U2 = 0;        // kind 1 updates
   size_t o_W2hT = 0, o_W2hs = 0;                          // kind 1 h projections
   size_t o_WoT = 0, o_Wo = 0, o_wo = 0;                   // kind 1 readout

@@ -8,6 +8,17 @@
 //   kick:  v <- v + (tau * KAPPA / m) * F      (F = F_small, F_large or F_large - F_small)
 //   drift: x <- x + tau * v
 // KAPPA converts eV/(A amu) into A/fs^2.
+//
+// Neighbor lists.  Each reference-model evaluation builds one list at
+// r_list = max(r_c,large, r_c,small + 1 A) and records the positions it was built at.  The
+// fast model of the following inner steps runs on that same list: its kernels keep only
+// pairs within its own cutoff, and rows are sorted by sender, so the sums it takes are
+// exactly those of a list built at its cutoff.  The list is complete for the fast model as
+// long as no atom has moved more than (r_list - r_c,small)/2 since the build; every drift
+// launch checks that bound on the device.  If it is ever exceeded, the call is rolled back
+// to its starting state and repeated with a fresh list for every fast evaluation.
+#include <algorithm>
+
 #include "common.h"
 
 namespace dmts {
@@ -27,11 +38,14 @@ struct Prog {
   double c[kMaxOps];   // kicks: tau * KAPPA; drifts: tau
 };
 
+constexpr uint32_t kFlagStale = 0x100u;   // internal: shared list no longer complete
+constexpr double kMinSkin = 1.0;           // A between the fast cutoff and the shared list
+
 __global__ void __launch_bounds__(256)
 k_apply(Prog prog, int n, double* __restrict__ x, double* __restrict__ v,
         const float* __restrict__ FL, const float* __restrict__ Fs,
         const int32_t* __restrict__ species, const double* __restrict__ inv_mass,
-        uint32_t* __restrict__ flags) {
+        const double* __restrict__ x_ref, double max_disp2, uint32_t* __restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double im = inv_mass[species[i]];
@@ -68,14 +82,27 @@ k_apply(Prog prog, int n, double* __restrict__ x, double* __restrict__ v,
     v[(size_t)d * n + i] = vv[d];
     bad |= !isfinite(vv[d]);
   }
+  uint32_t f = 0;
   if (moved) {
+    double d2 = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       x[(size_t)d * n + i] = xx[d];
       bad |= !isfinite(xx[d]);
+      if (x_ref) {
+        const double u = xx[d] - x_ref[(size_t)d * n + i];
+        d2 += u * u;
+      }
     }
+    if (x_ref && !(d2 <= max_disp2)) f |= kFlagStale;
   }
-  if (bad) atomicOr(flags, DMTS_FLAG_NONFINITE);
+  if (bad) f |= DMTS_FLAG_NONFINITE;
+  if (f) atomicOr(flags, f);
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
 }
 
 // Kinetic energy sum(m v^2)/2 / KAPPA in eV (single work-group, fixed tree), then
@@ -130,6 +157,8 @@ struct State {
   NList* nl_large = nullptr;
   float* FL = nullptr;      // [3][n]
   float* Fs = nullptr;      // [3][n]
+  double* x_ref = nullptr;  // [3][n] positions of the last shared-list build
+  double* bak = nullptr;    // [6][n] x, v at the start of a call; then FL, Fs as [3][n] floats
   double* mass = nullptr;   // [Z]
   double* inv_mass = nullptr;
   double* e_models = nullptr;   // {E_large, E_small}
@@ -137,6 +166,7 @@ struct State {
   // models the carried forces belong to
   Model* last_small = nullptr;
   Model* last_large = nullptr;
+  int64_t n_fallbacks = 0;   // calls redone with exact lists
 };
 
 namespace {
@@ -147,12 +177,18 @@ struct Runner {
   double* v;
   hipStream_t s;
   Prog pending{};
+  // shared-list mode: the fast model runs on the reference model's list
+  bool shared = false;
+  double list_cut = 0.0;
+  double max_disp2 = 0.0;
 
   dmts_status flush() {
     if (pending.nops == 0) return DMTS_OK;
     ProfScope ps(DMTS_K_INTEGRATE, s);
     k_apply<<<ceil_div(st->n, 256), 256, 0, s>>>(pending, st->n, x, v, st->FL, st->Fs,
-                                                 st->species, st->inv_mass, st->flags);
+                                                 st->species, st->inv_mass,
+                                                 shared ? st->x_ref : nullptr, max_disp2,
+                                                 st->flags);
     DMTS_CHECK_LAUNCH();
     pending.nops = 0;
     return DMTS_OK;
@@ -174,7 +210,70 @@ struct Runner {
     if (r != DMTS_OK) return r;
     return energy_forces(m, nl, x, st->species, st->n, st->box, nullptr, 1, e, F, nullptr, s);
   }
+  // reference model: builds the list (at list_cut in shared mode) and records x_ref
+  dmts_status eval_large(Model* m) {
+    if (!shared) return eval(m, st->nl_large, st->FL, st->e_models);
+    dmts_status r = flush();
+    if (r != DMTS_OK) return r;
+    r = build_neighbors(st->nl_large, x, st->n, st->box, nullptr, 1, list_cut, s);
+    if (r != DMTS_OK) return r;
+    const int64_t n3 = 3 * (int64_t)st->n;
+    k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(x, st->x_ref, n3);
+    DMTS_CHECK_LAUNCH();
+    return energy_forces(m, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
+                         st->e_models, st->FL, nullptr, s);
+  }
+  dmts_status eval_small(Model* m) {
+    if (!shared) return eval(m, st->nl_small, st->Fs, st->e_models + 1);
+    dmts_status r = flush();
+    if (r != DMTS_OK) return r;
+    return energy_forces(m, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
+                         st->e_models + 1, st->Fs, nullptr, s);
+  }
 };
+
+// Algorithm 1 (or velocity Verlet when small is NULL) for n_outer outer steps.
+dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_outer) {
+  dmts_status r;
+  const double kappa = kKappa;
+  if (!small) {
+    // single-time-step baseline: velocity Verlet (BAOAB with the O-step off)
+    const double dt = st->dt;
+    if (st->first) {
+      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models)) != DMTS_OK) return r;
+      st->first = false;
+    }
+    for (int o = 0; o < n_outer; ++o) {
+      R.push(kKickLarge, 0.5 * dt * kappa);
+      R.push(kDrift, 0.5 * dt);
+      R.push(kDrift, 0.5 * dt);
+      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models)) != DMTS_OK) return r;
+      R.push(kKickLarge, 0.5 * dt * kappa);
+    }
+    return R.flush();
+  }
+  const double dt = st->dt;
+  const int n = st->n_inner;
+  const double h_in = dt / n;
+  if (st->first) {
+    if ((r = R.eval_large(large)) != DMTS_OK) return r;
+    if ((r = R.eval_small(small)) != DMTS_OK) return r;
+    st->first = false;
+  }
+  for (int o = 0; o < n_outer; ++o) {
+    R.push(kKickSlow, 0.5 * dt * kappa);
+    for (int k = 0; k < n; ++k) {
+      R.push(kKickFast, 0.5 * h_in * kappa);
+      R.push(kDrift, 0.5 * h_in);
+      R.push(kDrift, 0.5 * h_in);
+      if ((r = R.eval_small(small)) != DMTS_OK) return r;
+      R.push(kKickFast, 0.5 * h_in * kappa);
+    }
+    if ((r = R.eval_large(large)) != DMTS_OK) return r;
+    R.push(kKickSlow, 0.5 * dt * kappa);
+  }
+  return R.flush();
+}
 
 }  // namespace
 
@@ -222,6 +321,8 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
   if (r == DMTS_OK) {
     e = hipMalloc(&st->FL, sizeof(float) * 3 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->Fs, sizeof(float) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&st->x_ref, sizeof(double) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&st->bak, sizeof(double) * 9 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->mass, sizeof(double) * 16);
     if (e == hipSuccess) e = hipMalloc(&st->inv_mass, sizeof(double) * 16);
     if (e == hipSuccess) e = hipMalloc(&st->e_models, sizeof(double) * 4);
@@ -252,6 +353,8 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large));
   (void)hipFree(st->FL);
   (void)hipFree(st->Fs);
+  (void)hipFree(st->x_ref);
+  (void)hipFree(st->bak);
   (void)hipFree(st->mass);
   (void)hipFree(st->inv_mass);
   (void)hipFree(st->e_models);
@@ -263,6 +366,13 @@ extern "C" dmts_status dmts_state_reset(dmts_state* h) {
   State* st = reinterpret_cast<State*>(h);
   DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_reset: null state");
   st->first = true;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_fallbacks(dmts_state* h, int64_t* n_calls) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st && n_calls, DMTS_E_ARG, "dmts_state_fallbacks: null argument");
+  *n_calls = st->n_fallbacks;
   return DMTS_OK;
 }
 
@@ -307,46 +417,53 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
   st->last_large = large;
   dmts::Runner R{st, x, v, s};
   dmts_status r;
-  const double kappa = dmts::kKappa;
-  double* eL = st->e_models;
-  double* eS = st->e_models + 1;
-  if (!small) {
-    // single-time-step baseline: velocity Verlet (BAOAB with the O-step off)
-    const double dt = st->dt;
-    if (st->first) {
-      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
-      st->first = false;
-    }
-    for (int o = 0; o < n_outer; ++o) {
-      R.push(dmts::kKickLarge, 0.5 * dt * kappa);
-      R.push(dmts::kDrift, 0.5 * dt);
-      R.push(dmts::kDrift, 0.5 * dt);
-      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
-      R.push(dmts::kKickLarge, 0.5 * dt * kappa);
-    }
-  } else {
-    const double dt = st->dt;
-    const int n = st->n_inner;
-    const double h_in = dt / n;
-    if (st->first) {
-      if ((r = R.eval(small, st->nl_small, st->Fs, eS)) != DMTS_OK) return r;
-      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
-      st->first = false;
-    }
-    for (int o = 0; o < n_outer; ++o) {
-      R.push(dmts::kKickSlow, 0.5 * dt * kappa);
-      for (int k = 0; k < n; ++k) {
-        R.push(dmts::kKickFast, 0.5 * h_in * kappa);
-        R.push(dmts::kDrift, 0.5 * h_in);
-        R.push(dmts::kDrift, 0.5 * h_in);
-        if ((r = R.eval(small, st->nl_small, st->Fs, eS)) != DMTS_OK) return r;
-        R.push(dmts::kKickFast, 0.5 * h_in * kappa);
-      }
-      if ((r = R.eval(large, st->nl_large, st->FL, eL)) != DMTS_OK) return r;
-      R.push(dmts::kKickSlow, 0.5 * dt * kappa);
+  const int64_t n3 = 3 * (int64_t)st->n;
+  if (small) {
+    const double want = std::max((double)large->desc.cutoff,
+                                 (double)small->desc.cutoff + dmts::kMinSkin);
+    if (st->box == 0.0 || want < 0.5 * st->box) {
+      R.shared = true;
+      R.list_cut = want;
+      const double half_skin = 0.5 * (want - (double)small->desc.cutoff);
+      R.max_disp2 = half_skin * half_skin;
     }
   }
-  if ((r = R.flush()) != DMTS_OK) return r;
+  // starting state, for the rare roll-back of a shared-list call
+  const bool first0 = st->first;
+  if (R.shared) {
+    double* b = st->bak;
+    dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(x, b, n3);
+    dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(v, b + n3, n3);
+    if (!first0) {   // carried forces: 2 x 3n floats = 3n doubles
+      DMTS_HIP(hipMemcpyAsync(b + 2 * n3, st->FL, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+      DMTS_HIP(hipMemcpyAsync(reinterpret_cast<float*>(b + 2 * n3) + n3, st->Fs,
+                              sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+    }
+    DMTS_CHECK_LAUNCH();
+  }
+  if ((r = dmts::run_steps(st, R, small, large, n_outer)) != DMTS_OK) return r;
+  if (R.shared) {
+    uint32_t f = 0;
+    DMTS_HIP(hipMemcpyAsync(&f, st->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    DMTS_HIP(hipStreamSynchronize(s));
+    if (f & dmts::kFlagStale) {
+      // an atom moved beyond the shared list's skin: restore and redo with exact lists
+      double* b = st->bak;
+      dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(b, x, n3);
+      dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(b + n3, v, n3);
+      if (!first0) {
+        DMTS_HIP(hipMemcpyAsync(st->FL, b + 2 * n3, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+        DMTS_HIP(hipMemcpyAsync(st->Fs, reinterpret_cast<float*>(b + 2 * n3) + n3,
+                                sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+      }
+      DMTS_CHECK_LAUNCH();
+      st->first = first0;
+      if ((r = dmts::fill_u32(st->flags, f & ~dmts::kFlagStale, 1, s)) != DMTS_OK) return r;
+      dmts::Runner E{st, x, v, s};
+      ++st->n_fallbacks;
+      if ((r = dmts::run_steps(st, E, small, large, n_outer)) != DMTS_OK) return r;
+    }
+  }
   dmts::k_energies<<<1, 256, 0, s>>>(st->n, v, st->species, st->mass, st->e_models,
                                      energies_out, st->flags);
   DMTS_CHECK_LAUNCH();

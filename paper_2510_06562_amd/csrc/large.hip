@@ -19,7 +19,7 @@
 // pair geometry is staged in LDS 64 pairs at a time and recomputed in the reverse pass.
 // No floating-point atomics: every sum has a fixed order, so results are bitwise
 // reproducible.
-#include "gemm.h"
+#include "atom_mlp.h"
 
 namespace dmts {
 
@@ -395,23 +395,6 @@ k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nb
   RS[(size_t)i * 2 * F_L + F_L + lane + 64] = s1;
 }
 
-// E_i = s_E w_o . SiLU(y_i) and dy = s_E w_o * SiLU'(y).
-__global__ void __launch_bounds__(kWaves * 64)
-k_readout(const float* __restrict__ y, const float* __restrict__ wo, float escale, int n,
-          float* __restrict__ atom_e, float* __restrict__ dy) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * kWaves + w;
-  if (i >= n) return;
-  float s0, g0, s1, g1;
-  silu_and_grad(y[(size_t)i * F_L + lane], s0, g0);
-  silu_and_grad(y[(size_t)i * F_L + lane + 64], s1, g1);
-  const float w0 = wo[lane], w1 = wo[lane + 64];
-  const float e = wave_sum(w0 * s0 + w1 * s1) * escale;
-  dy[(size_t)i * F_L + lane] = escale * w0 * g0;
-  dy[(size_t)i * F_L + lane + 64] = escale * w1 * g1;
-  if (lane == 0) atom_e[i] = e;
-}
-
 }  // namespace
 
 // F_i = sum_{p in row i} v[p] - v[rev[p]]  (v[p] = dE/dd_ij, d_ij = x_j - x_i)
@@ -450,10 +433,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   // per-atom workspace layout (floats)
   const size_t o_q1 = 0, o_M1 = o_q1 + N * 3 * F, o_z1 = o_M1 + N * NMOM * F;
   const size_t o_h1 = o_z1 + N * F, o_P2 = o_h1 + N * F, o_q2 = o_P2 + N * 2 * F;
-  const size_t o_M2 = o_q2 + N * 3 * F, o_z2 = o_M2 + N * NMOM * F, o_h2 = o_z2 + N * F;
-  const size_t o_y = o_h2 + N * F, o_dy = o_y + N * F, o_dh2 = o_dy + N * F;
-  const size_t o_dz2 = o_dh2 + N * F, o_dq2 = o_dz2 + N * F, o_RS = o_dq2 + N * 3 * F;
-  const size_t o_dz1 = o_RS + N * 2 * F, o_dq1 = o_dz1 + N * F, o_e = o_dq1 + N * 3 * F;
+  const size_t o_M2 = o_q2 + N * 3 * F, o_dh2 = o_M2 + N * NMOM * F;
+  const size_t o_dq2 = o_dh2 + N * F, o_RS = o_dq2 + N * 3 * F;
+  const size_t o_dq1 = o_RS + N * 2 * F, o_e = o_dq1 + N * 3 * F;
   const size_t total = o_e + N;
   DMTS_REQUIRE(m->atom_ws.reserve(total * sizeof(float), s) == DMTS_OK, DMTS_E_OOM,
                "large model: atom workspace");
@@ -466,44 +448,26 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   float* e_atom = atom_energy ? atom_energy : W + o_e;
   LargeParams P1{m->p(m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts), m->rc, m->sigma, m->Z};
   LargeParams P2{m->p(m->o_W2bT), nullptr, nullptr, m->rc, m->sigma, m->Z};
+  AtomMlpParams A{m->p(m->o_U1T), m->p(m->o_W2hT), m->p(m->o_U2T), m->p(m->o_WoT),
+                  m->p(m->o_wo),  m->p(m->o_Wo),   m->p(m->o_U2),  m->p(m->o_W2hs),
+                  m->p(m->o_U1)};
   const int blocks = ceil_div(n, kWaves);
-  const int ld3 = 3 * F_L;
   dmts_status st;
   if (n > 0) {
     { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
     k_pair_forward<1><<<blocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, pos, species, n, box,
                                                      nullptr, W + o_M1, W + o_q1); }
     DMTS_CHECK_LAUNCH();
-    GemmAux ax;
-    ax.out = W + o_h1;
-    if ((st = gemm_f32(kEpiSilu, n, F_L, ld3, W + o_q1, ld3, m->p(m->o_U1T), F_L, W + o_z1, F_L,
-                       ax, s)) != DMTS_OK) return st;
-    if ((st = gemm_f32(kEpiStore, n, 2 * F_L, F_L, W + o_h1, F_L, m->p(m->o_W2hT), 2 * F_L,
-                       W + o_P2, 2 * F_L, GemmAux{}, s)) != DMTS_OK) return st;
+    if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
     { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
     k_pair_forward<2><<<blocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, pos, species, n, box,
                                                      W + o_P2, W + o_M2, W + o_q2); }
     DMTS_CHECK_LAUNCH();
-    ax = GemmAux{};
-    ax.out = W + o_h2;
-    ax.in0 = W + o_h1;
-    if ((st = gemm_f32(kEpiResidSilu, n, F_L, ld3, W + o_q2, ld3, m->p(m->o_U2T), F_L, W + o_z2,
-                       F_L, ax, s)) != DMTS_OK) return st;
-    if ((st = gemm_f32(kEpiStore, n, F_L, F_L, W + o_h2, F_L, m->p(m->o_WoT), F_L, W + o_y, F_L,
-                       GemmAux{}, s)) != DMTS_OK) return st;
-    k_readout<<<blocks, kWaves * 64, 0, s>>>(W + o_y, m->p(m->o_wo), m->escale, n, e_atom,
-                                             W + o_dy);
-    DMTS_CHECK_LAUNCH();
+    if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
+                          forces != nullptr, s)) != DMTS_OK) return st;
     if (forces) {
       float* dA = m->pair_ws.as<float>();
       float* v = dA + (size_t)cap * F;
-      ax = GemmAux{};
-      ax.out = W + o_dz2;
-      ax.in0 = W + o_z2;
-      if ((st = gemm_f32(kEpiDsilu, n, F_L, F_L, W + o_dy, F_L, m->p(m->o_Wo), F_L, W + o_dh2,
-                         F_L, ax, s)) != DMTS_OK) return st;
-      if ((st = gemm_f32(kEpiStore, n, ld3, F_L, W + o_dz2, F_L, m->p(m->o_U2), ld3, W + o_dq2,
-                         ld3, GemmAux{}, s)) != DMTS_OK) return st;
       { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
       k_pair_backward<2><<<blocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, pos, species, n,
                                                         box, W + o_P2, W + o_M2, W + o_dq2, dA,
@@ -512,14 +476,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       { ProfScope ps(DMTS_K_GATHER, s);
       k_sender_gather<<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, dA, W + o_RS); }
       DMTS_CHECK_LAUNCH();
-      ax = GemmAux{};
-      ax.out = W + o_dz1;
-      ax.in0 = W + o_z1;
-      ax.in1 = W + o_dh2;
-      if ((st = gemm_f32(kEpiResidDsilu, n, F_L, 2 * F_L, W + o_RS, 2 * F_L, m->p(m->o_W2hs), F_L,
-                         nullptr, F_L, ax, s)) != DMTS_OK) return st;
-      if ((st = gemm_f32(kEpiStore, n, ld3, F_L, W + o_dz1, F_L, m->p(m->o_U1), ld3, W + o_dq1,
-                         ld3, GemmAux{}, s)) != DMTS_OK) return st;
+      if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
+        return st;
       { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
       k_pair_backward<1><<<blocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, pos, species, n,
                                                         box, nullptr, W + o_M1, W + o_dq1, nullptr,

@@ -4,11 +4,16 @@
 // minimum-image convention of a cube (plain difference for open boundaries, restricted
 // to one molecule for a batch).  The paper leaves the search unspecified; this is a
 // cell list: atoms are binned into cells of edge >= r_c, each receiver scans the 27
-// surrounding cells.  Every receiver is handled by one wavefront whose lanes walk the
-// candidate stream of those cells; a ballot compacts the accepted senders, so each row
-// comes out in candidate order (stencil order, then ascending atom index inside a cell)
-// and the whole list is bitwise reproducible.  Rows are padded with -1 to a multiple of
-// the list's row alignment.  rev[p] locates the reverse pair of every real entry.
+// surrounding cells (all atoms of its molecule, or all atoms, when there are fewer than 3
+// cells per edge).  One wavefront per receiver walks the candidate stream; a ballot
+// compacts the accepted senders into LDS, where they are rank-sorted by index.  Rows are
+// therefore ascending in j whatever order the binning produced, so the list, and every
+// floating-point sum taken along it, is bitwise reproducible.
+//
+// Launches per build: bin (cell id + count), scan of cells, scatter, rows (search + sort
+// into a fixed-width staging table), scan of row lengths, compaction into CSR with the
+// reverse index rev[p] (binary search of i in the sorted row of j).  Rows are padded with
+// -1 to a multiple of the list's row alignment.
 #include "common.h"
 
 namespace dmts {
@@ -26,11 +31,14 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
 // Exclusive scan of in[0..n) into out[0..n]; single work-group.  When the total exceeds
 // `cap` the list would not fit: every offset is set to 0 (all rows empty) and the
 // overflow flag is raised, so no consumer can index past the capacity.
-__global__ void __launch_bounds__(kScanThreads) k_scan(const int32_t* __restrict__ in,
+// With `zero_in`, the input is cleared after it has been read (the cell counters are then
+// ready for the next build without a separate fill).
+__global__ void __launch_bounds__(kScanThreads) k_scan(int32_t* __restrict__ in,
                                                       int32_t* __restrict__ out,
                                                       int32_t* __restrict__ copy_to,
                                                       int32_t n, int64_t cap,
-                                                      uint32_t* __restrict__ flags) {
+                                                      uint32_t* __restrict__ flags,
+                                                      bool zero_in) {
   __shared__ int64_t part[kScanThreads];
   __shared__ int64_t total_s;
   const int t = threadIdx.x;
@@ -57,6 +65,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(const int32_t* __restrict
     out[k] = o;
     if (copy_to) copy_to[k] = o;
     run += in[k];
+    if (zero_in) in[k] = 0;
   }
   if (t == 0) {
     out[n] = overflow ? 0 : static_cast<int32_t>(total);
@@ -90,24 +99,6 @@ __global__ void k_cell_scatter(const int32_t* __restrict__ cell_of, int32_t n,
   if (i >= n) return;
   int slot = atomicAdd(&cursor[cell_of[i]], 1);
   cell_atoms[slot] = i;
-}
-
-// Members of each cell in ascending atom order (undoes the arbitrary order of the
-// atomic scatter).
-__global__ void k_cell_sort(const int32_t* __restrict__ cell_start, int32_t n_cells,
-                            int32_t* __restrict__ cell_atoms) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  const int lo = cell_start[c], hi = cell_start[c + 1];
-  for (int a = lo + 1; a < hi; ++a) {
-    int v = cell_atoms[a];
-    int b = a - 1;
-    while (b >= lo && cell_atoms[b] > v) {
-      cell_atoms[b + 1] = cell_atoms[b];
-      --b;
-    }
-    cell_atoms[b + 1] = v;
-  }
 }
 
 struct Geo {
@@ -203,76 +194,79 @@ __device__ __forceinline__ void molecule_range(const int32_t* sys_offsets, int32
 }
 
 constexpr int kNbWaves = 4;
+constexpr int kRowCap = kNlistRowCap;
 
+// Search + sort of one receiver's row into ell[i][0 .. kRowCap); the row length goes to
+// len[i] and, padded to `align`, to cnt[i].  A row longer than kRowCap raises the
+// overflow flag and is cut.
 template <bool kCells>
 __global__ void __launch_bounds__(kNbWaves * 64)
-k_count(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys,
-        int32_t align, int32_t* __restrict__ cnt) {
+k_rows(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys,
+       int32_t align, int32_t* __restrict__ ell, int32_t* __restrict__ len,
+       int32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
   __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
-  const int w = threadIdx.x >> 6;
+  __shared__ int32_t s_row[kNbWaves][kRowCap];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNbWaves + w;
   if (i >= g.n) return;
-  const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
-  int lo = 0, hi = 0;
-  if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
-  int total = 0;
-  walk_candidates<kCells>(i, lo, hi, cc, s_pref[w], s_first[w], [&](int j, bool ok) {
-    bool acc = ok && within(g, xi, yi, zi, j);
-    total += __popcll(__ballot(acc));
-  });
-  if ((threadIdx.x & 63) == 0) cnt[i] = (total + align - 1) / align * align;
-}
-
-template <bool kCells>
-__global__ void __launch_bounds__(kNbWaves * 64)
-k_fill(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys,
-       const int32_t* __restrict__ offs, int32_t* __restrict__ nbr) {
-  __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
-  const int w = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * kNbWaves + w;
-  if (i >= g.n) return;
-  const int row0 = offs[i], row1 = offs[i + 1];
-  if (row1 == row0) return;  // empty row, or the list overflowed (all offsets zero)
   const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
   int lo = 0, hi = 0;
   if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
   int run = 0;
+  int32_t* row = s_row[w];
   walk_candidates<kCells>(i, lo, hi, cc, s_pref[w], s_first[w], [&](int j, bool ok) {
     bool acc = ok && within(g, xi, yi, zi, j);
     uint64_t mask = __ballot(acc);
-    int before = __popcll(mask & ((1ull << lane) - 1ull));
-    int p = row0 + run + before;
-    if (acc && p < row1) nbr[p] = j;
+    int p = run + __popcll(mask & ((1ull << lane) - 1ull));
+    if (acc && p < kRowCap) row[p] = j;
     run += __popcll(mask);
   });
-  for (int p = row0 + run + lane; p < row1; p += 64) nbr[p] = -1;
+  if (run > kRowCap) {
+    if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+    run = kRowCap;
+  }
+  wave_sync();
+  // rank sort (senders are distinct): rank = number of smaller entries
+  int32_t* out = ell + (size_t)i * kRowCap;
+  for (int e = lane; e < run; e += 64) {
+    const int v = row[e];
+    int rank = 0;
+    for (int k = 0; k < run; ++k) rank += row[k] < v;
+    out[rank] = v;
+  }
+  if (lane == 0) {
+    len[i] = run;
+    cnt[i] = (run + align - 1) / align * align;
+  }
 }
 
-// rev[p] for p = (i, j): position of i in row j (rows are at least 4-aligned).
+// CSR rows (padded with -1) from the staging table, and the reverse index:
+// rev[p] for p = (i, j) is offs[j] + (position of i in the sorted row of j).
 __global__ void __launch_bounds__(kNbWaves * 64)
-k_rev(int32_t n, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-      int32_t* __restrict__ rev) {
-  const int w = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+k_compact(int32_t n, const int32_t* __restrict__ ell, const int32_t* __restrict__ len,
+          const int32_t* __restrict__ offs, int32_t* __restrict__ nbr,
+          int32_t* __restrict__ rev) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNbWaves + w;
   if (i >= n) return;
   const int row0 = offs[i], row1 = offs[i + 1];
-  for (int p = row0 + lane; p < row1; p += 64) {
-    int j = nbr[p];
-    int found = -1;
+  if (row1 == row0) return;   // empty row, or the list overflowed (all offsets zero)
+  const int li = len[i];
+  const int32_t* src = ell + (size_t)i * kRowCap;
+  for (int k = lane; k < row1 - row0; k += 64) {
+    int j = k < li ? src[k] : -1;
+    int r = -1;
     if (j >= 0) {
-      const int q0 = offs[j], q1 = offs[j + 1];
-      for (int q = q0; q < q1 && found < 0; q += 4) {
-        int4 v = *reinterpret_cast<const int4*>(nbr + q);
-        if (v.x == i) found = q;
-        else if (v.y == i) found = q + 1;
-        else if (v.z == i) found = q + 2;
-        else if (v.w == i) found = q + 3;
-        else if (v.w < 0) break;
+      const int32_t* rj = ell + (size_t)j * kRowCap;
+      int a = 0, b = len[j];        // lower bound of i in rj[0 .. len_j)
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (rj[mid] < i) a = mid + 1; else b = mid;
       }
+      r = (a < len[j] && rj[a] == i) ? offs[j] + a : -1;
     }
-    rev[p] = found;
+    nbr[row0 + k] = j;
+    rev[row0 + k] = r;
   }
 }
 
@@ -313,40 +307,40 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
   if (cells) {
     nc = nc > kMaxCellsPerDim ? kMaxCellsPerDim : nc;
     const int n_cells = nc * nc * nc;
-    DMTS_REQUIRE(nl->cell_buf.reserve(sizeof(int32_t) * (3 * (size_t)n_cells + 2), s) == DMTS_OK,
-                 DMTS_E_OOM, "build_neighbors: cell buffer allocation failed");
+    if (n_cells > nl->n_cells_cap) {
+      DMTS_REQUIRE(nl->cell_buf.reserve(sizeof(int32_t) * (3 * (size_t)n_cells + 2), s) == DMTS_OK,
+                   DMTS_E_OOM, "build_neighbors: cell buffer allocation failed");
+      // counters start at zero; every scan clears them again after reading
+      dmts_status st = fill_u32(nl->cell_buf.as<uint32_t>(), 0u, n_cells, s);
+      if (st != DMTS_OK) return st;
+      nl->n_cells_cap = n_cells;
+    }
     int32_t* cell_count = nl->cell_buf.as<int32_t>();
-    int32_t* cell_start = cell_count + n_cells;
-    int32_t* cursor = cell_start + n_cells + 1;
-    dmts_status st = fill_u32(reinterpret_cast<uint32_t*>(cell_count), 0u, n_cells, s);
-    if (st != DMTS_OK) return st;
+    int32_t* cell_start = cell_count + nl->n_cells_cap;
+    int32_t* cursor = cell_start + nl->n_cells_cap + 1;
     const double inv_cell = nc / box;
     k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
                                                    cell_count);
     DMTS_CHECK_LAUNCH();
     k_scan<<<1, kScanThreads, 0, s>>>(cell_count, cell_start, cursor, n_cells, INT64_MAX,
-                                      nullptr);
+                                      nullptr, true);
     DMTS_CHECK_LAUNCH();
     k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms);
-    DMTS_CHECK_LAUNCH();
-    k_cell_sort<<<ceil_div(n_cells, 128), 128, 0, s>>>(cell_start, n_cells, nl->cell_atoms);
     DMTS_CHECK_LAUNCH();
     cc = CellCtx{cell_start, nl->cell_atoms, nl->cell_of, nc};
   }
   const int blocks = ceil_div(n, kNbWaves);
   if (cells)
-    k_count<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align, nl->cnt);
+    k_rows<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align,
+                                                   nl->ell, nl->len, nl->cnt, nl->flags);
   else
-    k_count<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align, nl->cnt);
+    k_rows<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align,
+                                                    nl->ell, nl->len, nl->cnt, nl->flags);
   DMTS_CHECK_LAUNCH();
-  k_scan<<<1, kScanThreads, 0, s>>>(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags);
+  k_scan<<<1, kScanThreads, 0, s>>>(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags,
+                                    false);
   DMTS_CHECK_LAUNCH();
-  if (cells)
-    k_fill<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->offs, nl->nbr);
-  else
-    k_fill<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->offs, nl->nbr);
-  DMTS_CHECK_LAUNCH();
-  k_rev<<<blocks, kNbWaves * 64, 0, s>>>(n, nl->offs, nl->nbr, nl->rev);
+  k_compact<<<blocks, kNbWaves * 64, 0, s>>>(n, nl->ell, nl->len, nl->offs, nl->nbr, nl->rev);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
@@ -375,6 +369,8 @@ extern "C" dmts_status nnp_nlist_create(int32_t max_atoms, int64_t max_pairs,
   e = e == hipSuccess ? hipMalloc(&nl->cnt, sizeof(int32_t) * a) : e;
   e = e == hipSuccess ? hipMalloc(&nl->cell_of, sizeof(int32_t) * a) : e;
   e = e == hipSuccess ? hipMalloc(&nl->cell_atoms, sizeof(int32_t) * a) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->len, sizeof(int32_t) * a) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->ell, sizeof(int32_t) * a * dmts::kNlistRowCap) : e;
   e = e == hipSuccess ? hipMalloc(&nl->nbr, sizeof(int32_t) * nl->max_pairs) : e;
   e = e == hipSuccess ? hipMalloc(&nl->rev, sizeof(int32_t) * nl->max_pairs) : e;
   e = e == hipSuccess ? hipMalloc(&nl->flags, sizeof(uint32_t)) : e;
@@ -398,6 +394,8 @@ extern "C" void nnp_nlist_destroy(nnp_nlist* h) {
   (void)hipFree(nl->cnt);
   (void)hipFree(nl->cell_of);
   (void)hipFree(nl->cell_atoms);
+  (void)hipFree(nl->len);
+  (void)hipFree(nl->ell);
   (void)hipFree(nl->nbr);
   (void)hipFree(nl->rev);
   (void)hipFree(nl->flags);

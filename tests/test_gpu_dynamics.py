@@ -68,6 +68,26 @@ def test_dmts_matches_oracle_algorithm1_water192(models):
     assert e[0] == pytest.approx(o.E, abs=1e-6) and e[1] == pytest.approx(o.E_small, abs=1e-6)
 
 
+def test_fast_atom_triggers_exact_fallback(models):
+    """An atom fast enough to leave the shared list's skin within one call: the call is
+    redone with exact lists and still follows Algorithm 1 of the oracle."""
+    say("shared-list fallback")
+    sy = system("water192")
+    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 200)
+    v0[7] = [0.35, 0.0, 0.0]          # 1.4 A per 4 fs outer step (skin half-width 0.85 A)
+    st, _ = _state(sy, 4.0, 4)
+    x, v = api.to_soa(sy.pos), api.to_soa(v0)
+    st.step(x, v, models["small"], models["large"], 1)
+    assert st.fallbacks == 1
+    o = OI.MTSState(x=sy.pos.copy(), v=v0.copy(), m=sy.masses())
+    OI.mts_step(o, 4.0, 4, _oracle_force("small", sy), _oracle_force("large", sy))
+    assert np.max(np.abs(api.from_soa(x) - o.x)) < 1e-7
+    # a normal call afterwards stays on the shared list
+    v[:, 7] = 0.0
+    st.step(x, v, models["small"], models["large"], 1)
+    assert st.fallbacks == 1
+
+
 def test_respa_collapses_bitwise_to_verlet(models):
     """F - F_small is exactly zero when both levels are one model, so Algorithm 1 with
     n inner steps is n velocity-Verlet steps of dt/n, bit for bit."""

@@ -63,6 +63,11 @@ def test_neighbor_set_matches_oracle(sysname, cut):
         row = nbr[offs[a]:offs[a + 1]]
         k = int(np.sum(row >= 0))
         assert np.all(row[:k] >= 0) and np.all(row[k:] == -1) and len(row) - k < 4
+    # rows ascend in the sender index
+    for a in range(sy.n_atoms):
+        row = nbr[offs[a]:offs[a + 1]]
+        row = row[row >= 0]
+        assert np.all(np.diff(row) > 0)
     p = np.nonzero(real)[0]
     assert np.all(nbr[rev[p]] == rows[p])
     assert np.all(rows[rev[p]] == nbr[p])
