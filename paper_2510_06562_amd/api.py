@@ -256,7 +256,7 @@ class Potential:
         self.model = model
         self.box = box
         self.sys_offsets = sys_offsets
-        self.nlist = NeighborList(max_atoms, max_atoms * (max_nbrs + 4), 4)
+        self.nlist = NeighborList(max_atoms, max_atoms * (max_nbrs + 16), 16)
 
     def __call__(self, pos_soa: torch.Tensor, species: torch.Tensor, want_forces=True,
                  atom_energy=False, stream=None):

@@ -62,6 +62,7 @@ struct NList {
   int32_t* offs = nullptr;   // [max_atoms + 1]
   int32_t* nbr = nullptr;    // [max_pairs]
   int32_t* rev = nullptr;    // [max_pairs]
+  float4* geo = nullptr;     // [max_pairs] (dx, dy, dz, r) at the build positions
   int32_t* cnt = nullptr;    // [max_atoms] padded row lengths
   uint32_t* flags = nullptr; // [1]
   int32_t* len = nullptr;    // [max_atoms] real row lengths

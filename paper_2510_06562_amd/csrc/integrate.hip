@@ -310,7 +310,7 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
   dmts_status r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_small + 4), 4,
                                    reinterpret_cast<nnp_nlist**>(&st->nl_small));
   if (r == DMTS_OK)
-    r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 4), 4,
+    r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 16), 16,
                          reinterpret_cast<nnp_nlist**>(&st->nl_large));
   double hm[16] = {0}, him[16] = {0};
   for (int z = 0; z < n_species; ++z) {

@@ -10,13 +10,13 @@
 // E_i = s_E w_o . SiLU(W_o h^2).
 //
 // Kernel sequence (forward, then the reverse pass):
-//   pair1F -> GEMM U1 (+SiLU) -> GEMM [A|B] -> pair2F -> GEMM U2 (+residual SiLU)
-//   -> GEMM W_o -> readout (E_i, dy) -> GEMM W_o^T (+SiLU') -> GEMM U2^T
-//   -> pair2B (stores dE/da_ij per pair for the sender sums, v_ij = dE/dd_ij, and the
-//      receiver sums) -> sender gather through rev[] -> GEMM [B;A]^T (+residual, SiLU')
-//   -> GEMM U1^T -> pair1B (adds its v_ij) -> force gather F_i = sum_j v_ij - v_ji.
-// The pair kernels run one wavefront per receiver, channels on lanes (two per lane);
-// pair geometry is staged in LDS 64 pairs at a time and recomputed in the reverse pass.
+//   pair 1 forward -> atom chain 1 (U1, SiLU, [A|B] projections) -> pair 2 forward
+//   -> atom chain 2 (U2, residual, readout, E_i, and its reverse down to dE/dq^2)
+//   -> pair 2 reverse (dE/da_ij per pair kept for the sender sums, v_ij = dE/dd_ij, the
+//      receiver sums) -> sender gather through rev[] -> atom chain 3 (dE/dh^1 down to
+//      dE/dq^1) -> pair 1 reverse (adds its v_ij) -> force gather F_i = sum_j v_ij - v_ji.
+// The pair kernels recompute every pair feature from the list's geometry; only dE/da of
+// interaction 2 is stored per pair, because the sender sums need it in the other row.
 // No floating-point atomics: every sum has a fixed order, so results are bitwise
 // reproducible.
 #include "atom_mlp.h"
@@ -26,6 +26,7 @@ namespace dmts {
 namespace {
 
 constexpr int kWaves = 4;
+constexpr int kAtomsPerWg = 2;   // pair kernels: two waves (channel halves) per receiver
 constexpr int K_L = 32;
 constexpr int F_L = 128;
 constexpr int Z_MAX = 8;
@@ -39,338 +40,344 @@ struct LargeParams {
   int Z;
 };
 
-struct Stage {
-  float b[64][K_L];
-  float db[64][K_L];
-  float fc[64], dfc[64];
-  float ux[64], uy[64], uz[64];       // d / r_c
-  float rx[64], ry[64], rz[64];       // d / r
-  int z[64], j[64];
-};
+// ------------------------------------------------------------------ MFMA pair kernels
+// One wavefront per receiver, 16-pair row tiles (rows are padded to 16).  Pair geometry
+// (d, r) comes from the neighbor list, which is built at the evaluation's positions.
+// Lane l has group g = l / 16 and column cl = l % 16; v_mfma_f32_16x16x4f32 layout:
+//   A operand: A[cl][k0 + g], B operand: B[k0 + g][cl], D register r: D[4 g + r][cl].
+//
+// Forward: a = b W_b as D[pair][channel] (pair 4g + r, channel 16 blk + cl).  The moments
+// M^T[y][c] = sum_p Y[p][y] m[p][c] then use that accumulator as their B operand: in step
+// s the K index g stands for pair 4g + s, i.e. register s of the lane.
+// Reverse pass: the transposed product a^T = W_b b^T as D[channel][pair] (channel
+// 16 blk + 4g + r, pair cl): each lane owns one pair and 32 channels, so the channel sums
+// of a pair are in-lane plus two cross-group shuffles; dm^T = D_i^T Y^T likewise.
 
-__device__ __forceinline__ void stage_pair(Stage& st, int lane, int p, int row1,
-                                           const int32_t* nbr, const double* pos, int n,
-                                           double box, double inv_box, double xi, double yi,
-                                           double zi, const int32_t* species,
-                                           const LargeParams& P, bool need_grad) {
-  int j = p < row1 ? nbr[p] : -1;
-  float r = 0.f, fc = 0.f, dfc = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
-  bool valid = false;
-  if (j >= 0) {
-    dx = static_cast<float>(minimage(pos[j] - xi, box, inv_box));
-    dy = static_cast<float>(minimage(pos[n + j] - yi, box, inv_box));
-    dz = static_cast<float>(minimage(pos[2 * n + j] - zi, box, inv_box));
-    r = sqrtf(dx * dx + dy * dy + dz * dz);
-    valid = r < P.rc;
-    if (valid) {
-      float sn, cs;
-      __sincosf(3.14159265358979f * r / P.rc, &sn, &cs);
-      fc = 0.5f * (cs + 1.0f);
-      dfc = -0.5f * 3.14159265358979f / P.rc * sn;
-    }
-  }
-  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
-#pragma unroll
-  for (int k = 0; k < K_L; ++k) {
-    float x = r - P.sigma * k;
-    float bk = valid ? __expf(-0.5f * x * x * inv_s2) : 0.f;
-    st.b[lane][k] = bk;
-    if (need_grad) st.db[lane][k] = -x * inv_s2 * bk;
-  }
-  const float irc = 1.0f / P.rc;
-  const float ir = valid ? 1.0f / r : 0.f;
-  st.fc[lane] = fc;
-  st.dfc[lane] = dfc;
-  st.ux[lane] = valid ? dx * irc : 0.f;
-  st.uy[lane] = valid ? dy * irc : 0.f;
-  st.uz[lane] = valid ? dz * irc : 0.f;
-  st.rx[lane] = dx * ir;
-  st.ry[lane] = dy * ir;
-  st.rz[lane] = dz * ir;
-  st.j[lane] = valid ? j : -1;
-  st.z[lane] = valid ? species[j] : 0;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 16;
+constexpr int kLdW = 144;   // LDS stride of W_b^T rows [k][c]
+constexpr int kLdT = 36;    // LDS stride of W_b rows [c][k]
+constexpr int kLdH = 80;    // LDS stride of per-half rows (64 channels)
+
+// Y = [1, u, u u^T - |u|^2/3 (xx, yy, zz), xy, xz, yz], zero beyond the ten components.
+__device__ __forceinline__ float ycomp(int y, float ux, float uy, float uz) {
+  const float t3 = (ux * ux + uy * uy + uz * uz) * (1.0f / 3.0f);
+  float v = 0.f;
+  v = y == 0 ? 1.0f : v;
+  v = y == 1 ? ux : v;
+  v = y == 2 ? uy : v;
+  v = y == 3 ? uz : v;
+  v = y == 4 ? ux * ux - t3 : v;
+  v = y == 5 ? uy * uy - t3 : v;
+  v = y == 6 ? uz * uz - t3 : v;
+  v = y == 7 ? ux * uy : v;
+  v = y == 8 ? ux * uz : v;
+  v = y == 9 ? uy * uz : v;
+  return v;
 }
 
-// Moments of one channel.
-struct Mom {
-  float m0, x, y, z, xx, yy, zz, xy, xz, yz;
-  __device__ void zero() { m0 = x = y = z = xx = yy = zz = xy = xz = yz = 0.f; }
-};
-
-__device__ __forceinline__ void accumulate(Mom& M, float m, float ux, float uy, float uz,
-                                           float u2) {
-  const float t3 = u2 * (1.0f / 3.0f);
-  M.m0 += m;
-  M.x = fmaf(m, ux, M.x);
-  M.y = fmaf(m, uy, M.y);
-  M.z = fmaf(m, uz, M.z);
-  M.xx = fmaf(m, ux * ux - t3, M.xx);
-  M.yy = fmaf(m, uy * uy - t3, M.yy);
-  M.zz = fmaf(m, uz * uz - t3, M.zz);
-  M.xy = fmaf(m, ux * uy, M.xy);
-  M.xz = fmaf(m, ux * uz, M.xz);
-  M.yz = fmaf(m, uy * uz, M.yz);
+// Sum over the 16 lanes of a DPP row; every lane gets the same bits.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+  return v;
 }
 
-__device__ __forceinline__ void store_moments(const Mom& M, float* Mout, float* q, int c) {
-  Mout[0 * F_L + c] = M.m0;
-  Mout[1 * F_L + c] = M.x;
-  Mout[2 * F_L + c] = M.y;
-  Mout[3 * F_L + c] = M.z;
-  Mout[4 * F_L + c] = M.xx;
-  Mout[5 * F_L + c] = M.yy;
-  Mout[6 * F_L + c] = M.zz;
-  Mout[7 * F_L + c] = M.xy;
-  Mout[8 * F_L + c] = M.xz;
-  Mout[9 * F_L + c] = M.yz;
-  q[c] = M.m0;
-  q[F_L + c] = M.x * M.x + M.y * M.y + M.z * M.z;
-  q[2 * F_L + c] = M.xx * M.xx + M.yy * M.yy + M.zz * M.zz +
-                   2.0f * (M.xy * M.xy + M.xz * M.xz + M.yz * M.yz);
+// Cosine cutoff and its derivative (zero outside).
+__device__ __forceinline__ void cutoff_fn(float r, float rc, bool valid, float& fc, float& dfc) {
+  float sn, cs;
+  __sincosf(3.14159265358979f * r / rc, &sn, &cs);
+  fc = valid ? 0.5f * (cs + 1.0f) : 0.f;
+  dfc = valid ? -0.5f * 3.14159265358979f / rc * sn : 0.f;
 }
 
-// LAYER 1: species tables; LAYER 2: per-atom projections P2 = [A | B] (sender | receiver).
 template <int LAYER>
 __global__ void __launch_bounds__(kWaves * 64)
-k_pair_forward(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-               const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
-               double box, const float* __restrict__ P2, float* __restrict__ Mout,
-               float* __restrict__ q) {
-  __shared__ Stage stage[kWaves];
-  __shared__ float s_Ts[LAYER == 1 ? Z_MAX : 1][F_L];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
+                const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
+                const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
+  __shared__ float sW[K_L * kLdW];
+  __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
+  __shared__ float sM[kWaves][NMOM * kLdW];
+  for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
+    sW[(e / F_L) * kLdW + e % F_L] = P.WbT[e];
   if (LAYER == 1)
-    for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) s_Ts[e / F_L][e % F_L] = P.Ts[e];
+    for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
-  const int i = blockIdx.x * kWaves + w;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int i = blockIdx.x * kAtomsPerWg + (w >> 1);
+  const int hb = 4 * (w & 1);   // first channel block of this wave's half
   if (i >= n) return;
-  Stage& st = stage[w];
-  const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
-  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-  const int c0 = lane, c1 = lane + 64;
-  float wb0[K_L], wb1[K_L];
+  const int zi_s = species[i];
+  float base[4];
 #pragma unroll
-  for (int k = 0; k < K_L; ++k) {
-    wb0[k] = P.WbT[k * F_L + c0];
-    wb1[k] = P.WbT[k * F_L + c1];
-  }
-  float base0, base1;
-  if (LAYER == 1) {
-    base0 = P.Td[species[i] * F_L + c0];
-    base1 = P.Td[species[i] * F_L + c1];
-  } else {
-    base0 = P2[(size_t)i * 2 * F_L + F_L + c0];
-    base1 = P2[(size_t)i * 2 * F_L + F_L + c1];
-  }
-  Mom A, B;
-  A.zero();
-  B.zero();
+  for (int b = 0; b < 4; ++b)
+    base[b] = LAYER == 1 ? P.Td[zi_s * F_L + 16 * (hb + b) + cl]
+                         : P2[(size_t)i * 2 * F_L + F_L + 16 * (hb + b) + cl];
+  f32x4 Mt[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) Mt[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
+  const float irc = 1.0f / P.rc;
   const int row0 = offs[i], row1 = offs[i + 1];
-  for (int base = row0; base < row1; base += 64) {
-    stage_pair(st, lane, base + lane, row1, nbr, pos, n, box, inv_box, xi, yi, zi, species, P,
-               false);
-    wave_sync();
-    const int nq = min(64, row1 - base);
-    for (int q0 = 0; q0 < nq; ++q0) {
-      const int j = st.j[q0];
-      if (j < 0) continue;
-      float a0, a1;
-      if (LAYER == 1) {
-        a0 = base0 + s_Ts[st.z[q0]][c0];
-        a1 = base1 + s_Ts[st.z[q0]][c1];
-      } else {
-        a0 = base0 + P2[(size_t)j * 2 * F_L + c0];
-        a1 = base1 + P2[(size_t)j * 2 * F_L + c1];
+  for (int t0 = row0; t0 < row1; t0 += kTile) {
+    // A operand of a = b W_b: b_k of pair cl at k = 4 s + g
+    const float rp = geo[t0 + cl].w;
+    const bool vp = nbr[t0 + cl] >= 0 && rp < P.rc;
+    float bop[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const float x = rp - P.sigma * (4 * s + g);
+      bop[s] = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+    }
+    // the lane's four pairs of the D layout: 4 g + r
+    float fc[4], yop[4];
+    int jj[4], zz[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = t0 + 4 * g + r;
+      const float4 gv = geo[p];
+      const int j = nbr[p];
+      const bool v = j >= 0 && gv.w < P.rc;
+      float dfc;
+      cutoff_fn(gv.w, P.rc, v, fc[r], dfc);
+      jj[r] = v ? j : -1;
+      zz[r] = LAYER == 1 ? species[v ? j : i] : 0;
+      yop[r] = v ? ycomp(cl, gv.x * irc, gv.y * irc, gv.z * irc) : (cl == 0 ? 1.f : 0.f);
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+            bop[s], sW[(4 * s + g) * kLdW + 16 * (hb + b) + cl], acc[b], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = 16 * (hb + b) + cl;
+      f32x4 mv;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float a = acc[b][r] + base[b];
+        if (LAYER == 1) a += sTs[zz[r] * F_L + c];
+        else a += P2[(size_t)(jj[r] >= 0 ? jj[r] : i) * 2 * F_L + c];   // f_c = 0 if invalid
+        mv[r] = fc[r] * silu_f(a);
       }
 #pragma unroll
-      for (int k = 0; k < K_L; ++k) {
-        const float bk = st.b[q0][k];
-        a0 = fmaf(wb0[k], bk, a0);
-        a1 = fmaf(wb1[k], bk, a1);
-      }
-      const float fc = st.fc[q0];
-      const float ux = st.ux[q0], uy = st.uy[q0], uz = st.uz[q0];
-      const float u2 = ux * ux + uy * uy + uz * uz;
-      accumulate(A, fc * silu_f(a0), ux, uy, uz, u2);
-      accumulate(B, fc * silu_f(a1), ux, uy, uz, u2);
+      for (int s = 0; s < 4; ++s)
+        Mt[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(yop[s], mv[s], Mt[b], 0, 0, 0);
     }
-    wave_sync();
   }
+  // M^T rows y = 4 g + r (y < 10) -> LDS, then moments and invariants per channel
+  float* sm = sM[w];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int y = 4 * g + r;
+      if (y < NMOM) sm[y * kLdW + 16 * b + cl] = Mt[b][r];
+    }
+  wave_sync();
   float* Mi = Mout + (size_t)i * NMOM * F_L;
   float* qi = q + (size_t)i * 3 * F_L;
-  store_moments(A, Mi, qi, c0);
-  store_moments(B, Mi, qi, c1);
+  {
+    const int c = 16 * hb + lane;
+    float mm[NMOM];
+#pragma unroll
+    for (int y = 0; y < NMOM; ++y) {
+      mm[y] = sm[y * kLdW + lane];
+      Mi[y * F_L + c] = mm[y];
+    }
+    qi[c] = mm[0];
+    qi[F_L + c] = mm[1] * mm[1] + mm[2] * mm[2] + mm[3] * mm[3];
+    qi[2 * F_L + c] = mm[4] * mm[4] + mm[5] * mm[5] + mm[6] * mm[6] +
+                      2.0f * (mm[7] * mm[7] + mm[8] * mm[8] + mm[9] * mm[9]);
+  }
 }
 
-// Per-channel reverse-mode state of one receiver: dE/dM (M2 part as a symmetric matrix).
-struct DMom {
-  float m0, x, y, z, xx, yy, zz, xy, xz, yz, tr;
-};
-
-__device__ __forceinline__ DMom load_dmom(const float* Mi, const float* dqi, int c) {
-  DMom d;
-  d.m0 = dqi[c];
-  const float s1 = 2.0f * dqi[F_L + c];
-  const float s2 = 2.0f * dqi[2 * F_L + c];
-  d.x = s1 * Mi[1 * F_L + c];
-  d.y = s1 * Mi[2 * F_L + c];
-  d.z = s1 * Mi[3 * F_L + c];
-  d.xx = s2 * Mi[4 * F_L + c];
-  d.yy = s2 * Mi[5 * F_L + c];
-  d.zz = s2 * Mi[6 * F_L + c];
-  d.xy = s2 * Mi[7 * F_L + c];
-  d.xz = s2 * Mi[8 * F_L + c];
-  d.yz = s2 * Mi[9 * F_L + c];
-  d.tr = d.xx + d.yy + d.zz;
-  return d;
-}
-
-// One channel's share of a pair's reverse pass.  Returns dE/da (for the feature sums)
-// and adds the channel's contribution to v = dE/dd into (vx, vy, vz).
-__device__ __forceinline__ float pair_channel_backward(const DMom& d, float a, float gd, float fc,
-                                                       float dfc, float ux, float uy, float uz,
-                                                       float u2, float rx, float ry, float rz,
-                                                       float inv_rc, float& vx, float& vy,
-                                                       float& vz) {
-  float s, ds;
-  silu_and_grad(a, s, ds);
-  const float m = fc * s;
-  const float t3 = u2 * (1.0f / 3.0f);
-  const float dm = d.m0 + d.x * ux + d.y * uy + d.z * uz + d.xx * (ux * ux - t3) +
-                   d.yy * (uy * uy - t3) + d.zz * (uz * uz - t3) +
-                   2.0f * (d.xy * ux * uy + d.xz * ux * uz + d.yz * uy * uz);
-  const float da = dm * fc * ds;
-  const float rho = dm * s * dfc + da * gd;   // dE/dr through f_c and b(r)
-  // dE/du through u and Y2(u): m (dM1 + 2 dM2 u - 2/3 tr(dM2) u)
-  const float mr = m * inv_rc;
-  const float ax = d.x + 2.0f * (d.xx * ux + d.xy * uy + d.xz * uz) - (2.0f / 3.0f) * d.tr * ux;
-  const float ay = d.y + 2.0f * (d.xy * ux + d.yy * uy + d.yz * uz) - (2.0f / 3.0f) * d.tr * uy;
-  const float az = d.z + 2.0f * (d.xz * ux + d.yz * uy + d.zz * uz) - (2.0f / 3.0f) * d.tr * uz;
-  vx += rho * rx + mr * ax;
-  vy += rho * ry + mr * ay;
-  vz += rho * rz + mr * az;
-  return da;
-}
-
-// LAYER 2 stores dE/da_ij per pair (dA) and the receiver sums (RS[:, 0:F]); LAYER 1 adds its
-// v_ij into the per-pair vector accumulated by layer 2.
 template <int LAYER>
 __global__ void __launch_bounds__(kWaves * 64)
-k_pair_backward(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-                const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
-                double box, const float* __restrict__ P2, const float* __restrict__ Mall,
+k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
+                const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
+                const float* __restrict__ P2, const float* __restrict__ Mall,
                 const float* __restrict__ dq, float* __restrict__ dA, float* __restrict__ RS,
                 float* __restrict__ v, int64_t cap) {
-  __shared__ Stage stage[kWaves];
-  __shared__ float s_Ts[LAYER == 1 ? Z_MAX : 1][F_L];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ float sWt[F_L * kLdT];                  // W_b [c][k]
+  __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
+  // per wave, over its 64 channels (local index cc = c - 64 half)
+  __shared__ float sD[kWaves][NMOM * kLdH];          // D[y][cc] of the receiver
+  __shared__ float sB[kWaves][F_L / 2];              // receiver term S_i of a_ij
+  __shared__ float sR[LAYER == 2 ? kWaves : 1][kTile][F_L / 2 + 4];  // per-pair-slot sums of dE/da
+  for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x) {
+    const int k = e / F_L, c = e % F_L;
+    sWt[c * kLdT + k] = P.WbT[e];
+  }
   if (LAYER == 1)
-    for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) s_Ts[e / F_L][e % F_L] = P.Ts[e];
+    for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
-  const int i = blockIdx.x * kWaves + w;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int i = blockIdx.x * kAtomsPerWg + (w >> 1);
+  const int half = w & 1, hb = 4 * half;
   if (i >= n) return;
-  Stage& st = stage[w];
-  const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
-  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-  const int c0 = lane, c1 = lane + 64;
-  float wb0[K_L], wb1[K_L];
+  float* sd = sD[w];
+  float* vh = v + (size_t)half * 3 * cap;   // this half's share of v_ij
+  const int zi_s = species[i];
+  // D[y][c]: dE/dq folded with dq/dM, off-diagonal M2 components doubled, so that
+  // dm = sum_y Y[y] D[y]
+  {
+    const float* Mi = Mall + (size_t)i * NMOM * F_L;
+    const float* dqi = dq + (size_t)i * 3 * F_L;
+    {
+      const int c = 16 * hb + lane;
+      const float s1 = 2.0f * dqi[F_L + c], s2 = 2.0f * dqi[2 * F_L + c];
+      sd[lane] = dqi[c];
 #pragma unroll
-  for (int k = 0; k < K_L; ++k) {
-    wb0[k] = P.WbT[k * F_L + c0];
-    wb1[k] = P.WbT[k * F_L + c1];
+      for (int y = 1; y < 4; ++y) sd[y * kLdH + lane] = s1 * Mi[y * F_L + c];
+#pragma unroll
+      for (int y = 4; y < 7; ++y) sd[y * kLdH + lane] = s2 * Mi[y * F_L + c];
+#pragma unroll
+      for (int y = 7; y < NMOM; ++y) sd[y * kLdH + lane] = 2.0f * s2 * Mi[y * F_L + c];
+    }
   }
-  float base0, base1;
-  if (LAYER == 1) {
-    base0 = P.Td[species[i] * F_L + c0];
-    base1 = P.Td[species[i] * F_L + c1];
-  } else {
-    base0 = P2[(size_t)i * 2 * F_L + F_L + c0];
-    base1 = P2[(size_t)i * 2 * F_L + F_L + c1];
+  {
+    const float* src = LAYER == 1 ? P.Td + zi_s * F_L : P2 + (size_t)i * 2 * F_L + F_L;
+    sB[w][lane] = src[16 * hb + lane];
+    if (LAYER == 2)
+      for (int e = lane; e < kTile * (F_L / 2); e += 64) sR[w][e / (F_L / 2)][e % (F_L / 2)] = 0.f;
   }
-  const float* Mi = Mall + (size_t)i * NMOM * F_L;
-  const float* dqi = dq + (size_t)i * 3 * F_L;
-  const DMom d0 = load_dmom(Mi, dqi, c0);
-  const DMom d1 = load_dmom(Mi, dqi, c1);
-  const float inv_rc = 1.0f / P.rc;
-  float R0 = 0.f, R1 = 0.f;
+  wave_sync();
+  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
+  const float irc = 1.0f / P.rc;
   const int row0 = offs[i], row1 = offs[i + 1];
-  for (int base = row0; base < row1; base += 64) {
-    stage_pair(st, lane, base + lane, row1, nbr, pos, n, box, inv_box, xi, yi, zi, species, P,
-               true);
-    wave_sync();
-    const int nq = min(64, row1 - base);
-    float vx_mine = 0.f, vy_mine = 0.f, vz_mine = 0.f;
-    for (int q0 = 0; q0 < nq; ++q0) {
-      const int j = st.j[q0];
-      if (j < 0) {
-        // padding, or a listed pair beyond this model's cutoff: no message, but the
-        // sender gather reads dA of every listed pair
-        if (LAYER == 2) {
-          const size_t p = (size_t)(base + q0);
-          dA[p * F_L + c0] = 0.f;
-          dA[p * F_L + c1] = 0.f;
-        }
-        continue;
-      }
-      float a0, a1;
-      if (LAYER == 1) {
-        a0 = base0 + s_Ts[st.z[q0]][c0];
-        a1 = base1 + s_Ts[st.z[q0]][c1];
-      } else {
-        a0 = base0 + P2[(size_t)j * 2 * F_L + c0];
-        a1 = base1 + P2[(size_t)j * 2 * F_L + c1];
-      }
-      float gd0 = 0.f, gd1 = 0.f;
+  for (int t0 = row0; t0 < row1; t0 += kTile) {
+    // the lane's pair
+    const int p = t0 + cl;
+    const float4 gv = geo[p];
+    const int j0 = nbr[p];
+    const bool vp = j0 >= 0 && gv.w < P.rc;
+    const int j = vp ? j0 : -1;
+    float fc, dfc;
+    cutoff_fn(gv.w, P.rc, vp, fc, dfc);
+    const float ux = vp ? gv.x * irc : 0.f, uy = vp ? gv.y * irc : 0.f, uz = vp ? gv.z * irc : 0.f;
+    float bop[8], dbop[8];
 #pragma unroll
-      for (int k = 0; k < K_L; ++k) {
-        const float bk = st.b[q0][k], dbk = st.db[q0][k];
-        a0 = fmaf(wb0[k], bk, a0);
-        a1 = fmaf(wb1[k], bk, a1);
-        gd0 = fmaf(wb0[k], dbk, gd0);
-        gd1 = fmaf(wb1[k], dbk, gd1);
-      }
-      const float fc = st.fc[q0], dfc = st.dfc[q0];
-      const float ux = st.ux[q0], uy = st.uy[q0], uz = st.uz[q0];
-      const float rx = st.rx[q0], ry = st.ry[q0], rz = st.rz[q0];
-      const float u2 = ux * ux + uy * uy + uz * uz;
-      float vx = 0.f, vy = 0.f, vz = 0.f;
-      const float da0 = pair_channel_backward(d0, a0, gd0, fc, dfc, ux, uy, uz, u2, rx, ry, rz,
-                                              inv_rc, vx, vy, vz);
-      const float da1 = pair_channel_backward(d1, a1, gd1, fc, dfc, ux, uy, uz, u2, rx, ry, rz,
-                                              inv_rc, vx, vy, vz);
-      if (LAYER == 2) {
-        const size_t p = (size_t)(base + q0);
-        dA[p * F_L + c0] = da0;
-        dA[p * F_L + c1] = da1;
-        R0 += da0;
-        R1 += da1;
-      }
-      vx = wave_sum(vx);
-      vy = wave_sum(vy);
-      vz = wave_sum(vz);
-      if (lane == q0) {
-        vx_mine = vx;
-        vy_mine = vy;
-        vz_mine = vz;
-      }
+    for (int s = 0; s < 8; ++s) {
+      const float x = gv.w - P.sigma * (4 * s + g);
+      const float bk = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+      bop[s] = bk;
+      dbop[s] = -x * inv_s2 * bk;
     }
-    const int p = base + lane;
-    if (lane < nq) {
+    float yop[4];   // B operand of dm^T: Y^T[4 s + g][pair cl]
+#pragma unroll
+    for (int s = 0; s < 4; ++s) yop[s] = ycomp(4 * s + g, ux, uy, uz);
+    // invalid pairs have f_c = 0, so any finite sender term will do: use the receiver's
+    const float* Aj = LAYER == 2 ? P2 + (size_t)(j >= 0 ? j : i) * 2 * F_L : nullptr;
+    const float* Tj = LAYER == 1 ? sTs + species[j >= 0 ? j : i] * F_L : nullptr;
+    float S1 = 0.f, S2 = 0.f, G[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G[k] = 0.f;
+#pragma unroll
+    for (int bb4 = 0; bb4 < 4; ++bb4) {
+      const int b = hb + bb4;
+      f32x4 ga = {0.f, 0.f, 0.f, 0.f}, gd = ga, dmv = ga;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float wv = sWt[(16 * b + cl) * kLdT + 4 * s + g];
+        ga = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, bop[s], ga, 0, 0, 0);
+        gd = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, dbop[s], gd, 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        dmv = __builtin_amdgcn_mfma_f32_16x16x4f32(sd[(4 * s + g) * kLdH + 16 * bb4 + cl], yop[s],
+                                                   dmv, 0, 0, 0);
+      const int c0 = 16 * b + 4 * g;   // the lane's four channels c0 .. c0+3
+      const int l0 = 16 * bb4 + 4 * g;  // their index within the half
+      float4 add = make_float4(0.f, 0.f, 0.f, 0.f);
       if (LAYER == 2) {
-        v[p] = vx_mine;
-        v[cap + p] = vy_mine;
-        v[2 * cap + p] = vz_mine;
+        add = *reinterpret_cast<const float4*>(Aj + c0);
       } else {
-        v[p] += vx_mine;
-        v[cap + p] += vy_mine;
-        v[2 * cap + p] += vz_mine;
+        add = *reinterpret_cast<const float4*>(Tj + c0);
+      }
+      const float4 bb = *reinterpret_cast<const float4*>(&sB[w][l0]);
+      float4 Dk[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Dk[k] = *reinterpret_cast<const float4*>(sd + (k + 1) * kLdH + l0);
+      float4 dav;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float addr = r == 0 ? add.x : r == 1 ? add.y : r == 2 ? add.z : add.w;
+        const float br = r == 0 ? bb.x : r == 1 ? bb.y : r == 2 ? bb.z : bb.w;
+        const float a = ga[r] + br + addr;
+        float sv, dsv;
+        silu_and_grad(a, sv, dsv);
+        const float m = fc * sv;
+        const float dm = dmv[r];
+        const float da = dm * fc * dsv;
+        S1 = fmaf(dm, sv, S1);
+        S2 = fmaf(da, gd[r], S2);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const float dk = r == 0 ? Dk[k].x : r == 1 ? Dk[k].y : r == 2 ? Dk[k].z : Dk[k].w;
+          G[k] = fmaf(m, dk, G[k]);
+        }
+        if (r == 0) dav.x = da; else if (r == 1) dav.y = da; else if (r == 2) dav.z = da; else dav.w = da;
+      }
+      if (LAYER == 2) {
+        *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
+        float4* acc = reinterpret_cast<float4*>(&sR[w][cl][l0]);
+        float4 t = *acc;
+        t.x += dav.x;
+        t.y += dav.y;
+        t.z += dav.z;
+        t.w += dav.w;
+        *acc = t;
+      }
+      // one channel block at a time: keeps the live accumulators to three MFMA tiles
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // channel sums of the pair: in-lane above, then across the four groups
+    S1 += __shfl_xor(S1, 16, 64);
+    S1 += __shfl_xor(S1, 32, 64);
+    S2 += __shfl_xor(S2, 16, 64);
+    S2 += __shfl_xor(S2, 32, 64);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      G[k] += __shfl_xor(G[k], 16, 64);
+      G[k] += __shfl_xor(G[k], 32, 64);
+    }
+    if (g == 0) {
+      // G[0..2] = sum m dM1, G[3..5] = sum m dM2_aa, G[6..8] = sum m 2 dM2_ab (xy, xz, yz)
+      const float t23 = (2.0f / 3.0f) * (G[3] + G[4] + G[5]);
+      const float ax = G[0] + 2.0f * G[3] * ux + G[6] * uy + G[7] * uz - t23 * ux;
+      const float ay = G[1] + G[6] * ux + 2.0f * G[4] * uy + G[8] * uz - t23 * uy;
+      const float az = G[2] + G[7] * ux + G[8] * uy + 2.0f * G[5] * uz - t23 * uz;
+      const float rho = dfc * S1 + S2;
+      const float ir = vp ? 1.0f / gv.w : 0.f;
+      const float vx = rho * gv.x * ir + irc * ax;
+      const float vy = rho * gv.y * ir + irc * ay;
+      const float vz = rho * gv.z * ir + irc * az;
+      if (LAYER == 2) {
+        vh[p] = vx;
+        vh[cap + p] = vy;
+        vh[2 * cap + p] = vz;
+      } else {
+        vh[p] += vx;
+        vh[cap + p] += vy;
+        vh[2 * cap + p] += vz;
       }
     }
-    wave_sync();
   }
   if (LAYER == 2) {
-    RS[(size_t)i * 2 * F_L + c0] = R0;
-    RS[(size_t)i * 2 * F_L + c1] = R1;
+    // receiver sums: add the 16 pair slots in a fixed order
+    wave_sync();
+    float t = 0.f;
+    for (int k = 0; k < kTile; ++k) t += sR[w][k][lane];
+    RS[(size_t)i * 2 * F_L + 16 * hb + lane] = t;
   }
 }
 
@@ -397,7 +404,8 @@ k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nb
 
 }  // namespace
 
-// F_i = sum_{p in row i} v[p] - v[rev[p]]  (v[p] = dE/dd_ij, d_ij = x_j - x_i)
+// F_i = sum_{p in row i} v[p] - v[rev[p]]  (v[p] = dE/dd_ij, d_ij = x_j - x_i), with v
+// kept as two channel-half partial sums added here in a fixed order.
 __global__ void __launch_bounds__(256)
 k_force_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                const int32_t* __restrict__ rev, int n, const float* __restrict__ v, int64_t cap,
@@ -411,9 +419,10 @@ k_force_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr
     if (nbr[p] < 0) continue;
     const int q = rev[p];
     if (q < 0) continue;
-    fx += v[p] - v[q];
-    fy += v[cap + p] - v[cap + q];
-    fz += v[2 * cap + p] - v[2 * cap + q];
+    const float* v1 = v + 3 * cap;
+    fx += (v[p] + v1[p]) - (v[q] + v1[q]);
+    fy += (v[cap + p] + v1[cap + p]) - (v[cap + q] + v1[cap + q]);
+    fz += (v[2 * cap + p] + v1[2 * cap + p]) - (v[2 * cap + q] + v1[2 * cap + q]);
   }
   fx = wave_sum(fx);
   fy = wave_sum(fy);
@@ -429,6 +438,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                                 int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
                                 double* energy, float* forces, float* atom_energy, hipStream_t s) {
   DMTS_REQUIRE(m->K == K_L && m->F == F_L, DMTS_E_ARG, "large model: unsupported shape");
+  DMTS_REQUIRE(nl->row_align % kTile == 0, DMTS_E_ARG,
+               "large model: the neighbor list needs row_align 16 (or a multiple), got %d",
+               nl->row_align);
   const size_t F = F_L, N = (size_t)((n + 63) / 64 * 64);
   // per-atom workspace layout (floats)
   const size_t o_q1 = 0, o_M1 = o_q1 + N * 3 * F, o_z1 = o_M1 + N * NMOM * F;
@@ -441,7 +453,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                "large model: atom workspace");
   const int64_t cap = nl->max_pairs;
   if (forces) {
-    DMTS_REQUIRE(m->pair_ws.reserve(sizeof(float) * (size_t)cap * (F + 3), s) == DMTS_OK,
+    DMTS_REQUIRE(m->pair_ws.reserve(sizeof(float) * (size_t)cap * (F + 6), s) == DMTS_OK,
                  DMTS_E_OOM, "large model: pair workspace");
   }
   float* W = m->atom_ws.as<float>();
@@ -452,16 +464,17 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                   m->p(m->o_wo),  m->p(m->o_Wo),   m->p(m->o_U2),  m->p(m->o_W2hs),
                   m->p(m->o_U1)};
   const int blocks = ceil_div(n, kWaves);
+  const int pblocks = ceil_div(n, kAtomsPerWg);
   dmts_status st;
   if (n > 0) {
     { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
-    k_pair_forward<1><<<blocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, pos, species, n, box,
-                                                     nullptr, W + o_M1, W + o_q1); }
+    k_pair_fwd_mfma<1><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
+                                                      nullptr, W + o_M1, W + o_q1); }
     DMTS_CHECK_LAUNCH();
     if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
     { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
-    k_pair_forward<2><<<blocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, pos, species, n, box,
-                                                     W + o_P2, W + o_M2, W + o_q2); }
+    k_pair_fwd_mfma<2><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
+                                                      W + o_P2, W + o_M2, W + o_q2); }
     DMTS_CHECK_LAUNCH();
     if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
                           forces != nullptr, s)) != DMTS_OK) return st;
@@ -469,8 +482,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       float* dA = m->pair_ws.as<float>();
       float* v = dA + (size_t)cap * F;
       { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
-      k_pair_backward<2><<<blocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, pos, species, n,
-                                                        box, W + o_P2, W + o_M2, W + o_dq2, dA,
+      k_pair_bwd_mfma<2><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
+                                                        n, W + o_P2, W + o_M2, W + o_dq2, dA,
                                                         W + o_RS, v, cap); }
       DMTS_CHECK_LAUNCH();
       { ProfScope ps(DMTS_K_GATHER, s);
@@ -479,8 +492,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
         return st;
       { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
-      k_pair_backward<1><<<blocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, pos, species, n,
-                                                        box, nullptr, W + o_M1, W + o_dq1, nullptr,
+      k_pair_bwd_mfma<1><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
+                                                        n, nullptr, W + o_M1, W + o_dq1, nullptr,
                                                         nullptr, v, cap); }
       DMTS_CHECK_LAUNCH();
       { ProfScope ps(DMTS_K_GATHER, s);

@@ -240,12 +240,14 @@ k_rows(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys
   }
 }
 
-// CSR rows (padded with -1) from the staging table, and the reverse index:
-// rev[p] for p = (i, j) is offs[j] + (position of i in the sorted row of j).
+// CSR rows (padded with -1) from the staging table, the reverse index
+// rev[p] = offs[j] + (position of i in the sorted row of j), and the pair geometry at the
+// build positions: geo[p] = (d_ij as float, |d_ij|), zero for padding.
 __global__ void __launch_bounds__(kNbWaves * 64)
-k_compact(int32_t n, const int32_t* __restrict__ ell, const int32_t* __restrict__ len,
+k_compact(Geo gm, const int32_t* __restrict__ ell, const int32_t* __restrict__ len,
           const int32_t* __restrict__ offs, int32_t* __restrict__ nbr,
-          int32_t* __restrict__ rev) {
+          int32_t* __restrict__ rev, float4* __restrict__ geo) {
+  const int32_t n = gm.n;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNbWaves + w;
   if (i >= n) return;
@@ -265,8 +267,17 @@ k_compact(int32_t n, const int32_t* __restrict__ ell, const int32_t* __restrict_
       }
       r = (a < len[j] && rj[a] == i) ? offs[j] + a : -1;
     }
+    float4 gv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j >= 0) {
+      const double xi = gm.pos[i], yi = gm.pos[n + i], zi = gm.pos[2 * n + i];
+      const float dx = static_cast<float>(minimage(gm.pos[j] - xi, gm.box, gm.inv_box));
+      const float dy = static_cast<float>(minimage(gm.pos[n + j] - yi, gm.box, gm.inv_box));
+      const float dz = static_cast<float>(minimage(gm.pos[2 * n + j] - zi, gm.box, gm.inv_box));
+      gv = make_float4(dx, dy, dz, sqrtf(dx * dx + dy * dy + dz * dz));
+    }
     nbr[row0 + k] = j;
     rev[row0 + k] = r;
+    geo[row0 + k] = gv;
   }
 }
 
@@ -340,7 +351,8 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
   k_scan<<<1, kScanThreads, 0, s>>>(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags,
                                     false);
   DMTS_CHECK_LAUNCH();
-  k_compact<<<blocks, kNbWaves * 64, 0, s>>>(n, nl->ell, nl->len, nl->offs, nl->nbr, nl->rev);
+  k_compact<<<blocks, kNbWaves * 64, 0, s>>>(g, nl->ell, nl->len, nl->offs, nl->nbr, nl->rev,
+                                             nl->geo);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
@@ -373,6 +385,7 @@ extern "C" dmts_status nnp_nlist_create(int32_t max_atoms, int64_t max_pairs,
   e = e == hipSuccess ? hipMalloc(&nl->ell, sizeof(int32_t) * a * dmts::kNlistRowCap) : e;
   e = e == hipSuccess ? hipMalloc(&nl->nbr, sizeof(int32_t) * nl->max_pairs) : e;
   e = e == hipSuccess ? hipMalloc(&nl->rev, sizeof(int32_t) * nl->max_pairs) : e;
+  e = e == hipSuccess ? hipMalloc(&nl->geo, sizeof(float4) * nl->max_pairs) : e;
   e = e == hipSuccess ? hipMalloc(&nl->flags, sizeof(uint32_t)) : e;
   e = e == hipSuccess ? hipMemset(nl->flags, 0, sizeof(uint32_t)) : e;
   e = e == hipSuccess ? hipMemset(nl->offs, 0, sizeof(int32_t) * (a + 1)) : e;
@@ -398,6 +411,7 @@ extern "C" void nnp_nlist_destroy(nnp_nlist* h) {
   (void)hipFree(nl->ell);
   (void)hipFree(nl->nbr);
   (void)hipFree(nl->rev);
+  (void)hipFree(nl->geo);
   (void)hipFree(nl->flags);
   nl->cell_buf.release();
   delete nl;

@@ -42,19 +42,19 @@ def _pairs_of(nl, n):
     return offs, nbr, rev, rows, real
 
 
-@pytest.mark.parametrize("sysname,cut", [("water192", 3.5), ("water192", 5.2),
-                                         ("water4500", 3.5), ("water4500", 5.2),
-                                         ("batch16", 5.2), ("open60", 3.5),
-                                         ("wrapped1500", 5.2)])
-def test_neighbor_set_matches_oracle(sysname, cut):
-    say(f"nlist {sysname} rc={cut}")
+@pytest.mark.parametrize("sysname,cut,align", [("water192", 3.5, 4), ("water192", 5.2, 16),
+                                               ("water4500", 3.5, 4), ("water4500", 5.2, 16),
+                                               ("batch16", 5.2, 16), ("open60", 3.5, 32),
+                                               ("wrapped1500", 5.2, 4)])
+def test_neighbor_set_matches_oracle(sysname, cut, align):
+    say(f"nlist {sysname} rc={cut} align={align}")
     sy = system(sysname)
     pos, _, offs_d = _dev(sy)
-    nl = api.NeighborList(sy.n_atoms, sy.n_atoms * 200, 4)
+    nl = api.NeighborList(sy.n_atoms, sy.n_atoms * 200, align)
     nl.build(pos, sy.box, cut, offs_d)
     assert nl.flags() == 0
     offs, nbr, rev, rows, real = _pairs_of(nl, sy.n_atoms)
-    assert np.all(offs % 4 == 0)
+    assert np.all(offs % align == 0)
     got = set(zip(rows[real].tolist(), nbr[real].tolist()))
     i, j, _ = oracle_pairs(sysname, cut)
     assert got == set(zip(i.tolist(), j.tolist()))
@@ -62,7 +62,7 @@ def test_neighbor_set_matches_oracle(sysname, cut):
     for a in range(0, sy.n_atoms, max(1, sy.n_atoms // 50)):
         row = nbr[offs[a]:offs[a + 1]]
         k = int(np.sum(row >= 0))
-        assert np.all(row[:k] >= 0) and np.all(row[k:] == -1) and len(row) - k < 4
+        assert np.all(row[:k] >= 0) and np.all(row[k:] == -1) and len(row) - k < align
     # rows ascend in the sender index
     for a in range(sy.n_atoms):
         row = nbr[offs[a]:offs[a + 1]]
@@ -143,12 +143,22 @@ def test_pairs_listed_beyond_the_model_cutoff_contribute_nothing(models):
     sy = system("water192")
     pos, sp, _ = _dev(sy)
     for which, big in (("small", 5.0), ("large", 6.0)):
-        nl = api.NeighborList(sy.n_atoms, sy.n_atoms * 200, 4)
+        nl = api.NeighborList(sy.n_atoms, sy.n_atoms * 200, 16)
         nl.build(pos, sy.box, big)
         E, F = api.energy_forces(models[which], nl, pos, sp, sy.box)
         E0, F0, _ = oracle_ef("water192", which)
         assert rel_rmse(api.from_soa(F), F0) <= F_TOL
         np.testing.assert_allclose(E.cpu().numpy(), E0, atol=E_TOTAL_PER_ATOM * sy.n_atoms)
+
+
+def test_reference_model_needs_16_aligned_rows(models):
+    sy = system("water192")
+    pos, sp, _ = _dev(sy)
+    nl = api.NeighborList(sy.n_atoms, sy.n_atoms * 200, 4)
+    nl.build(pos, sy.box, 5.2)
+    with pytest.raises(api.DmtsError) as e:
+        api.energy_forces(models["large"], nl, pos, sp, sy.box)
+    assert e.value.status == api.E_ARG
 
 
 def test_list_below_model_cutoff_is_rejected(models):
