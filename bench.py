@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="MLP contraction operands (bf16: bfloat16 operands, FP32 accumulate)")
     return ap.parse_args()
 
 
@@ -95,8 +97,9 @@ def main():
     sy = synth.water_4500() if args.workload == "water4500" else synth.water_192()
     ws = synth.model_weights(synth.SMALL, synth.SMALL_SEED)
     wl = synth.model_weights(synth.LARGE, synth.LARGE_SEED)
-    small = api.Model.from_spec(synth.SMALL, ws)
-    large = api.Model.from_spec(synth.LARGE, wl)
+    prec = api.PREC_BF16 if args.precision == "bf16" else api.PREC_FP32
+    small = api.Model.from_spec(synth.SMALL, ws, precision=prec)
+    large = api.Model.from_spec(synth.LARGE, wl, precision=prec)
     sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
     v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201)
     n_inner, dt_in = args.n_inner, args.dt_inner
@@ -211,13 +214,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": sy.n_atoms, "box_A": sy.box,
                    "dt_inner_fs": dt_in, "dt_outer_fs": dt_out,
                    "fast_model": "1 interaction, rc 3.5 A, K 16, F 64",
                    "reference_model": "2 interactions, rc 5.2 A, K 32, F 128, l<=2",
-                   "integration": "f64", "ensemble": "NVE"},
+                   "integration": "f64", "ensemble": "NVE",
+                   "mlp_operands": args.precision},
         "atom_steps_per_s": round(atom_steps, 1),
         "verlet_ns_per_day": round(vv["ns_per_day"], 4) if vv else None,
         "verlet_ms_per_step": round(vv["ms_per_step"], 5) if vv else None,

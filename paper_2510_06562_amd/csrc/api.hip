@@ -130,6 +130,34 @@ struct Blob {
   }
 };
 
+// Round to nearest even, to bfloat16 bits (finite inputs).
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return static_cast<uint16_t>(u >> 16);
+}
+
+float bf16_round(float f) {
+  uint32_t u = static_cast<uint32_t>(bf16_bits(f)) << 16;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+
+std::vector<float> rounded(std::vector<float> v) {
+  for (auto& x : v) x = bf16_round(x);
+  return v;
+}
+
+// Append a [rows][cols] float matrix as bfloat16 (rows = outputs, cols = inputs).
+void append16(std::vector<uint16_t>& dst, size_t& off, const std::vector<float>& src) {
+  off = dst.size();
+  for (float x : src) dst.push_back(bf16_bits(x));
+  while (dst.size() % 128) dst.push_back(0);
+}
+
 void append(std::vector<float>& dst, size_t& off, const std::vector<float>& src) {
   off = dst.size();
   dst.insert(dst.end(), src.begin(), src.end());
@@ -249,16 +277,65 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
     append(P, m->o_Wo, std::vector<float>(Wo, Wo + (size_t)F * F));
     append(P, m->o_wo, std::vector<float>(wo, wo + F));
   }
+  std::vector<uint16_t> H;
+  if (d.precision == NNP_PREC_BF16) {
+    m->bf16 = true;
+    if (d.kind == NNP_KIND_ONE_INTERACTION) {
+      // the fast model's contractions run on the vector units with bfloat16-valued operands
+      const float* Wp = host_weights + (size_t)Z * D;
+      const float* W1 = Wp + (size_t)F * (K + 2 * D);
+      append(P, m->o_WbR, rounded(transpose_block(Wp, F, K + 2 * D, 0, K)));
+      append(P, m->o_W1R, rounded(std::vector<float>(W1, W1 + (size_t)F * F)));
+      append(P, m->o_W1TR, rounded(transpose_block(W1, F, F, 0, F)));
+    } else {
+      const int cols1 = K + 2 * D, cols2 = K + 2 * F, Q = 3 * F;
+      const float* Wp1 = host_weights + (size_t)Z * D;
+      const float* U1 = Wp1 + (size_t)F * cols1;
+      const float* Wp2 = U1 + (size_t)F * Q;
+      const float* U2 = Wp2 + (size_t)F * cols2;
+      const float* Wo = U2 + (size_t)F * Q;
+      auto block = [](const float* W, int rows, int cols, int c0, int nc) {
+        std::vector<float> t((size_t)rows * nc);
+        for (int r = 0; r < rows; ++r)
+          for (int c = 0; c < nc; ++c) t[(size_t)r * nc + c] = W[(size_t)r * cols + c0 + c];
+        return t;
+      };
+      append16(H, m->h_Wb1, block(Wp1, F, cols1, 0, K));
+      append16(H, m->h_Wb2, block(Wp2, F, cols2, 0, K));
+      append16(H, m->h_U1, std::vector<float>(U1, U1 + (size_t)F * Q));            // [F][3F]
+      std::vector<float> W2h((size_t)2 * F * F), W2hs((size_t)F * 2 * F);
+      for (int nn = 0; nn < 2 * F; ++nn)                                              // [2F][F]
+        for (int k = 0; k < F; ++k)
+          W2h[(size_t)nn * F + k] = nn < F ? Wp2[(size_t)nn * cols2 + K + F + k]
+                                           : Wp2[(size_t)(nn - F) * cols2 + K + k];
+      for (int e = 0; e < F; ++e)                                                      // [F][2F]
+        for (int k = 0; k < 2 * F; ++k)
+          W2hs[(size_t)e * 2 * F + k] = k < F ? Wp2[(size_t)k * cols2 + K + e]
+                                              : Wp2[(size_t)(k - F) * cols2 + K + F + e];
+      append16(H, m->h_W2h, W2h);
+      append16(H, m->h_U2, std::vector<float>(U2, U2 + (size_t)F * Q));
+      append16(H, m->h_Wo, std::vector<float>(Wo, Wo + (size_t)F * F));
+      append16(H, m->h_WoT, transpose_block(Wo, F, F, 0, F));
+      append16(H, m->h_U2T, transpose_block(U2, F, Q, 0, Q));                         // [3F][F]
+      append16(H, m->h_W2hs, W2hs);
+      append16(H, m->h_U1T, transpose_block(U1, F, Q, 0, Q));
+    }
+  }
   if (m->params.reserve(P.size() * sizeof(float), nullptr) != DMTS_OK) {
     delete m;
     return DMTS_E_OOM;
   }
   hipError_t e = hipMemcpy(m->params.ptr, P.data(), P.size() * sizeof(float),
                            hipMemcpyHostToDevice);
+  if (e == hipSuccess && !H.empty()) {
+    if (m->params16.reserve(H.size() * sizeof(uint16_t), nullptr) != DMTS_OK) e = hipErrorOutOfMemory;
+    else e = hipMemcpy(m->params16.ptr, H.data(), H.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     dmts::set_error("nnp_model_create: %s", hipGetErrorString(e));
     m->params.release();
+    m->params16.release();
     delete m;
     return DMTS_E_HIP;
   }
@@ -271,6 +348,7 @@ extern "C" void nnp_model_destroy(nnp_model* h) {
   if (!m) return;
   (void)hipDeviceSynchronize();
   m->params.release();
+  m->params16.release();
   m->atom_ws.release();
   m->pair_ws.release();
   m->sys_ws.release();
@@ -290,8 +368,6 @@ dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t*
                m->desc.cutoff);
   DMTS_REQUIRE(sys_offsets == nullptr || n_sys >= 1, DMTS_E_ARG,
                "nnp_energy_forces: n_sys must be >= 1 with sys_offsets");
-  DMTS_REQUIRE(m->desc.precision == NNP_PREC_FP32, DMTS_E_ARG,
-               "nnp_energy_forces: this build evaluates FP32 models only");
   if (m->desc.kind == NNP_KIND_ONE_INTERACTION)
     return small_energy_forces(m, nl, pos, species, n, box, sys_offsets, n_sys, energy, forces,
                                atom_energy, s);

@@ -16,6 +16,15 @@ struct AtomMlpParams {
   const float* U2;    // [128][384]  dq2 = U2^T dz2
   const float* W2hs;  // [256][128]  dh1 = W_r^T R + W_s^T S
   const float* U1;    // [128][384]  dq1 = U1^T dz1
+  // BF16 form (all null for FP32): the same layers as bfloat16 [out][in]
+  const __bf16* h_U1 = nullptr;    // [128][384]
+  const __bf16* h_W2h = nullptr;   // [256][128]
+  const __bf16* h_U2 = nullptr;    // [128][384]
+  const __bf16* h_Wo = nullptr;    // [128][128]
+  const __bf16* h_WoT = nullptr;   // [128][128]
+  const __bf16* h_U2T = nullptr;   // [384][128]
+  const __bf16* h_W2hs = nullptr;  // [128][256]
+  const __bf16* h_U1T = nullptr;   // [384][128]
 };
 
 dmts_status atom_chain1(const AtomMlpParams& P, int M, const float* q1, float* z1, float* h1,

@@ -14,6 +14,9 @@
 //   chain 3 (after the sender sums): dh1 = dh2 + W_r^T R + W_s^T S, dz1 = dh1 SiLU'(z1),
 //                                   dq1 = U1^T dz1
 //
+// In the BF16 form (weights given as bfloat16 [out][in]) the contractions run on
+// v_mfma_f32_16x16x32_bf16 with the activations rounded to bfloat16 as they are read.
+//
 // MFMA 16x16x4 f32 register layout:
 //   A operand: lane l holds A[l % 16][k0 + l / 16]
 //   B operand: lane l holds B[k0 + l / 16][l % 16]
@@ -45,14 +48,47 @@ __device__ __forceinline__ f32x4 mfma_block(const float* X, int K, const float* 
   return acc;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// BF16 form: acc[16 x 16] = X[16 x K] * W^T with W [N x K] bfloat16 (input index
+// contiguous), on v_mfma_f32_16x16x32_bf16:
+//   A operand: lane l holds A[l % 16][k0 + 8 (l / 16) + e], e = 0..7
+//   B operand: lane l holds B[k0 + 8 (l / 16) + e][l % 16]
+// X is rounded to bfloat16 (nearest even) as it is read; accumulation is FP32.
+__device__ __forceinline__ f32x4 mfma_block_bf16(const float* X, int K,
+                                                 const __bf16* __restrict__ W, int n0,
+                                                 int lane) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int r = lane & 15, g = lane >> 4;
+  const float* xp = X + r * kLd + 8 * g;
+  const __bf16* wp = W + (size_t)(n0 + r) * K + 8 * g;
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const float4 x0 = *reinterpret_cast<const float4*>(xp + k0);
+    const float4 x1 = *reinterpret_cast<const float4*>(xp + k0 + 4);
+    bf16x8 a;
+    a[0] = (__bf16)x0.x; a[1] = (__bf16)x0.y; a[2] = (__bf16)x0.z; a[3] = (__bf16)x0.w;
+    a[4] = (__bf16)x1.x; a[5] = (__bf16)x1.y; a[6] = (__bf16)x1.z; a[7] = (__bf16)x1.w;
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(wp + k0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Weights of one layer: FP32 [K][N] or BF16 [N][K].
+struct LayerW {
+  const float* f32;
+  const __bf16* b16;
+};
+
 // Runs one layer: for every 16-column block of N assigned to this wave, calls
 // epi(row, col, value) for the lane's four outputs.
 template <class Epi>
-__device__ __forceinline__ void layer(const float* X, int K, const float* __restrict__ B, int N,
-                                      Epi&& epi) {
+__device__ __forceinline__ void layer(const float* X, int K, LayerW Wt, int N, Epi&& epi) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int nb = wave; nb < N / 16; nb += kThreads / 64) {
-    f32x4 acc = mfma_block(X, K, B, N, nb * 16, lane);
+    f32x4 acc = Wt.b16 ? mfma_block_bf16(X, K, Wt.b16, nb * 16, lane)
+                       : mfma_block(X, K, Wt.f32, N, nb * 16, lane);
 #pragma unroll
     for (int r = 0; r < 4; ++r) epi(4 * (lane >> 4) + r, nb * 16 + (lane & 15), acc[r]);
   }
@@ -75,7 +111,7 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
   const int m0 = blockIdx.x * kRows;
   stage_rows(X, q1, 384, 384, m0, M);
   __syncthreads();
-  layer(X, 384, P.U1T, 128, [&](int r, int c, float v) {
+  layer(X, 384, LayerW{P.U1T, P.h_U1}, 128, [&](int r, int c, float v) {
     const float h = silu_f(v);
     H[r * kLd + c] = h;
     if (m0 + r < M) {
@@ -84,7 +120,7 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
     }
   });
   __syncthreads();
-  layer(H, 128, P.W2hT, 256, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.W2hT, P.h_W2h}, 256, [&](int r, int c, float v) {
     if (m0 + r < M) P2[(size_t)(m0 + r) * 256 + c] = v;
   });
 }
@@ -100,14 +136,14 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
   const int m0 = blockIdx.x * kRows;
   stage_rows(X, q2, 384, 384, m0, M);
   __syncthreads();
-  layer(X, 384, P.U2T, 128, [&](int r, int c, float v) {
+  layer(X, 384, LayerW{P.U2T, P.h_U2}, 128, [&](int r, int c, float v) {
     Z[r * 128 + c] = v;
     const float hp = (m0 + r) < M ? h1[(size_t)(m0 + r) * 128 + c] : 0.f;
     H[r * kLd + c] = hp + silu_f(v);
   });
   __syncthreads();
   // y = W_o h2; energy terms and dy (dy overwrites the X buffer)
-  layer(H, 128, P.WoT, 128, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.WoT, P.h_Wo}, 128, [&](int r, int c, float v) {
     float s, ds;
     silu_and_grad(v, s, ds);
     const float w = P.wo[c];
@@ -126,12 +162,12 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
   }
   if (!backward) return;
   // dh2 = W_o^T dy, dz2 = dh2 SiLU'(z2)   (dz2 goes to H)
-  layer(X, 128, P.Wo, 128, [&](int r, int c, float v) {
+  layer(X, 128, LayerW{P.Wo, P.h_WoT}, 128, [&](int r, int c, float v) {
     if (m0 + r < M) dh2_out[(size_t)(m0 + r) * 128 + c] = v;
     H[r * kLd + c] = v * dsilu_f(Z[r * 128 + c]);
   });
   __syncthreads();
-  layer(H, 128, P.U2, 384, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.U2, P.h_U2T}, 384, [&](int r, int c, float v) {
     if (m0 + r < M) dq2[(size_t)(m0 + r) * 384 + c] = v;
   });
 }
@@ -144,7 +180,7 @@ k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __re
   const int m0 = blockIdx.x * kRows;
   stage_rows(X, RS, 256, 256, m0, M);
   __syncthreads();
-  layer(X, 256, P.W2hs, 128, [&](int r, int c, float v) {
+  layer(X, 256, LayerW{P.W2hs, P.h_W2hs}, 128, [&](int r, int c, float v) {
     float dz = 0.f;
     if (m0 + r < M) {
       const size_t o = (size_t)(m0 + r) * 128 + c;
@@ -153,7 +189,7 @@ k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __re
     H[r * kLd + c] = dz;
   });
   __syncthreads();
-  layer(H, 128, P.U1, 384, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.U1, P.h_U1T}, 384, [&](int r, int c, float v) {
     if (m0 + r < M) dq1[(size_t)(m0 + r) * 384 + c] = v;
   });
 }

@@ -19,6 +19,8 @@
 // interaction 2 is stored per pair, because the sender sums need it in the other row.
 // No floating-point atomics: every sum has a fixed order, so results are bitwise
 // reproducible.
+#include <type_traits>
+
 #include "atom_mlp.h"
 
 namespace dmts {
@@ -34,6 +36,7 @@ constexpr int NMOM = 10;   // M0, M1 (x, y, z), M2 (xx, yy, zz, xy, xz, yz)
 
 struct LargeParams {
   const float* WbT;   // [K][F] radial block of the interaction
+  const __bf16* Wb16; // [F][K] the same block as bfloat16 (BF16 form only)
   const float* Td;    // [Z][F] layer 1 receiver table
   const float* Ts;    // [Z][F] layer 1 sender table
   float rc, sigma;
@@ -49,13 +52,18 @@ struct LargeParams {
 // Forward: a = b W_b as D[pair][channel] (pair 4g + r, channel 16 blk + cl).  The moments
 // M^T[y][c] = sum_p Y[p][y] m[p][c] then use that accumulator as their B operand: in step
 // s the K index g stands for pair 4g + s, i.e. register s of the lane.
+// BF16 form: the radial contraction is one v_mfma_f32_16x16x32_bf16 per 16 x 16 block (A
+// operand: lane l holds A[l % 16][8 g + e], B operand B[8 g + e][l % 16], e = 0..7), with
+// b and W_b rounded to bfloat16; moments, their reverse and all elementwise math stay FP32.
 // Reverse pass: the transposed product a^T = W_b b^T as D[channel][pair] (channel
 // 16 blk + 4g + r, pair cl): each lane owns one pair and 32 channels, so the channel sums
 // of a pair are in-lane plus two cross-group shuffles; dm^T = D_i^T Y^T likewise.
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTile = 16;
+constexpr int kLdK = 40;    // LDS stride (bfloat16) of W_b rows [c][k] in the BF16 form
 constexpr int kLdW = 144;   // LDS stride of W_b^T rows [k][c]
 constexpr int kLdT = 36;    // LDS stride of W_b rows [c][k]
 constexpr int kLdH = 80;    // LDS stride of per-half rows (64 channels)
@@ -94,16 +102,22 @@ __device__ __forceinline__ void cutoff_fn(float r, float rc, bool valid, float& 
   dfc = valid ? -0.5f * 3.14159265358979f / rc * sn : 0.f;
 }
 
-template <int LAYER>
+template <int LAYER, bool BF16>
 __global__ void __launch_bounds__(kWaves * 64)
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
-  __shared__ float sW[K_L * kLdW];
+  __shared__ float sW[BF16 ? 1 : K_L * kLdW];
+  __shared__ __bf16 sW16[BF16 ? F_L * kLdK : 1];
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   __shared__ float sM[kWaves][NMOM * kLdW];
-  for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
-    sW[(e / F_L) * kLdW + e % F_L] = P.WbT[e];
+  if (BF16) {
+    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
+      sW16[(e / K_L) * kLdK + e % K_L] = P.Wb16[e];
+  } else {
+    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
+      sW[(e / F_L) * kLdW + e % F_L] = P.WbT[e];
+  }
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
@@ -130,7 +144,8 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float bop[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const float x = rp - P.sigma * (4 * s + g);
+      const int k = BF16 ? 8 * g + s : 4 * s + g;
+      const float x = rp - P.sigma * k;
       bop[s] = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
     }
     // the lane's four pairs of the D layout: 4 g + r
@@ -151,12 +166,24 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     f32x4 acc[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (BF16) {
+      bf16x8 a8;
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
+      for (int e = 0; e < 8; ++e) a8[e] = (__bf16)bop[e];
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-            bop[s], sW[(4 * s + g) * kLdW + 16 * (hb + b) + cl], acc[b], 0, 0, 0);
+      for (int b = 0; b < 4; ++b) {
+        const bf16x8 w8 =
+            *reinterpret_cast<const bf16x8*>(&sW16[(16 * (hb + b) + cl) * kLdK + 8 * g]);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, w8, acc[b], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              bop[s], sW[(4 * s + g) * kLdW + 16 * (hb + b) + cl], acc[b], 0, 0, 0);
+    }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int c = 16 * (hb + b) + cl;
@@ -200,22 +227,28 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   }
 }
 
-template <int LAYER>
+template <int LAYER, bool BF16>
 __global__ void __launch_bounds__(kWaves * 64)
 k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, const float* __restrict__ Mall,
                 const float* __restrict__ dq, float* __restrict__ dA, float* __restrict__ RS,
                 float* __restrict__ v, int64_t cap) {
-  __shared__ float sWt[F_L * kLdT];                  // W_b [c][k]
+  __shared__ float sWt[BF16 ? 1 : F_L * kLdT];       // W_b [c][k]
+  __shared__ __bf16 sW16[BF16 ? F_L * kLdK : 1];      // W_b [c][k] as bfloat16
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   // per wave, over its 64 channels (local index cc = c - 64 half)
   __shared__ float sD[kWaves][NMOM * kLdH];          // D[y][cc] of the receiver
   __shared__ float sB[kWaves][F_L / 2];              // receiver term S_i of a_ij
   __shared__ float sR[LAYER == 2 ? kWaves : 1][kTile][F_L / 2 + 4];  // per-pair-slot sums of dE/da
-  for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x) {
-    const int k = e / F_L, c = e % F_L;
-    sWt[c * kLdT + k] = P.WbT[e];
+  if (BF16) {
+    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
+      sW16[(e / K_L) * kLdK + e % K_L] = P.Wb16[e];
+  } else {
+    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x) {
+      const int k = e / F_L, c = e % F_L;
+      sWt[c * kLdT + k] = P.WbT[e];
+    }
   }
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
@@ -267,10 +300,19 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float bop[8], dbop[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const float x = gv.w - P.sigma * (4 * s + g);
+      const int k = BF16 ? 8 * g + s : 4 * s + g;
+      const float x = gv.w - P.sigma * k;
       const float bk = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
       bop[s] = bk;
       dbop[s] = -x * inv_s2 * bk;
+    }
+    bf16x8 b8, db8;
+    if (BF16) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        b8[e] = (__bf16)bop[e];
+        db8[e] = (__bf16)dbop[e];
+      }
     }
     float yop[4];   // B operand of dm^T: Y^T[4 s + g][pair cl]
 #pragma unroll
@@ -285,11 +327,17 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     for (int bb4 = 0; bb4 < 4; ++bb4) {
       const int b = hb + bb4;
       f32x4 ga = {0.f, 0.f, 0.f, 0.f}, gd = ga, dmv = ga;
+      if (BF16) {
+        const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(&sW16[(16 * b + cl) * kLdK + 8 * g]);
+        ga = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, b8, ga, 0, 0, 0);
+        gd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, db8, gd, 0, 0, 0);
+      } else {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const float wv = sWt[(16 * b + cl) * kLdT + 4 * s + g];
-        ga = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, bop[s], ga, 0, 0, 0);
-        gd = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, dbop[s], gd, 0, 0, 0);
+        for (int s = 0; s < 8; ++s) {
+          const float wv = sWt[(16 * b + cl) * kLdT + 4 * s + g];
+          ga = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, bop[s], ga, 0, 0, 0);
+          gd = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, dbop[s], gd, 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
@@ -458,49 +506,69 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   }
   float* W = m->atom_ws.as<float>();
   float* e_atom = atom_energy ? atom_energy : W + o_e;
-  LargeParams P1{m->p(m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts), m->rc, m->sigma, m->Z};
-  LargeParams P2{m->p(m->o_W2bT), nullptr, nullptr, m->rc, m->sigma, m->Z};
+  LargeParams P1{m->p(m->o_WbT), m->bf16 ? m->p16(m->h_Wb1) : nullptr, m->p(m->o_Td),
+                 m->p(m->o_Ts), m->rc, m->sigma, m->Z};
+  LargeParams P2{m->p(m->o_W2bT), m->bf16 ? m->p16(m->h_Wb2) : nullptr, nullptr, nullptr, m->rc,
+                 m->sigma, m->Z};
   AtomMlpParams A{m->p(m->o_U1T), m->p(m->o_W2hT), m->p(m->o_U2T), m->p(m->o_WoT),
                   m->p(m->o_wo),  m->p(m->o_Wo),   m->p(m->o_U2),  m->p(m->o_W2hs),
                   m->p(m->o_U1)};
+  if (m->bf16) {
+    A.h_U1 = m->p16(m->h_U1);
+    A.h_W2h = m->p16(m->h_W2h);
+    A.h_U2 = m->p16(m->h_U2);
+    A.h_Wo = m->p16(m->h_Wo);
+    A.h_WoT = m->p16(m->h_WoT);
+    A.h_U2T = m->p16(m->h_U2T);
+    A.h_W2hs = m->p16(m->h_W2hs);
+    A.h_U1T = m->p16(m->h_U1T);
+  }
   const int blocks = ceil_div(n, kWaves);
   const int pblocks = ceil_div(n, kAtomsPerWg);
-  dmts_status st;
-  if (n > 0) {
-    { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
-    k_pair_fwd_mfma<1><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
-                                                      nullptr, W + o_M1, W + o_q1); }
-    DMTS_CHECK_LAUNCH();
-    if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
-    { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
-    k_pair_fwd_mfma<2><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
-                                                      W + o_P2, W + o_M2, W + o_q2); }
-    DMTS_CHECK_LAUNCH();
-    if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
-                          forces != nullptr, s)) != DMTS_OK) return st;
-    if (forces) {
-      float* dA = m->pair_ws.as<float>();
-      float* v = dA + (size_t)cap * F;
-      { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
-      k_pair_bwd_mfma<2><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
-                                                        n, W + o_P2, W + o_M2, W + o_dq2, dA,
-                                                        W + o_RS, v, cap); }
+  // the whole evaluation, instantiated for the FP32 and the BF16 form
+  auto run = [&](auto bf_tag) -> dmts_status {
+    constexpr bool BF = decltype(bf_tag)::value;
+    dmts_status st;
+    if (n > 0) {
+      { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
+      k_pair_fwd_mfma<1, BF><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
+                                                        nullptr, W + o_M1, W + o_q1); }
       DMTS_CHECK_LAUNCH();
-      { ProfScope ps(DMTS_K_GATHER, s);
-      k_sender_gather<<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, dA, W + o_RS); }
+      if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
+      { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
+      k_pair_fwd_mfma<2, BF><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
+                                                        W + o_P2, W + o_M2, W + o_q2); }
       DMTS_CHECK_LAUNCH();
-      if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
-        return st;
-      { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
-      k_pair_bwd_mfma<1><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
-                                                        n, nullptr, W + o_M1, W + o_dq1, nullptr,
-                                                        nullptr, v, cap); }
-      DMTS_CHECK_LAUNCH();
-      { ProfScope ps(DMTS_K_GATHER, s);
-      k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces); }
-      DMTS_CHECK_LAUNCH();
+      if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
+                            forces != nullptr, s)) != DMTS_OK) return st;
+      if (forces) {
+        float* dA = m->pair_ws.as<float>();
+        float* v = dA + (size_t)cap * F;
+        { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
+        k_pair_bwd_mfma<2, BF><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
+                                                          n, W + o_P2, W + o_M2, W + o_dq2, dA,
+                                                          W + o_RS, v, cap); }
+        DMTS_CHECK_LAUNCH();
+        { ProfScope ps(DMTS_K_GATHER, s);
+        k_sender_gather<<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, dA, W + o_RS); }
+        DMTS_CHECK_LAUNCH();
+        if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
+          return st;
+        { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
+        k_pair_bwd_mfma<1, BF><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
+                                                          n, nullptr, W + o_M1, W + o_dq1, nullptr,
+                                                          nullptr, v, cap); }
+        DMTS_CHECK_LAUNCH();
+        { ProfScope ps(DMTS_K_GATHER, s);
+        k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces); }
+        DMTS_CHECK_LAUNCH();
+      }
     }
-  }
+
+    return DMTS_OK;
+  };
+  const dmts_status rs = m->bf16 ? run(std::true_type{}) : run(std::false_type{});
+  if (rs != DMTS_OK) return rs;
   if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, s);
   return DMTS_OK;
 }

@@ -14,6 +14,9 @@
 // Pair geometry (b, b', f_c, f_c', unit vector) is computed lane-per-pair for 64 pairs at
 // a time and staged in LDS; the channel loop then reads it as wave-uniform broadcasts.
 // Displacements are minimum-image differences of the float64 positions, rounded to float.
+// BF16 form: the operands of the two contractions (W_r with b or b', W1 with h or its
+// adjoint) are rounded to bfloat16 values (nearest even) and accumulated in FP32; the
+// kernels run the same code with rounded weights and a rounding step on the activations.
 #include "common.h"
 
 namespace dmts {
@@ -36,6 +39,8 @@ struct SmallParams {
   int Z;
 };
 
+__device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
+
 struct PairStage {
   float b[64][K_S];
   float db[64][K_S];
@@ -50,7 +55,8 @@ __device__ __forceinline__ void stage_pair(PairStage& st, int lane, int p, int r
                                            const int32_t* nbr, const double* pos, int n,
                                            double box, double inv_box, double xi, double yi,
                                            double zi, const int32_t* species,
-                                           const SmallParams& P, bool need_grad) {
+                                           const SmallParams& P, bool need_grad,
+                                           bool bf16) {
   int j = p < row1 ? nbr[p] : -1;
   float r = 0.f, fc = 0.f, dfc = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
   bool valid = false;
@@ -77,8 +83,9 @@ __device__ __forceinline__ void stage_pair(PairStage& st, int lane, int p, int r
   for (int k = 0; k < K_S; ++k) {
     float x = r - P.sigma * k;   // mu_k = k r_c/(K-1) = k sigma
     float bk = valid ? __expf(-0.5f * x * x * inv_s2) : 0.f;
-    st.b[lane][k] = bk;
-    if (need_grad) st.db[lane][k] = -x * inv_s2 * bk;
+    const float dbk = -x * inv_s2 * bk;
+    st.b[lane][k] = bf16 ? bf16r(bk) : bk;
+    if (need_grad) st.db[lane][k] = bf16 ? bf16r(dbk) : dbk;
   }
   st.fc[lane] = fc;
   st.dfc[lane] = dfc;
@@ -89,6 +96,7 @@ __device__ __forceinline__ void stage_pair(PairStage& st, int lane, int p, int r
   st.z[lane] = valid ? species[j] : 0;
 }
 
+template <bool BF16>
 __global__ void __launch_bounds__(kWaves * 64)
 k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
@@ -113,7 +121,7 @@ k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* 
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int base = row0; base < row1; base += 64) {
     stage_pair(st, lane, base + lane, row1, nbr, pos, n, box, inv_box, xi, yi, zi, species, P,
-               false);
+               false, BF16);
     wave_sync();
     const int nq = min(64, row1 - base);
     for (int q = 0; q < nq; ++q) {
@@ -126,7 +134,7 @@ k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* 
     wave_sync();
   }
   // readout: z = W1 h, E_i = s_E w2 . SiLU(z), and g = dE/dh = W1^T (s_E w2 * SiLU'(z))
-  s_vec[w][c] = h;
+  s_vec[w][c] = BF16 ? bf16r(h) : h;
   wave_sync();
   float z = 0.f;
   for (int e = 0; e < F_S; ++e) z = fmaf(P.W1T[e * F_S + c], s_vec[w][e], z);
@@ -135,7 +143,7 @@ k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float w2 = P.w2[c];
   float e_i = wave_sum(w2 * y) * P.escale;
   wave_sync();
-  s_vec[w][c] = P.escale * w2 * dy;
+  s_vec[w][c] = BF16 ? bf16r(P.escale * w2 * dy) : P.escale * w2 * dy;
   wave_sync();
   float g = 0.f;
   for (int k = 0; k < F_S; ++k) g = fmaf(P.W1[k * F_S + c], s_vec[w][k], g);
@@ -143,6 +151,7 @@ k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* 
   if (lane == 0) atom_e[i] = e_i;
 }
 
+template <bool BF16>
 __global__ void __launch_bounds__(kWaves * 64)
 k_small_backward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                  const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
@@ -172,7 +181,7 @@ k_small_backward(SmallParams P, const int32_t* __restrict__ offs, const int32_t*
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int base = row0; base < row1; base += 64) {
     stage_pair(st, lane, base + lane, row1, nbr, pos, n, box, inv_box, xi, yi, zi, species, P,
-               true);
+               true, BF16);
     wave_sync();
     const int nq = min(64, row1 - base);
     for (int q = 0; q < nq; ++q) {
@@ -220,18 +229,27 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
   DMTS_REQUIRE(m->atom_ws.reserve(need, s) == DMTS_OK, DMTS_E_OOM, "small model: workspace");
   float* e_atom = atom_energy ? atom_energy : m->atom_ws.as<float>();
   float* g = m->atom_ws.as<float>() + ((size_t)n + 63) / 64 * 64;
-  SmallParams P{m->p(m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts), m->p(m->o_W1), m->p(m->o_W1T),
+  SmallParams P{m->p(m->bf16 ? m->o_WbR : m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts),
+                m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
                 m->p(m->o_w2), m->rc, m->sigma, m->escale, m->Z};
   if (n > 0) {
     const int blocks = ceil_div(n, kWaves);
     { ProfScope ps(DMTS_K_SMALL_FORWARD, s);
-    k_small_forward<<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n, box,
-                                                   e_atom, g); }
+    if (m->bf16)
+      k_small_forward<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,
+                                                           box, e_atom, g);
+    else
+      k_small_forward<false><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,
+                                                            box, e_atom, g); }
     DMTS_CHECK_LAUNCH();
     if (forces) {
       { ProfScope ps(DMTS_K_SMALL_BACKWARD, s);
-      k_small_backward<<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n, box,
-                                                      g, forces); }
+      if (m->bf16)
+        k_small_backward<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species,
+                                                              n, box, g, forces);
+      else
+        k_small_backward<false><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species,
+                                                               n, box, g, forces); }
       DMTS_CHECK_LAUNCH();
     }
   }
