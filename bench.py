@@ -47,7 +47,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed outer steps (4 fs each)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="water4500", choices=["water4500", "water192"])
+    ap.add_argument("--workload", default="water4500",
+                    choices=["water4500", "water192", "solvated100k"])
+    ap.add_argument("--batch", action="store_true",
+                    help="instead of the throughput line: the batched form on 256 open "
+                         "molecules (energy+forces of both models) against a per-molecule loop")
+    ap.add_argument("--nve-ps", type=float, default=0.0,
+                    help="instead of the throughput line: run DMTS and Verlet for this many ps "
+                         "of NVE dynamics and report the drift of KE + E_reference")
     ap.add_argument("--n-inner", type=int, default=4)
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -82,6 +89,94 @@ def cpu_oracle(sy, ws, wl, n_inner, dt_inner):
                 Es=Es, Fs=Fs, El=El, Fl=Fl)
 
 
+def nve_drift(args, api, synth, sy, sp, v0, small, large):
+    """NVE runs of DMTS (dt_inner / n_inner) and of 1 fs Verlet (reference model): the
+    conserved energy H = KE + E_reference sampled every outer step, its least-squares slope
+    and the drift over the run per atom."""
+    import torch
+
+    out = {"mode": "nve-drift", "workload": args.workload, "n_atoms": sy.n_atoms,
+           "precision": args.precision, "ps": args.nve_ps}
+    for name, small_m, dt, n_in in (("dmts", small, args.dt_inner * args.n_inner, args.n_inner),
+                                    ("verlet", None, args.dt_inner, 1)):
+        st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt, n_in, 64, 128)
+        x, v = api.to_soa(sy.pos), api.to_soa(v0)
+        n_steps = int(round(args.nve_ps * 1000.0 / dt))
+        chunk = max(1, int(round(20.0 / dt)))   # sample every ~20 fs
+        t, H = [0.0], [st.step(x, v, small_m, large, 0)[3].item()]
+        done = 0
+        t0 = time.perf_counter()
+        while done < n_steps:
+            k = min(chunk, n_steps - done)
+            H.append(st.step(x, v, small_m, large, k)[3].item())
+            done += k
+            t.append(done * dt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t, H = np.array(t) / 1000.0, np.array(H)      # ps, eV
+        slope = np.polyfit(t, H, 1)[0]
+        out[name] = {"slope_eV_per_atom_per_ps": slope / sy.n_atoms,
+                     "drift_eV_per_atom": slope * args.nve_ps / sy.n_atoms,
+                     "max_dev_eV_per_atom": float(np.max(np.abs(H - H[0]))) / sy.n_atoms,
+                     "kT_eV": 8.617333262e-5 * 300.0, "steps": n_steps, "dt_fs": dt,
+                     "wall_s": wall, "fallbacks": st.fallbacks}
+        print(f"{name}: {n_steps} steps in {wall:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def batch_throughput(args, api, synth, small, large):
+    """256 open molecules (20-120 atoms): energy and forces of both models, batched in one
+    launch per kernel with an autotuned persistent grid, against a loop that evaluates one
+    molecule at a time.  Reports molecules/s and atom-evaluations/s of both."""
+    import torch
+
+    sy = synth.molecule_batch(256, 3)
+    pos = api.to_soa(sy.pos)
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    offs = torch.as_tensor(sy.sys_offsets, dtype=torch.int32, device="cuda")
+    pots = [api.Potential(m, sy.n_atoms, 0.0, 160, offs) for m in (small, large)]
+    tuned = [api.autotune(p, pos, sp, reps=3) for p in pots]
+    reps = max(args.steps, 3)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return max(ev0.elapsed_time(ev1), (time.perf_counter() - t0) * 1e3) / reps
+
+    def batched():
+        for p in pots:
+            p(pos, sp)
+
+    ones = [api.Potential(m, 128, 0.0, 160) for m in (small, large)]
+    mols = [(api.to_soa(sy.pos[a:b]), sp[a:b].contiguous())
+            for a, b in zip(sy.sys_offsets[:-1], sy.sys_offsets[1:])]
+
+    def loop():
+        for pm, sm in mols:
+            for p in ones:
+                p(pm, sm)
+
+    t_b = timed(batched)
+    t_l = timed(loop)
+    out = {"mode": "batch", "molecules": 256, "n_atoms": sy.n_atoms,
+           "precision": args.precision, "tuned_work_groups": {"fast": tuned[0][0],
+                                                             "reference": tuned[1][0]},
+           "batched_ms": round(t_b, 4), "per_molecule_loop_ms": round(t_l, 4),
+           "batched_molecules_per_s": round(256 / (t_b * 1e-3), 1),
+           "loop_molecules_per_s": round(256 / (t_l * 1e-3), 1),
+           "batched_atom_evals_per_s": round(sy.n_atoms / (t_b * 1e-3), 1),
+           "speedup": round(t_l / t_b, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -94,7 +189,8 @@ def main():
     from paper_2510_06562_amd import api, synth
 
     torch.cuda.set_device(0)
-    sy = synth.water_4500() if args.workload == "water4500" else synth.water_192()
+    sy = {"water4500": synth.water_4500, "water192": synth.water_192,
+          "solvated100k": synth.solvated_chain}[args.workload]()
     ws = synth.model_weights(synth.SMALL, synth.SMALL_SEED)
     wl = synth.model_weights(synth.LARGE, synth.LARGE_SEED)
     prec = api.PREC_BF16 if args.precision == "bf16" else api.PREC_FP32
@@ -105,6 +201,10 @@ def main():
     n_inner, dt_in = args.n_inner, args.dt_inner
     dt_out = n_inner * dt_in
     stream = torch.cuda.current_stream()
+    if args.nve_ps > 0:
+        return nve_drift(args, api, synth, sy, sp, v0, small, large)
+    if args.batch:
+        return batch_throughput(args, api, synth, small, large)
 
     # ---------------------------------------------------------------- GPU forces for the error
     pot_s = api.Potential(small, sy.n_atoms, sy.box, 64)

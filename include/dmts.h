@@ -109,6 +109,21 @@ dmts_status nnp_model_create(const nnp_model_desc* desc, const float* host_weigh
                              int64_t n_weights, nnp_model** out);
 void nnp_model_destroy(nnp_model* model);
 
+/* Launch shape.  The pair kernels of a model loop over groups of receivers in a
+ * grid-stride order with a fixed per-receiver arithmetic, so the number of work-groups
+ * changes speed only, never results.  nnp_model_set_grid sets it (0 = one work-group per
+ * group of receivers, the default; k > 0 = a persistent grid of at most k work-groups).
+ * nnp_autotune times one energy+force evaluation on the given system for each candidate
+ * (0, 256, 512, 1024, 2048, 4096; median of `reps` after a warm-up, HIP events on
+ * `stream`), keeps the fastest in the model and returns it in *chosen (host) with its time
+ * in *best_ms (host).  Blocking: synchronizes the stream and allocates scratch. */
+dmts_status nnp_model_set_grid(nnp_model* model, int32_t work_groups);
+dmts_status nnp_model_get_grid(nnp_model* model, int32_t* work_groups);
+dmts_status nnp_autotune(nnp_model* model, nnp_nlist* nl, const double* pos,
+                         const int32_t* species, int32_t n_atoms, double box,
+                         const int32_t* sys_offsets, int32_t n_sys, int32_t reps, void* stream,
+                         int32_t* chosen, double* best_ms);
+
 /* ---------------------------------------------------------------- neighbor lists
  * A full (both directions) list of ordered pairs {(i, j): j != i, |d_ij| < cutoff},
  * d_ij = x_j - x_i under the minimum-image convention of the cube (or plain difference

@@ -60,6 +60,10 @@ _SIGS = {
     "dmts_version": ([], ctypes.c_char_p),
     "nnp_model_create": ([ctypes.POINTER(_Desc), _P, _I64, ctypes.POINTER(_P)], _I32),
     "nnp_model_destroy": ([_P], None),
+    "nnp_model_set_grid": ([_P, _I32], _I32),
+    "nnp_model_get_grid": ([_P, ctypes.POINTER(_I32)], _I32),
+    "nnp_autotune": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _I32, _P, ctypes.POINTER(_I32),
+                      ctypes.POINTER(_D)], _I32),
     "nnp_nlist_create": ([_I32, _I64, _I32, ctypes.POINTER(_P)], _I32),
     "nnp_nlist_destroy": ([_P], None),
     "nnp_build_neighbors": ([_P, _P, _I32, _D, _P, _I32, _D, _P], _I32),
@@ -178,6 +182,16 @@ class Model:
     def handle(self):
         return self._h
 
+    @property
+    def grid(self) -> int:
+        g = ctypes.c_int32()
+        _check(lib().nnp_model_get_grid(self._h, ctypes.byref(g)))
+        return g.value
+
+    @grid.setter
+    def grid(self, work_groups: int):
+        _check(lib().nnp_model_set_grid(self._h, int(work_groups)))
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.nnp_model_destroy(self._h)
@@ -263,6 +277,22 @@ class Potential:
         self.nlist.build(pos_soa, self.box, self.model.desc.cutoff, self.sys_offsets, stream)
         return energy_forces(self.model, self.nlist, pos_soa, species, self.box,
                              self.sys_offsets, want_forces, atom_energy, stream)
+
+
+def autotune(potential: "Potential", pos_soa: torch.Tensor, species: torch.Tensor,
+             reps: int = 3, stream=None):
+    """Pick the pair kernels' work-group count for this system (see nnp_autotune); returns
+    (work_groups, best_ms).  Builds the potential's list from pos_soa first."""
+    potential.nlist.build(pos_soa, potential.box, potential.model.desc.cutoff,
+                          potential.sys_offsets, stream)
+    n = pos_soa.shape[1]
+    offs = potential.sys_offsets
+    n_sys = 1 if offs is None else offs.numel() - 1
+    g, t = ctypes.c_int32(), ctypes.c_double()
+    _check(lib().nnp_autotune(potential.model.handle, potential.nlist.handle, _ptr(pos_soa),
+                              _ptr(species), n, float(potential.box), _ptr(offs), n_sys, reps,
+                              _stream(stream), ctypes.byref(g), ctypes.byref(t)))
+    return g.value, t.value
 
 
 class NNPEnergy(torch.autograd.Function):

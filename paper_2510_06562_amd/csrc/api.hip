@@ -1,5 +1,6 @@
 // Library glue: error reporting, device buffers, model creation (weight re-layout) and the
 // energy/force entry point.
+#include <algorithm>
 #include <cstdarg>
 #include <cstring>
 #include <vector>
@@ -415,5 +416,82 @@ extern "C" dmts_status dmts_prof_read(int32_t kernel_class, double* total_ms, in
   }
   *total_ms = t;
   *launches = (int64_t)dmts::g_prof[kernel_class].size();
+  return DMTS_OK;
+}
+
+extern "C" dmts_status nnp_model_set_grid(nnp_model* h, int32_t work_groups) {
+  Model* m = reinterpret_cast<Model*>(h);
+  DMTS_REQUIRE(m && work_groups >= 0, DMTS_E_ARG, "nnp_model_set_grid: bad argument");
+  m->grid = work_groups;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status nnp_model_get_grid(nnp_model* h, int32_t* work_groups) {
+  Model* m = reinterpret_cast<Model*>(h);
+  DMTS_REQUIRE(m && work_groups, DMTS_E_ARG, "nnp_model_get_grid: bad argument");
+  *work_groups = m->grid;
+  return DMTS_OK;
+}
+
+// Times one energy+force evaluation per candidate work-group count (median of `reps`
+// after one warm-up) with HIP events on `stream`, keeps the fastest in the model.
+extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* pos,
+                                    const int32_t* species, int32_t n_atoms, double box,
+                                    const int32_t* sys_offsets, int32_t n_sys, int32_t reps,
+                                    void* stream, int32_t* chosen, double* best_ms) {
+  Model* m = reinterpret_cast<Model*>(h);
+  NList* nl = reinterpret_cast<NList*>(nlh);
+  DMTS_REQUIRE(m && nl && reps >= 1 && reps <= 64, DMTS_E_ARG, "nnp_autotune: bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = sys_offsets ? n_sys : 1;
+  double* energy = nullptr;
+  float* forces = nullptr;
+  DMTS_HIP(hipMalloc(&energy, sizeof(double) * ns));
+  if (hipMalloc(&forces, sizeof(float) * 3 * (size_t)(n_atoms > 0 ? n_atoms : 1)) != hipSuccess) {
+    (void)hipFree(energy);
+    dmts::set_error("nnp_autotune: allocation failed");
+    return DMTS_E_OOM;
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int32_t cands[] = {0, 256, 512, 1024, 2048, 4096};
+  const int32_t saved = m->grid;
+  int32_t best = saved;
+  double best_t = 1e300;
+  dmts_status st = DMTS_OK;
+  for (int32_t c : cands) {
+    m->grid = c;
+    std::vector<double> t;
+    for (int r = 0; r <= reps && st == DMTS_OK; ++r) {
+      (void)hipEventRecord(e0, s);
+      st = dmts::energy_forces(m, nl, pos, species, n_atoms, box, sys_offsets, n_sys, energy,
+                               forces, nullptr, s);
+      (void)hipEventRecord(e1, s);
+      if (st != DMTS_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = DMTS_E_HIP;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) t.push_back(ms);   // the first run warms up
+    }
+    if (st != DMTS_OK) break;
+    std::sort(t.begin(), t.end());
+    const double med = t[t.size() / 2];
+    if (med < best_t) {
+      best_t = med;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(energy);
+  (void)hipFree(forces);
+  m->grid = st == DMTS_OK ? best : saved;
+  if (st != DMTS_OK) return st;
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = best_t;
   return DMTS_OK;
 }

@@ -99,8 +99,12 @@ struct Model {
   size_t h_WoT = 0, h_U2T = 0, h_W2hs = 0, h_U1T = 0;     // reverse chain layers
   size_t o_WbR = 0, o_W1R = 0, o_W1TR = 0;                // kind 0: bf16-valued floats
   const __bf16* p16(size_t off) const { return params16.as<__bf16>() + off; }
+  // launch: work-groups of the pair kernels (0 = one per group of receivers); the pair
+  // kernels loop over receivers in a grid-stride order, so any count gives the same bits
+  int32_t grid = 0;
   // workspace
   DevBuf atom_ws, pair_ws, sys_ws;
+  int launch_grid(int natural) const { return grid > 0 && grid < natural ? grid : natural; }
   const float* p(size_t off) const { return params.as<float>() + off; }
 };
 

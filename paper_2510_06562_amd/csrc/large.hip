@@ -122,9 +122,11 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int i = blockIdx.x * kAtomsPerWg + (w >> 1);
+  const int n_wg = (n + kAtomsPerWg - 1) / kAtomsPerWg;
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+  const int i = wg * kAtomsPerWg + (w >> 1);
+  if (i >= n) continue;
   const int hb = 4 * (w & 1);   // first channel block of this wave's half
-  if (i >= n) return;
   const int zi_s = species[i];
   float base[4];
 #pragma unroll
@@ -225,6 +227,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     qi[2 * F_L + c] = mm[4] * mm[4] + mm[5] * mm[5] + mm[6] * mm[6] +
                       2.0f * (mm[7] * mm[7] + mm[8] * mm[8] + mm[9] * mm[9]);
   }
+  }  // grid-stride loop over work-groups of atoms
 }
 
 template <int LAYER, bool BF16>
@@ -254,9 +257,11 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int i = blockIdx.x * kAtomsPerWg + (w >> 1);
+  const int n_wg = (n + kAtomsPerWg - 1) / kAtomsPerWg;
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+  const int i = wg * kAtomsPerWg + (w >> 1);
+  if (i >= n) continue;
   const int half = w & 1, hb = 4 * half;
-  if (i >= n) return;
   float* sd = sD[w];
   float* vh = v + (size_t)half * 3 * cap;   // this half's share of v_ij
   const int zi_s = species[i];
@@ -427,6 +432,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     for (int k = 0; k < kTile; ++k) t += sR[w][k][lane];
     RS[(size_t)i * 2 * F_L + 16 * hb + lane] = t;
   }
+  }  // grid-stride loop over work-groups of atoms
 }
 
 // S_j = sum over the rows of j of dA at the reverse positions (the sender sums).
@@ -524,7 +530,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
     A.h_U1T = m->p16(m->h_U1T);
   }
   const int blocks = ceil_div(n, kWaves);
-  const int pblocks = ceil_div(n, kAtomsPerWg);
+  const int pblocks = m->launch_grid(ceil_div(n, kAtomsPerWg));
   // the whole evaluation, instantiated for the FP32 and the BF16 form
   auto run = [&](auto bf_tag) -> dmts_status {
     constexpr bool BF = decltype(bf_tag)::value;

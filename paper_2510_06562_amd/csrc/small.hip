@@ -107,8 +107,10 @@ k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int e = threadIdx.x; e < P.Z * F_S; e += blockDim.x) s_Ts[e / F_S][e % F_S] = P.Ts[e];
   __syncthreads();
-  const int i = blockIdx.x * kWaves + w;
-  if (i >= n) return;
+  const int n_wg = (n + kWaves - 1) / kWaves;
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+  const int i = wg * kWaves + w;
+  if (i >= n) continue;
   PairStage& st = stage[w];
   const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
@@ -149,6 +151,7 @@ k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* 
   for (int k = 0; k < F_S; ++k) g = fmaf(P.W1[k * F_S + c], s_vec[w][k], g);
   g_out[(size_t)i * F_S + c] = g;
   if (lane == 0) atom_e[i] = e_i;
+  }  // grid-stride loop over work-groups of atoms
 }
 
 template <bool BF16>
@@ -165,8 +168,10 @@ k_small_backward(SmallParams P, const int32_t* __restrict__ offs, const int32_t*
     s_Td[e / F_S][e % F_S] = P.Td[e];
   }
   __syncthreads();
-  const int i = blockIdx.x * kWaves + w;
-  if (i >= n) return;
+  const int n_wg = (n + kWaves - 1) / kWaves;
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+  const int i = wg * kWaves + w;
+  if (i >= n) continue;
   PairStage& st = stage[w];
   const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
@@ -216,6 +221,7 @@ k_small_backward(SmallParams P, const int32_t* __restrict__ offs, const int32_t*
     forces[n + i] = fy;
     forces[2 * n + i] = fz;
   }
+  }  // grid-stride loop over work-groups of atoms
 }
 
 }  // namespace
@@ -233,7 +239,7 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
                 m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
                 m->p(m->o_w2), m->rc, m->sigma, m->escale, m->Z};
   if (n > 0) {
-    const int blocks = ceil_div(n, kWaves);
+    const int blocks = m->launch_grid(ceil_div(n, kWaves));
     { ProfScope ps(DMTS_K_SMALL_FORWARD, s);
     if (m->bf16)
       k_small_forward<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,

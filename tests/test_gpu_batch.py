@@ -1,0 +1,87 @@
+"""The batched form: 256 uneven open molecules (about 18,000 atoms) evaluated together,
+per-molecule energies against the FP64 oracle, launch-shape invariance of the persistent
+grid, the autotuner, and equality with a per-molecule loop."""
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu_common import oracle_ef, rel_rmse, say, system, weights, SPECS
+from paper_2510_06562_amd import api
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(sy):
+    pos = api.to_soa(sy.pos)
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    offs = torch.as_tensor(sy.sys_offsets, dtype=torch.int32, device="cuda")
+    return pos, sp, offs
+
+
+@pytest.mark.parametrize("prec,ftol", [(api.PREC_FP32, 1e-5), (api.PREC_BF16, 1e-2)])
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_batch256_matches_oracle_per_molecule(which, prec, ftol):
+    say(f"batch256 {which} prec={prec}")
+    sy = system("batch256")
+    pos, sp, offs = _dev(sy)
+    model = api.Model.from_spec(SPECS[which], weights(which), precision=prec)
+    pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
+    E, F = pot(pos, sp)
+    E0, F0, _ = oracle_ef("batch256", which)
+    sizes = np.diff(sy.sys_offsets)
+    assert E.numel() == 256
+    err_e = np.abs(E.cpu().numpy() - E0) / sizes
+    err_f = rel_rmse(api.from_soa(F), F0)
+    say(f"  max |dE|/atom {err_e.max():.2e}, force rel RMSE {err_f:.2e}")
+    assert err_f <= ftol
+    assert err_e.max() <= (1e-7 if prec == api.PREC_FP32 else 2e-4)
+
+
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_persistent_grid_does_not_change_bits(which):
+    say(f"grid invariance {which}")
+    sy = system("batch256")
+    pos, sp, offs = _dev(sy)
+    model = api.Model.from_spec(SPECS[which], weights(which))
+    pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
+    E0, F0 = pot(pos, sp)
+    for g in (1, 7, 256, 1024):
+        model.grid = g
+        E, F = pot(pos, sp)
+        assert torch.equal(E, E0) and torch.equal(F, F0), g
+    model.grid = 0
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    say("autotune")
+    sy = system("batch256")
+    pos, sp, offs = _dev(sy)
+    model = api.Model.from_spec(SPECS["large"], weights("large"), precision=api.PREC_BF16)
+    pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
+    E0, F0 = pot(pos, sp)
+    g, t = api.autotune(pot, pos, sp, reps=2)
+    assert g in (0, 256, 512, 1024, 2048, 4096) and t > 0
+    assert model.grid == g
+    E, F = pot(pos, sp)
+    assert torch.equal(E, E0) and torch.equal(F, F0)
+
+
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_batched_equals_per_molecule_loop(which):
+    """Evaluating each molecule alone gives the same bits as the batched launch."""
+    say(f"batched vs loop {which}")
+    sy = system("batch256")
+    pos, sp, offs = _dev(sy)
+    model = api.Model.from_spec(SPECS[which], weights(which))
+    pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
+    E, F = pot(pos, sp)
+    F = F.cpu()
+    one = api.Potential(model, 200, 0.0, 160)
+    for m in range(0, 256, 17):
+        a, b = int(sy.sys_offsets[m]), int(sy.sys_offsets[m + 1])
+        pm = api.to_soa(sy.pos[a:b])
+        sm = sp[a:b].contiguous()
+        Em, Fm = one(pm, sm)
+        assert Em.item() == E[m].item()
+        assert torch.equal(Fm.cpu(), F[:, a:b])
