@@ -42,6 +42,26 @@ PAIR_FLOPS = {"pair2_backward": 128 * (4 * 32 + 40), "pair1_backward": 128 * (4 
               "small_backward": 64 * (4 * 16 + 56), "small_forward": 64 * (2 * 16 + 14)}
 
 
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary, or None when
+    the summary is for another workload or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+    if rec is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2510_06562_amd", "csrc")
+    src = "".join(open(os.path.join(csrc, f)).read() for f in ("large.hip", "small.hip", "common.h"))
+    if hashlib.sha1(src.encode()).hexdigest()[:16] != rec["hash"]:
+        return None
+    return rec["bytes"].get(kernel)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +69,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="water4500",
                     choices=["water4500", "water192", "solvated100k"])
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the throughput line: time a plain device-to-device copy "
+                         "of this many bytes (the reference for hardware byte counters)")
     ap.add_argument("--batch", action="store_true",
                     help="instead of the throughput line: the batched form on 256 open "
                          "molecules (energy+forces of both models) against a per-molecule loop")
@@ -189,6 +212,20 @@ def main():
     from paper_2510_06562_amd import api, synth
 
     torch.cuda.set_device(0)
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"mode": "copy", "bytes": args.copy_bytes,
+                          "GBps_read_plus_write": 2 * args.copy_bytes / dt / 1e9}), flush=True)
+        return
     sy = {"water4500": synth.water_4500, "water192": synth.water_192,
           "solvated100k": synth.solvated_chain}[args.workload]()
     ws = synth.model_weights(synth.SMALL, synth.SMALL_SEED)
@@ -276,9 +313,11 @@ def main():
         pairs = pairs_small if dom.startswith("small") else pairs_large
         flops = PAIR_FLOPS[dom] * pairs
         achieved = flops / avg_s / 1e12
+        traffic = measured_traffic(args.workload, args.precision, dom)
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                    "hbm_frac_of_8TBps": (round(traffic / avg_s / 8e12, 4) if traffic else None),
                     "avg_launch_us": round(avg_s * 1e6, 2), "pairs_per_launch": pairs,
                     "flops_per_pair": PAIR_FLOPS[dom]}
 

@@ -50,6 +50,7 @@ inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) 
 
 // ------------------------------------------------------------------ neighbor list
 constexpr int kNlistRowCap = 256;   // most neighbors one atom may have
+constexpr int kSmallPairCap = 64;   // most pairs one atom may have inside the fast cutoff
 struct NList {
   int32_t max_atoms = 0;
   int64_t max_pairs = 0;

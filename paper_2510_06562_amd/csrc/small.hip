@@ -4,32 +4,42 @@
 //                                                  W_pair folded with the embedding table)
 //   m_ij = f_c(r_ij) SiLU(a_ij),  h_i = sum_j m_ij,  E_i = s_E w2 . SiLU(W1 h_i)
 //
-// Two kernels, one wavefront per receiver atom, one hidden channel per lane (F = 64):
-//   k_small_forward:  pair messages summed into h_i, the readout, E_i and the adjoint
-//                     g_i = dE/dh_i (stored, F floats per atom).
-//   k_small_backward: recomputes every pair's features (nothing per pair is stored) and
-//                     forms F_i = sum_j (s_ij + s_ji) d_ij / r_ij with
-//                     s_ij = g_i . dm_ij/dr, where the reverse message m_ji differs from
-//                     m_ij only by the swapped species tables, so one W_r b(r) serves both.
-// Pair geometry (b, b', f_c, f_c', unit vector) is computed lane-per-pair for 64 pairs at
-// a time and staged in LDS; the channel loop then reads it as wave-uniform broadcasts.
-// Displacements are minimum-image differences of the float64 positions, rounded to float.
-// BF16 form: the operands of the two contractions (W_r with b or b', W1 with h or its
-// adjoint) are rounded to bfloat16 values (nearest even) and accumulated in FP32; the
-// kernels run the same code with rounded weights and a rounding step on the activations.
+// Two kernels, one wavefront per receiver atom, pairs in 16-pair MFMA tiles:
+//   k_small_fwd: walks the receiver's neighbor-list row (which may come from a longer
+//     cutoff), computes the float geometry at the current positions, and compacts the pairs
+//     inside the cutoff with a ballot into LDS (and into a per-atom table for the reverse
+//     pass).  a = b W_r runs on MFMA (16 pairs x 64 channels), the messages are summed in
+//     registers, then the 64 -> 64 -> 1 readout gives E_i and the adjoint g_i = dE/dh_i.
+//   k_small_bwd: per tile of the compact table, the transposed product a^T = W_r b^T (and
+//     W_r b'^T) puts one pair on each lane and 16 channels in its registers; both messages
+//     of the pair (j -> i and i -> j differ only by the swapped species tables) give
+//     s_ij + s_ji = dE/dr_ij as an in-lane channel sum, and F_i = sum_j (s_ij + s_ji) d/r.
+// Rows are sorted by sender, so the sums do not depend on the list's cutoff or padding.
+//
+// MFMA 16x16x4 f32:  A operand lane l: A[l%16][k0 + l/16]; B: B[k0 + l/16][l%16];
+//                    D register r: D[4 (l/16) + r][l%16].
+// BF16 form: v_mfma_f32_16x16x16_bf16 (A: A[l%16][4 (l/16) + e], B: B[4 (l/16) + e][l%16],
+// e = 0..3) with b, b' and W_r rounded to bfloat16; the readout uses bfloat16-valued W1 and
+// activations with FP32 accumulation.  Geometry and elementwise math are FP32.
 #include "common.h"
 
 namespace dmts {
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kWaves = 4;
-constexpr int K_S = 16;   // radial functions
-constexpr int F_S = 64;   // hidden width
+constexpr int K_S = 16;    // radial functions
+constexpr int F_S = 64;    // hidden width
 constexpr int Z_MAX = 8;
+constexpr int kCap = kSmallPairCap;   // most pairs one receiver may have inside the cutoff
+constexpr int kTile = 16;
+constexpr int kLdW = 20;   // LDS stride of W_r rows [c][k]
 
 struct SmallParams {
-  const float* WbT;  // [K][F]
+  const float* WbT;  // [K][F]  (bfloat16-valued in the BF16 form)
   const float* Td;   // [Z][F]
   const float* Ts;   // [Z][F]
   const float* W1;   // [F][F]  z_c = sum_e W1[c][e] h_e
@@ -40,188 +50,265 @@ struct SmallParams {
 };
 
 __device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
+__device__ __forceinline__ short bf16bits(float x) { return __builtin_bit_cast(short, (__bf16)x); }
 
-struct PairStage {
-  float b[64][K_S];
-  float db[64][K_S];
-  float fc[64], dfc[64];
-  float rx[64], ry[64], rz[64];
-  int z[64], j[64];
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+  return v;
+}
+
+struct SmallLds {
+  float W[F_S * kLdW];        // W_r [c][k]
+  float Td[Z_MAX][F_S], Ts[Z_MAX][F_S];
+  float W1[F_S][F_S + 1];     // W1 [c][e]
 };
 
-// Geometry of this lane's pair p (row entry) for receiver i; invalid entries get f_c = 0
-// and b = 0 so that they contribute nothing.
-__device__ __forceinline__ void stage_pair(PairStage& st, int lane, int p, int row1,
-                                           const int32_t* nbr, const double* pos, int n,
-                                           double box, double inv_box, double xi, double yi,
-                                           double zi, const int32_t* species,
-                                           const SmallParams& P, bool need_grad,
-                                           bool bf16) {
-  int j = p < row1 ? nbr[p] : -1;
-  float r = 0.f, fc = 0.f, dfc = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
-  bool valid = false;
-  if (j >= 0) {
-    float dx = static_cast<float>(minimage(pos[j] - xi, box, inv_box));
-    float dy = static_cast<float>(minimage(pos[n + j] - yi, box, inv_box));
-    float dz = static_cast<float>(minimage(pos[2 * n + j] - zi, box, inv_box));
-    r = sqrtf(dx * dx + dy * dy + dz * dz);
-    valid = r < P.rc;
-    if (valid) {
-      float ang = 3.14159265358979f * r / P.rc;
-      float sn, cs;
-      __sincosf(ang, &sn, &cs);
-      fc = 0.5f * (cs + 1.0f);
-      dfc = -0.5f * 3.14159265358979f / P.rc * sn;
-      float inv = 1.0f / r;
-      ux = dx * inv;
-      uy = dy * inv;
-      uz = dz * inv;
-    }
-  }
-  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
-#pragma unroll
-  for (int k = 0; k < K_S; ++k) {
-    float x = r - P.sigma * k;   // mu_k = k r_c/(K-1) = k sigma
-    float bk = valid ? __expf(-0.5f * x * x * inv_s2) : 0.f;
-    const float dbk = -x * inv_s2 * bk;
-    st.b[lane][k] = bf16 ? bf16r(bk) : bk;
-    if (need_grad) st.db[lane][k] = bf16 ? bf16r(dbk) : dbk;
-  }
-  st.fc[lane] = fc;
-  st.dfc[lane] = dfc;
-  st.rx[lane] = ux;
-  st.ry[lane] = uy;
-  st.rz[lane] = uz;
-  st.j[lane] = valid ? j : -1;
-  st.z[lane] = valid ? species[j] : 0;
-}
-
-template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64)
-k_small_forward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-                const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
-                double box, float* __restrict__ atom_e, float* __restrict__ g_out) {
-  __shared__ PairStage stage[kWaves];
-  __shared__ float s_Ts[Z_MAX][F_S];
-  __shared__ float s_vec[kWaves][F_S];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int e = threadIdx.x; e < P.Z * F_S; e += blockDim.x) s_Ts[e / F_S][e % F_S] = P.Ts[e];
-  __syncthreads();
-  const int n_wg = (n + kWaves - 1) / kWaves;
-  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
-  const int i = wg * kWaves + w;
-  if (i >= n) continue;
-  PairStage& st = stage[w];
-  const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
-  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-  const int c = lane;
-  float wb[K_S];
-#pragma unroll
-  for (int k = 0; k < K_S; ++k) wb[k] = P.WbT[k * F_S + c];
-  const float td = P.Td[species[i] * F_S + c];
-  float h = 0.f;
-  const int row0 = offs[i], row1 = offs[i + 1];
-  for (int base = row0; base < row1; base += 64) {
-    stage_pair(st, lane, base + lane, row1, nbr, pos, n, box, inv_box, xi, yi, zi, species, P,
-               false, BF16);
-    wave_sync();
-    const int nq = min(64, row1 - base);
-    for (int q = 0; q < nq; ++q) {
-      if (st.j[q] < 0) continue;   // wave-uniform
-      float a = td + s_Ts[st.z[q]][c];
-#pragma unroll
-      for (int k = 0; k < K_S; ++k) a = fmaf(wb[k], st.b[q][k], a);
-      h = fmaf(st.fc[q], silu_f(a), h);
-    }
-    wave_sync();
-  }
-  // readout: z = W1 h, E_i = s_E w2 . SiLU(z), and g = dE/dh = W1^T (s_E w2 * SiLU'(z))
-  s_vec[w][c] = BF16 ? bf16r(h) : h;
-  wave_sync();
-  float z = 0.f;
-  for (int e = 0; e < F_S; ++e) z = fmaf(P.W1T[e * F_S + c], s_vec[w][e], z);
-  float y, dy;
-  silu_and_grad(z, y, dy);
-  const float w2 = P.w2[c];
-  float e_i = wave_sum(w2 * y) * P.escale;
-  wave_sync();
-  s_vec[w][c] = BF16 ? bf16r(P.escale * w2 * dy) : P.escale * w2 * dy;
-  wave_sync();
-  float g = 0.f;
-  for (int k = 0; k < F_S; ++k) g = fmaf(P.W1[k * F_S + c], s_vec[w][k], g);
-  g_out[(size_t)i * F_S + c] = g;
-  if (lane == 0) atom_e[i] = e_i;
-  }  // grid-stride loop over work-groups of atoms
-}
-
-template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64)
-k_small_backward(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-                 const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
-                 double box, const float* __restrict__ g, float* __restrict__ forces) {
-  __shared__ PairStage stage[kWaves];
-  __shared__ float s_Ts[Z_MAX][F_S];
-  __shared__ float s_Td[Z_MAX][F_S];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+__device__ void load_params(SmallLds& L, const SmallParams& P) {
+  for (int e = threadIdx.x; e < K_S * F_S; e += blockDim.x)
+    L.W[(e % F_S) * kLdW + e / F_S] = P.WbT[e];
   for (int e = threadIdx.x; e < P.Z * F_S; e += blockDim.x) {
-    s_Ts[e / F_S][e % F_S] = P.Ts[e];
-    s_Td[e / F_S][e % F_S] = P.Td[e];
+    L.Td[e / F_S][e % F_S] = P.Td[e];
+    L.Ts[e / F_S][e % F_S] = P.Ts[e];
   }
+  for (int e = threadIdx.x; e < F_S * F_S; e += blockDim.x) L.W1[e / F_S][e % F_S] = P.W1[e];
+}
+
+// 16 x 16 tile over K = 16 radial functions.  bk(e) / wk(e) give the lane's radial and
+// weight operands for k = 4 e + g (FP32, e = step) or k = 4 g + e (BF16, e = element);
+// b_is_a selects which of the two is the A operand.
+template <bool BF16, class BK, class WK>
+__device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (BF16) {
+    s16x4 x, y;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[e] = bf16bits(bk(e));
+      y[e] = bf16bits(wk(e));
+    }
+    acc = b_is_a ? __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0)
+                 : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(y, x, acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc = b_is_a ? __builtin_amdgcn_mfma_f32_16x16x4f32(bk(s), wk(s), acc, 0, 0, 0)
+                   : __builtin_amdgcn_mfma_f32_16x16x4f32(wk(s), bk(s), acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <bool BF16>
+__global__ void __launch_bounds__(kWaves * 64)
+k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
+            const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
+            double box, float* __restrict__ atom_e, float* __restrict__ g_out,
+            int32_t* __restrict__ ell_j, float4* __restrict__ ell_g, int32_t* __restrict__ ell_n,
+            uint32_t* __restrict__ flags) {
+  __shared__ SmallLds L;
+  __shared__ int sZ[kWaves][kCap];
+  __shared__ float4 sG[kWaves][kCap];
+  __shared__ float sVec[kWaves][F_S];
+  load_params(L, P);
   __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
+  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const int n_wg = (n + kWaves - 1) / kWaves;
   for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
-  const int i = wg * kWaves + w;
-  if (i >= n) continue;
-  PairStage& st = stage[w];
-  const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
-  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-  const int c = lane;
-  float wb[K_S];
-#pragma unroll
-  for (int k = 0; k < K_S; ++k) wb[k] = P.WbT[k * F_S + c];
-  const int zi_s = species[i];
-  const float td_i = s_Td[zi_s][c], ts_i = s_Ts[zi_s][c];
-  const float g_i = g[(size_t)i * F_S + c];
-  float fx = 0.f, fy = 0.f, fz = 0.f;
-  const int row0 = offs[i], row1 = offs[i + 1];
-  for (int base = row0; base < row1; base += 64) {
-    stage_pair(st, lane, base + lane, row1, nbr, pos, n, box, inv_box, xi, yi, zi, species, P,
-               true, BF16);
-    wave_sync();
-    const int nq = min(64, row1 - base);
-    for (int q = 0; q < nq; ++q) {
-      const int j = st.j[q];
-      if (j < 0) continue;
-      const int zj = st.z[q];
-      float gb = 0.f, gd = 0.f;
-#pragma unroll
-      for (int k = 0; k < K_S; ++k) {
-        gb = fmaf(wb[k], st.b[q][k], gb);
-        gd = fmaf(wb[k], st.db[q][k], gd);
+    const int i = wg * kWaves + w;
+    if (i >= n) continue;
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    // 1. pairs inside the cutoff, in row order, compacted into LDS and the table
+    int cnt = 0;
+    const int row0 = offs[i], row1 = offs[i + 1];
+    for (int base = row0; base < row1; base += 64) {
+      const int p = base + lane;
+      const int j = p < row1 ? nbr[p] : -1;
+      float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
+      bool ok = false;
+      if (j >= 0) {
+        dx = static_cast<float>(minimage(pos[j] - xi, box, inv_box));
+        dy = static_cast<float>(minimage(pos[n + j] - yi, box, inv_box));
+        dz = static_cast<float>(minimage(pos[2 * n + j] - zi, box, inv_box));
+        r = sqrtf(dx * dx + dy * dy + dz * dz);
+        ok = r < P.rc;
       }
-      const float a1 = gb + td_i + s_Ts[zj][c];   // message j -> i
-      const float a2 = gb + s_Td[zj][c] + ts_i;   // message i -> j
-      float s1, ds1, s2, ds2;
-      silu_and_grad(a1, s1, ds1);
-      silu_and_grad(a2, s2, ds2);
-      const float g_j = g[(size_t)j * F_S + c];
-      const float fc = st.fc[q], dfc = st.dfc[q];
-      const float t = g_i * (dfc * s1 + fc * ds1 * gd) + g_j * (dfc * s2 + fc * ds2 * gd);
-      fx = fmaf(t, st.rx[q], fx);
-      fy = fmaf(t, st.ry[q], fy);
-      fz = fmaf(t, st.rz[q], fz);
+      const uint64_t mask = __ballot(ok);
+      const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+      if (ok && k < kCap) {
+        const float4 gv = make_float4(dx, dy, dz, r);
+        sZ[w][k] = species[j];
+        sG[w][k] = gv;
+        ell_j[(size_t)i * kCap + k] = j;
+        ell_g[(size_t)i * kCap + k] = gv;
+      }
+      cnt += __popcll(mask);
+    }
+    if (cnt > kCap) {
+      if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+      cnt = kCap;
+    }
+    if (lane == 0) ell_n[i] = cnt;
+    wave_sync();
+    // 2. messages on MFMA tiles, summed over pairs in registers
+    const int zi_s = species[i];
+    float hacc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int t0 = 0; t0 < cnt; t0 += kTile) {
+      const int pc = t0 + cl;                       // pair of the A operand
+      const bool vp = pc < cnt;
+      const float rp = vp ? sG[w][pc].w : 0.f;
+      auto bk = [&](int e) {
+        const int kk = BF16 ? 4 * g + e : 4 * e + g;
+        const float x = rp - P.sigma * kk;
+        return vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+      };
+      float fc[4];
+      int zz[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = t0 + 4 * g + r;
+        const bool v = q < cnt;
+        const float rq = v ? sG[w][q].w : 0.f;
+        fc[r] = v ? 0.5f * (__cosf(3.14159265358979f * rq / P.rc) + 1.0f) : 0.f;
+        zz[r] = v ? sZ[w][q] : zi_s;
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = 16 * b + cl;
+        auto wk = [&](int e) {
+          const int kk = BF16 ? 4 * g + e : 4 * e + g;
+          return L.W[c * kLdW + kk];
+        };
+        const f32x4 acc = radial_mfma<BF16>(bk, wk, true);
+        const float td = L.Td[zi_s][c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float a = acc[r] + td + L.Ts[zz[r]][c];
+          hacc[b] = fmaf(fc[r], silu_f(a), hacc[b]);
+        }
+      }
+    }
+    // h[c] for c = 16 b + cl: add the four pair groups
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      hacc[b] += __shfl_xor(hacc[b], 16, 64);
+      hacc[b] += __shfl_xor(hacc[b], 32, 64);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) sVec[w][16 * b + cl] = BF16 ? bf16r(hacc[b]) : hacc[b];
     }
     wave_sync();
+    // 3. readout, channel c = lane: z = W1 h, E_i = s_E w2 . SiLU(z), g = W1^T (s_E w2 SiLU'(z))
+    const int c = lane;
+    float z = 0.f;
+    for (int e = 0; e < F_S; ++e) z = fmaf(L.W1[c][e], sVec[w][e], z);
+    float y, dy;
+    silu_and_grad(z, y, dy);
+    const float w2 = P.w2[c];
+    const float e_i = wave_sum(w2 * y) * P.escale;
+    wave_sync();
+    sVec[w][c] = BF16 ? bf16r(P.escale * w2 * dy) : P.escale * w2 * dy;
+    wave_sync();
+    float gi = 0.f;
+    for (int k = 0; k < F_S; ++k) gi = fmaf(L.W1[k][c], sVec[w][k], gi);
+    g_out[(size_t)i * F_S + c] = gi;
+    if (lane == 0) atom_e[i] = e_i;
+    wave_sync();
   }
-  fx = wave_sum(fx);
-  fy = wave_sum(fy);
-  fz = wave_sum(fz);
-  if (lane == 0) {
-    forces[i] = fx;
-    forces[n + i] = fy;
-    forces[2 * n + i] = fz;
+}
+
+template <bool BF16>
+__global__ void __launch_bounds__(kWaves * 64)
+k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
+            const float* __restrict__ g, const int32_t* __restrict__ ell_j,
+            const float4* __restrict__ ell_g, const int32_t* __restrict__ ell_n,
+            float* __restrict__ forces) {
+  __shared__ SmallLds L;
+  load_params(L, P);
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, cl = lane & 15;
+  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
+  const int n_wg = (n + kWaves - 1) / kWaves;
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+    const int i = wg * kWaves + w;
+    if (i >= n) continue;
+    const int cnt = ell_n[i];
+    const int zi_s = species[i];
+    // the lane's 16 channels: c = 16 b + 4 gq + r
+    float gi[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float4 t = *reinterpret_cast<const float4*>(g + (size_t)i * F_S + 16 * b + 4 * gq);
+      gi[4 * b] = t.x;
+      gi[4 * b + 1] = t.y;
+      gi[4 * b + 2] = t.z;
+      gi[4 * b + 3] = t.w;
+    }
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    for (int t0 = 0; t0 < cnt; t0 += kTile) {
+      const int pc = t0 + cl;            // the lane's pair
+      const bool vp = pc < cnt;
+      const int j = vp ? ell_j[(size_t)i * kCap + pc] : i;
+      const float4 gv = vp ? ell_g[(size_t)i * kCap + pc] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float rp = gv.w;
+      float sn, cs;
+      __sincosf(3.14159265358979f * rp / P.rc, &sn, &cs);
+      const float fc = vp ? 0.5f * (cs + 1.0f) : 0.f;
+      const float dfc = vp ? -0.5f * 3.14159265358979f / P.rc * sn : 0.f;
+      const int zj = species[j];
+      auto bk = [&](int e) {
+        const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
+        const float x = rp - P.sigma * kk;
+        return vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+      };
+      auto dbk = [&](int e) {
+        const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
+        const float x = rp - P.sigma * kk;
+        return vp ? -x * inv_s2 * __expf(-0.5f * x * x * inv_s2) : 0.f;
+      };
+      float S = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        auto wk = [&](int e) {
+          const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
+          return L.W[(16 * b + cl) * kLdW + kk];
+        };
+        const f32x4 gb = radial_mfma<BF16>(bk, wk, false);
+        const f32x4 gd = radial_mfma<BF16>(dbk, wk, false);
+        const float4 gj = *reinterpret_cast<const float4*>(g + (size_t)j * F_S + 16 * b + 4 * gq);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = 16 * b + 4 * gq + r;
+          const float a1 = gb[r] + L.Td[zi_s][c] + L.Ts[zj][c];   // message j -> i
+          const float a2 = gb[r] + L.Td[zj][c] + L.Ts[zi_s][c];   // message i -> j
+          float s1, ds1, s2, ds2;
+          silu_and_grad(a1, s1, ds1);
+          silu_and_grad(a2, s2, ds2);
+          const float gjr = r == 0 ? gj.x : r == 1 ? gj.y : r == 2 ? gj.z : gj.w;
+          S += gi[4 * b + r] * (dfc * s1 + fc * ds1 * gd[r]) + gjr * (dfc * s2 + fc * ds2 * gd[r]);
+        }
+      }
+      S += __shfl_xor(S, 16, 64);
+      S += __shfl_xor(S, 32, 64);
+      const float ir = vp ? 1.0f / rp : 0.f;
+      fx = fmaf(S * ir, gv.x, fx);
+      fy = fmaf(S * ir, gv.y, fy);
+      fz = fmaf(S * ir, gv.z, fz);
+    }
+    // sum over the 16 pair columns (every group holds the same values)
+    fx = row16_sum(fx);
+    fy = row16_sum(fy);
+    fz = row16_sum(fz);
+    if (lane == 0) {
+      forces[i] = fx;
+      forces[n + i] = fy;
+      forces[2 * n + i] = fz;
+    }
   }
-  }  // grid-stride loop over work-groups of atoms
 }
 
 }  // namespace
@@ -230,11 +317,19 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
                                 int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
                                 double* energy, float* forces, float* atom_energy, hipStream_t s) {
   DMTS_REQUIRE(m->K == K_S && m->F == F_S, DMTS_E_ARG, "small model: unsupported shape");
-  // workspace: atom energies [n] + adjoint g [n][F]
-  size_t need = sizeof(float) * ((size_t)n * (1 + F_S) + 64);
+  // workspace: compact pair table [n][kCap] (geometry, senders, counts), adjoint g [n][F],
+  // atom energies [n]
+  const size_t N = (size_t)(n + 63) / 64 * 64;
+  const size_t need = sizeof(float4) * N * kCap + sizeof(float) * (N * F_S + N) +
+                      sizeof(int32_t) * (N * kCap + N) + 256;
   DMTS_REQUIRE(m->atom_ws.reserve(need, s) == DMTS_OK, DMTS_E_OOM, "small model: workspace");
-  float* e_atom = atom_energy ? atom_energy : m->atom_ws.as<float>();
-  float* g = m->atom_ws.as<float>() + ((size_t)n + 63) / 64 * 64;
+  char* base = m->atom_ws.as<char>();
+  float4* ell_g = reinterpret_cast<float4*>(base);
+  float* g = reinterpret_cast<float*>(ell_g + N * kCap);
+  float* e_ws = g + N * F_S;
+  int32_t* ell_j = reinterpret_cast<int32_t*>(e_ws + N);
+  int32_t* ell_n = ell_j + N * kCap;
+  float* e_atom = atom_energy ? atom_energy : e_ws;
   SmallParams P{m->p(m->bf16 ? m->o_WbR : m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts),
                 m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
                 m->p(m->o_w2), m->rc, m->sigma, m->escale, m->Z};
@@ -242,20 +337,21 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
     const int blocks = m->launch_grid(ceil_div(n, kWaves));
     { ProfScope ps(DMTS_K_SMALL_FORWARD, s);
     if (m->bf16)
-      k_small_forward<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,
-                                                           box, e_atom, g);
+      k_small_fwd<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n, box,
+                                                       e_atom, g, ell_j, ell_g, ell_n, nl->flags);
     else
-      k_small_forward<false><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,
-                                                            box, e_atom, g); }
+      k_small_fwd<false><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,
+                                                        box, e_atom, g, ell_j, ell_g, ell_n,
+                                                        nl->flags); }
     DMTS_CHECK_LAUNCH();
     if (forces) {
       { ProfScope ps(DMTS_K_SMALL_BACKWARD, s);
       if (m->bf16)
-        k_small_backward<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species,
-                                                              n, box, g, forces);
+        k_small_bwd<true><<<blocks, kWaves * 64, 0, s>>>(P, species, n, g, ell_j, ell_g, ell_n,
+                                                         forces);
       else
-        k_small_backward<false><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species,
-                                                               n, box, g, forces); }
+        k_small_bwd<false><<<blocks, kWaves * 64, 0, s>>>(P, species, n, g, ell_j, ell_g, ell_n,
+                                                          forces); }
       DMTS_CHECK_LAUNCH();
     }
   }
