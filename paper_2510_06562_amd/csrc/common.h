@@ -141,14 +141,19 @@ struct ProfScope {
 };
 
 // ------------------------------------------------------------------ device helpers
-__device__ __forceinline__ float silu_f(float t) { return t / (1.0f + __expf(-t)); }
+// logistic(t) = 1 / (1 + e^-t) with the hardware reciprocal (v_rcp_f32, 1 ulp); for
+// t -> -inf the denominator is +inf and the result 0.
+__device__ __forceinline__ float logistic_f(float t) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-t));
+}
+__device__ __forceinline__ float silu_f(float t) { return t * logistic_f(t); }
 // d/dt SiLU = s (1 + t (1 - s)), s = logistic(t)
 __device__ __forceinline__ float dsilu_f(float t) {
-  float s = 1.0f / (1.0f + __expf(-t));
+  const float s = logistic_f(t);
   return s * (1.0f + t * (1.0f - s));
 }
 __device__ __forceinline__ void silu_and_grad(float t, float& y, float& dy) {
-  float s = 1.0f / (1.0f + __expf(-t));
+  const float s = logistic_f(t);
   y = t * s;
   dy = s * (1.0f + t * (1.0f - s));
 }

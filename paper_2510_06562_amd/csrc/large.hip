@@ -94,12 +94,13 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-// Cosine cutoff and its derivative (zero outside).
-__device__ __forceinline__ void cutoff_fn(float r, float rc, bool valid, float& fc, float& dfc) {
+// Cosine cutoff and its derivative (zero outside); pi_rc = pi / r_c.
+__device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, float& fc,
+                                          float& dfc) {
   float sn, cs;
-  __sincosf(3.14159265358979f * r / rc, &sn, &cs);
+  __sincosf(pi_rc * r, &sn, &cs);
   fc = valid ? 0.5f * (cs + 1.0f) : 0.f;
-  dfc = valid ? -0.5f * 3.14159265358979f / rc * sn : 0.f;
+  dfc = valid ? -0.5f * pi_rc * sn : 0.f;
 }
 
 template <int LAYER, bool BF16>
@@ -138,6 +139,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   for (int b = 0; b < 4; ++b) Mt[b] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
+  const float pi_rc = 3.14159265358979f * irc;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
     // A operand of a = b W_b: b_k of pair cl at k = 4 s + g
@@ -160,7 +162,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       const int j = nbr[p];
       const bool v = j >= 0 && gv.w < P.rc;
       float dfc;
-      cutoff_fn(gv.w, P.rc, v, fc[r], dfc);
+      cutoff_fn(gv.w, pi_rc, v, fc[r], dfc);
       jj[r] = v ? j : -1;
       zz[r] = LAYER == 1 ? species[v ? j : i] : 0;
       yop[r] = v ? ycomp(cl, gv.x * irc, gv.y * irc, gv.z * irc) : (cl == 0 ? 1.f : 0.f);
@@ -291,6 +293,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   wave_sync();
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
+  const float pi_rc = 3.14159265358979f * irc;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
     // the lane's pair
@@ -300,7 +303,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     const bool vp = j0 >= 0 && gv.w < P.rc;
     const int j = vp ? j0 : -1;
     float fc, dfc;
-    cutoff_fn(gv.w, P.rc, vp, fc, dfc);
+    cutoff_fn(gv.w, pi_rc, vp, fc, dfc);
     const float ux = vp ? gv.x * irc : 0.f, uy = vp ? gv.y * irc : 0.f, uz = vp ? gv.z * irc : 0.f;
     float bop[8], dbop[8];
 #pragma unroll
@@ -325,9 +328,11 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     // invalid pairs have f_c = 0, so any finite sender term will do: use the receiver's
     const float* Aj = LAYER == 2 ? P2 + (size_t)(j >= 0 ? j : i) * 2 * F_L : nullptr;
     const float* Tj = LAYER == 1 ? sTs + species[j >= 0 ? j : i] * F_L : nullptr;
-    float S1 = 0.f, S2 = 0.f, G[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) G[k] = 0.f;
+    float S1 = 0.f, S2 = 0.f;
+    // G^T[k][pair] = sum_c D[c][k + 1] m[c][pair] on MFMA: K runs over the lane group's
+    // channels (index g <-> channel 16 b + 4 g + s, register s of m^T), the A operand is
+    // D[16 b + 4 g + s][k + 1] for row k = cl < 9.
+    f32x4 Gt = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int bb4 = 0; bb4 < 4; ++bb4) {
       const int b = hb + bb4;
@@ -357,9 +362,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         add = *reinterpret_cast<const float4*>(Tj + c0);
       }
       const float4 bb = *reinterpret_cast<const float4*>(&sB[w][l0]);
-      float4 Dk[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Dk[k] = *reinterpret_cast<const float4*>(sd + (k + 1) * kLdH + l0);
+      f32x4 mv;
       float4 dav;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -373,12 +376,13 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         const float da = dm * fc * dsv;
         S1 = fmaf(dm, sv, S1);
         S2 = fmaf(da, gd[r], S2);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const float dk = r == 0 ? Dk[k].x : r == 1 ? Dk[k].y : r == 2 ? Dk[k].z : Dk[k].w;
-          G[k] = fmaf(m, dk, G[k]);
-        }
+        mv[r] = m;
         if (r == 0) dav.x = da; else if (r == 1) dav.y = da; else if (r == 2) dav.z = da; else dav.w = da;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const float dk = cl < 9 ? sd[(cl + 1) * kLdH + l0 + s4] : 0.f;
+        Gt = __builtin_amdgcn_mfma_f32_16x16x4f32(dk, mv[s4], Gt, 0, 0, 0);
       }
       if (LAYER == 2) {
         *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
@@ -398,11 +402,14 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     S1 += __shfl_xor(S1, 32, 64);
     S2 += __shfl_xor(S2, 16, 64);
     S2 += __shfl_xor(S2, 32, 64);
+    // Gt register r of group g holds component 4 g + r of pair cl: collect all nine
+    float G[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      G[k] += __shfl_xor(G[k], 16, 64);
-      G[k] += __shfl_xor(G[k], 32, 64);
+    for (int r = 0; r < 4; ++r) {
+      G[r] = Gt[r];
+      G[4 + r] = __shfl_xor(Gt[r], 16, 64);
     }
+    G[8] = __shfl_xor(Gt[0], 32, 64);
     if (g == 0) {
       // G[0..2] = sum m dM1, G[3..5] = sum m dM2_aa, G[6..8] = sum m 2 dM2_ab (xy, xz, yz)
       const float t23 = (2.0f / 3.0f) * (G[3] + G[4] + G[5]);
@@ -410,7 +417,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       const float ay = G[1] + G[6] * ux + 2.0f * G[4] * uy + G[8] * uz - t23 * uy;
       const float az = G[2] + G[7] * ux + G[8] * uy + 2.0f * G[5] * uz - t23 * uz;
       const float rho = dfc * S1 + S2;
-      const float ir = vp ? 1.0f / gv.w : 0.f;
+      const float ir = vp ? __builtin_amdgcn_rcpf(gv.w) : 0.f;
       const float vx = rho * gv.x * ir + irc * ax;
       const float vy = rho * gv.y * ir + irc * ay;
       const float vz = rho * gv.z * ir + irc * az;

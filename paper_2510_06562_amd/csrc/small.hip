@@ -116,6 +116,7 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
+  const float pi_rc = 3.14159265358979f / P.rc;
   const int n_wg = (n + kWaves - 1) / kWaves;
   for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
     const int i = wg * kWaves + w;
@@ -172,7 +173,7 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
         const int q = t0 + 4 * g + r;
         const bool v = q < cnt;
         const float rq = v ? sG[w][q].w : 0.f;
-        fc[r] = v ? 0.5f * (__cosf(3.14159265358979f * rq / P.rc) + 1.0f) : 0.f;
+        fc[r] = v ? 0.5f * (__cosf(pi_rc * rq) + 1.0f) : 0.f;
         zz[r] = v ? sZ[w][q] : zi_s;
       }
 #pragma unroll
@@ -232,6 +233,7 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, cl = lane & 15;
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
+  const float pi_rc = 3.14159265358979f / P.rc;
   const int n_wg = (n + kWaves - 1) / kWaves;
   for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
     const int i = wg * kWaves + w;
@@ -256,9 +258,9 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
       const float4 gv = vp ? ell_g[(size_t)i * kCap + pc] : make_float4(0.f, 0.f, 0.f, 0.f);
       const float rp = gv.w;
       float sn, cs;
-      __sincosf(3.14159265358979f * rp / P.rc, &sn, &cs);
+      __sincosf(pi_rc * rp, &sn, &cs);
       const float fc = vp ? 0.5f * (cs + 1.0f) : 0.f;
-      const float dfc = vp ? -0.5f * 3.14159265358979f / P.rc * sn : 0.f;
+      const float dfc = vp ? -0.5f * pi_rc * sn : 0.f;
       const int zj = species[j];
       auto bk = [&](int e) {
         const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
@@ -294,7 +296,7 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
       }
       S += __shfl_xor(S, 16, 64);
       S += __shfl_xor(S, 32, 64);
-      const float ir = vp ? 1.0f / rp : 0.f;
+      const float ir = vp ? __builtin_amdgcn_rcpf(rp) : 0.f;
       fx = fmaf(S * ir, gv.x, fx);
       fy = fmaf(S * ir, gv.y, fy);
       fz = fmaf(S * ir, gv.z, fz);
