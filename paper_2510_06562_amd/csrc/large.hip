@@ -103,8 +103,10 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
   dfc = valid ? -0.5f * pi_rc * sn : 0.f;
 }
 
+// Both pair kernels are latency bound at low occupancy: their registers are capped so that
+// three waves share a SIMD (three work-groups per CU, which their LDS also allows).
 template <int LAYER, bool BF16>
-__global__ void __launch_bounds__(kWaves * 64)
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
@@ -233,7 +235,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
 }
 
 template <int LAYER, bool BF16>
-__global__ void __launch_bounds__(kWaves * 64)
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, const float* __restrict__ Mall,
@@ -442,25 +444,40 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   }  // grid-stride loop over work-groups of atoms
 }
 
-// S_j = sum over the rows of j of dA at the reverse positions (the sender sums).
+// S_j = sum over the rows of j of dA at the reverse positions (the sender sums).  One wave
+// per atom, lane l owns channels 2l and 2l+1.  The row's reverse positions are read 64 at a
+// time (one per lane) and broadcast, so the dA rows of eight pairs are in flight at once;
+// they are added in row order.
 __global__ void __launch_bounds__(kWaves * 64)
 k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const int32_t* __restrict__ rev, int n, const float* __restrict__ dA,
                 float* __restrict__ RS) {
+  constexpr int kU = 8;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kWaves + w;
   if (i >= n) return;
-  float s0 = 0.f, s1 = 0.f;
+  const float2* dA2 = reinterpret_cast<const float2*>(dA);
+  float2 s = make_float2(0.f, 0.f);
   const int row0 = offs[i], row1 = offs[i + 1];
-  for (int p = row0; p < row1; ++p) {
-    if (nbr[p] < 0) break;
-    const int q = rev[p];
-    if (q < 0) continue;
-    s0 += dA[(size_t)q * F_L + lane];
-    s1 += dA[(size_t)q * F_L + lane + 64];
+  for (int base = row0; base < row1; base += 64) {
+    const int p = base + lane;
+    const int q = (p < row1 && nbr[p] >= 0) ? rev[p] : -1;
+    const int m = min(64, row1 - base);
+    for (int k = 0; k < m; k += kU) {
+      float2 t[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int qq = __builtin_amdgcn_readlane(q, k + u);
+        t[u] = qq >= 0 ? dA2[(size_t)qq * (F_L / 2) + lane] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        s.x += t[u].x;
+        s.y += t[u].y;
+      }
+    }
   }
-  RS[(size_t)i * 2 * F_L + F_L + lane] = s0;
-  RS[(size_t)i * 2 * F_L + F_L + lane + 64] = s1;
+  reinterpret_cast<float2*>(RS + (size_t)i * 2 * F_L + F_L)[lane] = s;
 }
 
 }  // namespace

@@ -100,8 +100,9 @@ __device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
   return acc;
 }
 
+// Five waves per SIMD: the registers are capped at 96, and five work-groups fit the LDS.
 template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64)
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
 k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
             const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
             double box, float* __restrict__ atom_e, float* __restrict__ g_out,
