@@ -203,16 +203,19 @@ struct Runner {
     ++pending.nops;
     return DMTS_OK;
   }
-  dmts_status eval(Model* m, NList* nl, float* F, double* e) {
+  // The model energies are only reported for the positions a call ends at, so an
+  // evaluation sums them (want_e) only when it is the last one of its model in the call.
+  dmts_status eval(Model* m, NList* nl, float* F, double* e, bool want_e) {
     dmts_status r = flush();
     if (r != DMTS_OK) return r;
     r = build_neighbors(nl, x, st->n, st->box, nullptr, 1, (double)m->desc.cutoff, s);
     if (r != DMTS_OK) return r;
-    return energy_forces(m, nl, x, st->species, st->n, st->box, nullptr, 1, e, F, nullptr, s);
+    return energy_forces(m, nl, x, st->species, st->n, st->box, nullptr, 1,
+                         want_e ? e : nullptr, F, nullptr, s);
   }
   // reference model: builds the list (at list_cut in shared mode) and records x_ref
-  dmts_status eval_large(Model* m) {
-    if (!shared) return eval(m, st->nl_large, st->FL, st->e_models);
+  dmts_status eval_large(Model* m, bool want_e) {
+    if (!shared) return eval(m, st->nl_large, st->FL, st->e_models, want_e);
     dmts_status r = flush();
     if (r != DMTS_OK) return r;
     r = build_neighbors(st->nl_large, x, st->n, st->box, nullptr, 1, list_cut, s);
@@ -221,14 +224,14 @@ struct Runner {
     k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(x, st->x_ref, n3);
     DMTS_CHECK_LAUNCH();
     return energy_forces(m, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
-                         st->e_models, st->FL, nullptr, s);
+                         want_e ? st->e_models : nullptr, st->FL, nullptr, s);
   }
-  dmts_status eval_small(Model* m) {
-    if (!shared) return eval(m, st->nl_small, st->Fs, st->e_models + 1);
+  dmts_status eval_small(Model* m, bool want_e) {
+    if (!shared) return eval(m, st->nl_small, st->Fs, st->e_models + 1, want_e);
     dmts_status r = flush();
     if (r != DMTS_OK) return r;
     return energy_forces(m, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
-                         st->e_models + 1, st->Fs, nullptr, s);
+                         want_e ? st->e_models + 1 : nullptr, st->Fs, nullptr, s);
   }
 };
 
@@ -240,14 +243,16 @@ dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_ou
     // single-time-step baseline: velocity Verlet (BAOAB with the O-step off)
     const double dt = st->dt;
     if (st->first) {
-      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models)) != DMTS_OK) return r;
+      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models, n_outer == 0)) != DMTS_OK)
+        return r;
       st->first = false;
     }
     for (int o = 0; o < n_outer; ++o) {
       R.push(kKickLarge, 0.5 * dt * kappa);
       R.push(kDrift, 0.5 * dt);
       R.push(kDrift, 0.5 * dt);
-      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models)) != DMTS_OK) return r;
+      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models, o == n_outer - 1)) != DMTS_OK)
+        return r;
       R.push(kKickLarge, 0.5 * dt * kappa);
     }
     return R.flush();
@@ -256,20 +261,21 @@ dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_ou
   const int n = st->n_inner;
   const double h_in = dt / n;
   if (st->first) {
-    if ((r = R.eval_large(large)) != DMTS_OK) return r;
-    if ((r = R.eval_small(small)) != DMTS_OK) return r;
+    if ((r = R.eval_large(large, n_outer == 0)) != DMTS_OK) return r;
+    if ((r = R.eval_small(small, n_outer == 0)) != DMTS_OK) return r;
     st->first = false;
   }
   for (int o = 0; o < n_outer; ++o) {
+    const bool last = o == n_outer - 1;
     R.push(kKickSlow, 0.5 * dt * kappa);
     for (int k = 0; k < n; ++k) {
       R.push(kKickFast, 0.5 * h_in * kappa);
       R.push(kDrift, 0.5 * h_in);
       R.push(kDrift, 0.5 * h_in);
-      if ((r = R.eval_small(small)) != DMTS_OK) return r;
+      if ((r = R.eval_small(small, last && k == n - 1)) != DMTS_OK) return r;
       R.push(kKickFast, 0.5 * h_in * kappa);
     }
-    if ((r = R.eval_large(large)) != DMTS_OK) return r;
+    if ((r = R.eval_large(large, last)) != DMTS_OK) return r;
     R.push(kKickSlow, 0.5 * dt * kappa);
   }
   return R.flush();

@@ -49,6 +49,9 @@ struct LargeParams {
 // Lane l has group g = l / 16 and column cl = l % 16; v_mfma_f32_16x16x4f32 layout:
 //   A operand: A[cl][k0 + g], B operand: B[k0 + g][cl], D register r: D[4 g + r][cl].
 //
+// The radial contraction over K = 32 takes, in step s = 0..7, the K index k = 8 g + s in
+// group g (both operands agree on it), so that a lane's eight weights W_b[c][8g .. 8g+7]
+// are two 16-byte LDS reads.
 // Forward: a = b W_b as D[pair][channel] (pair 4g + r, channel 16 blk + cl).  The moments
 // M^T[y][c] = sum_p Y[p][y] m[p][c] then use that accumulator as their B operand: in step
 // s the K index g stands for pair 4g + s, i.e. register s of the lane.
@@ -57,14 +60,15 @@ struct LargeParams {
 // b and W_b rounded to bfloat16; moments, their reverse and all elementwise math stay FP32.
 // Reverse pass: the transposed product a^T = W_b b^T as D[channel][pair] (channel
 // 16 blk + 4g + r, pair cl): each lane owns one pair and 32 channels, so the channel sums
-// of a pair are in-lane plus two cross-group shuffles; dm^T = D_i^T Y^T likewise.
+// of a pair are in-lane plus two cross-group shuffles; dm^T = D_i^T Y^T likewise.  The
+// products of channel block b + 1 are issued before the elementwise work of block b.
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTile = 16;
 constexpr int kLdK = 40;    // LDS stride (bfloat16) of W_b rows [c][k] in the BF16 form
-constexpr int kLdW = 144;   // LDS stride of W_b^T rows [k][c]
+constexpr int kLdM = 68;    // LDS stride of the per-wave moment rows (64 channels)
 constexpr int kLdT = 36;    // LDS stride of W_b rows [c][k]
 constexpr int kLdH = 80;    // LDS stride of per-half rows (64 channels)
 
@@ -94,6 +98,12 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
+// Column swizzle of the per-wave adjoint rows D[y][cc] (64 channels, stride kLdH): the low
+// two bits of the column are XORed with bits 2..3 of the row, so that both the row-wise
+// reads of dm^T (fixed y per group) and the column-wise reads of the angular sums (row
+// cl + 1 per lane) fall in distinct banks.
+__device__ __forceinline__ int dswz(int y, int cc) { return y * kLdH + (cc ^ ((y >> 2) & 3)); }
+
 // Cosine cutoff and its derivative (zero outside); pi_rc = pi / r_c.
 __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, float& fc,
                                           float& dfc) {
@@ -103,23 +113,24 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
   dfc = valid ? -0.5f * pi_rc * sn : 0.f;
 }
 
-// Both pair kernels are latency bound at low occupancy: their registers are capped so that
-// three waves share a SIMD (three work-groups per CU, which their LDS also allows).
+// Both pair kernels are latency bound at low occupancy: the registers of the forward kernel
+// are capped so that four waves share a SIMD, those of the reverse kernel for three (as
+// many work-groups per CU as their LDS allows).
 template <int LAYER, bool BF16>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
-  __shared__ float sW[BF16 ? 1 : K_L * kLdW];
+  __shared__ float sWt[BF16 ? 1 : F_L * kLdT];       // W_b [c][k]
   __shared__ __bf16 sW16[BF16 ? F_L * kLdK : 1];
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
-  __shared__ float sM[kWaves][NMOM * kLdW];
+  __shared__ float sM[kWaves][NMOM * kLdM];
   if (BF16) {
     for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
       sW16[(e / K_L) * kLdK + e % K_L] = P.Wb16[e];
   } else {
     for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
-      sW[(e / F_L) * kLdW + e % F_L] = P.WbT[e];
+      sWt[(e % F_L) * kLdT + e / F_L] = P.WbT[e];
   }
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
@@ -144,14 +155,13 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float pi_rc = 3.14159265358979f * irc;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
-    // A operand of a = b W_b: b_k of pair cl at k = 4 s + g
+    // A operand of a = b W_b: b_k of pair cl at k = 8 g + s
     const float rp = geo[t0 + cl].w;
     const bool vp = nbr[t0 + cl] >= 0 && rp < P.rc;
     float bop[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const int k = BF16 ? 8 * g + s : 4 * s + g;
-      const float x = rp - P.sigma * k;
+      const float x = rp - P.sigma * (8 * g + s);
       bop[s] = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
     }
     // the lane's four pairs of the D layout: 4 g + r
@@ -183,12 +193,17 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, w8, acc[b], 0, 0, 0);
       }
     } else {
+      // step s, group g <-> k = 8 g + s: the lane's weights W_b[c][8 g .. 8 g + 7]
 #pragma unroll
-      for (int s = 0; s < 8; ++s)
+      for (int b = 0; b < 4; ++b) {
+        const float* wr = &sWt[(16 * (hb + b) + cl) * kLdT + 8 * g];
+        const float4 w0 = *reinterpret_cast<const float4*>(wr);
+        const float4 w1 = *reinterpret_cast<const float4*>(wr + 4);
+        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-              bop[s], sW[(4 * s + g) * kLdW + 16 * (hb + b) + cl], acc[b], 0, 0, 0);
+        for (int s = 0; s < 8; ++s)
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bop[s], wv[s], acc[b], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -213,7 +228,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int y = 4 * g + r;
-      if (y < NMOM) sm[y * kLdW + 16 * b + cl] = Mt[b][r];
+      if (y < NMOM) sm[y * kLdM + 16 * b + cl] = Mt[b][r];
     }
   wave_sync();
   float* Mi = Mout + (size_t)i * NMOM * F_L;
@@ -223,7 +238,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float mm[NMOM];
 #pragma unroll
     for (int y = 0; y < NMOM; ++y) {
-      mm[y] = sm[y * kLdW + lane];
+      mm[y] = sm[y * kLdM + lane];
       Mi[y * F_L + c] = mm[y];
     }
     qi[c] = mm[0];
@@ -270,20 +285,20 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   float* vh = v + (size_t)half * 3 * cap;   // this half's share of v_ij
   const int zi_s = species[i];
   // D[y][c]: dE/dq folded with dq/dM, off-diagonal M2 components doubled, so that
-  // dm = sum_y Y[y] D[y]
+  // dm = sum_y Y[y] D[y].  Stored with the column swizzle dswz(y, cc).
   {
     const float* Mi = Mall + (size_t)i * NMOM * F_L;
     const float* dqi = dq + (size_t)i * 3 * F_L;
     {
       const int c = 16 * hb + lane;
       const float s1 = 2.0f * dqi[F_L + c], s2 = 2.0f * dqi[2 * F_L + c];
-      sd[lane] = dqi[c];
+      sd[dswz(0, lane)] = dqi[c];
 #pragma unroll
-      for (int y = 1; y < 4; ++y) sd[y * kLdH + lane] = s1 * Mi[y * F_L + c];
+      for (int y = 1; y < 4; ++y) sd[dswz(y, lane)] = s1 * Mi[y * F_L + c];
 #pragma unroll
-      for (int y = 4; y < 7; ++y) sd[y * kLdH + lane] = s2 * Mi[y * F_L + c];
+      for (int y = 4; y < 7; ++y) sd[dswz(y, lane)] = s2 * Mi[y * F_L + c];
 #pragma unroll
-      for (int y = 7; y < NMOM; ++y) sd[y * kLdH + lane] = 2.0f * s2 * Mi[y * F_L + c];
+      for (int y = 7; y < NMOM; ++y) sd[dswz(y, lane)] = 2.0f * s2 * Mi[y * F_L + c];
     }
   }
   {
@@ -296,6 +311,9 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
   const float pi_rc = 3.14159265358979f * irc;
+  // row of D read by lane (cl, g) for the angular sums: k + 1 = cl + 1 (clamped; lanes
+  // cl >= 9 are masked)
+  const int kr = cl < 9 ? cl + 1 : 9;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
     // the lane's pair
@@ -307,11 +325,11 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float fc, dfc;
     cutoff_fn(gv.w, pi_rc, vp, fc, dfc);
     const float ux = vp ? gv.x * irc : 0.f, uy = vp ? gv.y * irc : 0.f, uz = vp ? gv.z * irc : 0.f;
+    // radial operands b_k(r), b'_k(r) at k = 8 g + s
     float bop[8], dbop[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const int k = BF16 ? 8 * g + s : 4 * s + g;
-      const float x = gv.w - P.sigma * k;
+      const float x = gv.w - P.sigma * (8 * g + s);
       const float bk = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
       bop[s] = bk;
       dbop[s] = -x * inv_s2 * bk;
@@ -324,9 +342,9 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         db8[e] = (__bf16)dbop[e];
       }
     }
-    float yop[4];   // B operand of dm^T: Y^T[4 s + g][pair cl]
+    float yop[3];   // B operand of dm^T: Y^T[4 s + g][pair cl]
 #pragma unroll
-    for (int s = 0; s < 4; ++s) yop[s] = ycomp(4 * s + g, ux, uy, uz);
+    for (int s = 0; s < 3; ++s) yop[s] = ycomp(4 * s + g, ux, uy, uz);
     // invalid pairs have f_c = 0, so any finite sender term will do: use the receiver's
     const float* Aj = LAYER == 2 ? P2 + (size_t)(j >= 0 ? j : i) * 2 * F_L : nullptr;
     const float* Tj = LAYER == 1 ? sTs + species[j >= 0 ? j : i] * F_L : nullptr;
@@ -335,26 +353,44 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     // channels (index g <-> channel 16 b + 4 g + s, register s of m^T), the A operand is
     // D[16 b + 4 g + s][k + 1] for row k = cl < 9.
     f32x4 Gt = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int bb4 = 0; bb4 < 4; ++bb4) {
+    // The three products of channel block bb4: a^T and a'^T = W_b b^T, W_b b'^T (step s,
+    // group g <-> k = 8 g + s) and dm^T = D^T Y^T.  They are issued one block ahead, so
+    // that the matrix cores work on block bb4 + 1 while the vector units finish bb4.
+    auto issue = [&](int bb4, f32x4& ga, f32x4& gd, f32x4& dmv) {
       const int b = hb + bb4;
-      f32x4 ga = {0.f, 0.f, 0.f, 0.f}, gd = ga, dmv = ga;
+      ga = f32x4{0.f, 0.f, 0.f, 0.f};
+      gd = ga;
+      dmv = ga;
       if (BF16) {
         const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(&sW16[(16 * b + cl) * kLdK + 8 * g]);
         ga = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, b8, ga, 0, 0, 0);
         gd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, db8, gd, 0, 0, 0);
       } else {
+        const float4 w0 = *reinterpret_cast<const float4*>(&sWt[(16 * b + cl) * kLdT + 8 * g]);
+        const float4 w1 = *reinterpret_cast<const float4*>(&sWt[(16 * b + cl) * kLdT + 8 * g + 4]);
+        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const float wv = sWt[(16 * b + cl) * kLdT + 4 * s + g];
-          ga = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, bop[s], ga, 0, 0, 0);
-          gd = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, dbop[s], gd, 0, 0, 0);
+          ga = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[s], bop[s], ga, 0, 0, 0);
+          gd = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[s], dbop[s], gd, 0, 0, 0);
         }
       }
+      // K index 4 s + g = y runs over the ten components; rows 10 and 11 are zero and
+      // rows 12..15 (s = 3) are left out
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        dmv = __builtin_amdgcn_mfma_f32_16x16x4f32(sd[(4 * s + g) * kLdH + 16 * bb4 + cl], yop[s],
-                                                   dmv, 0, 0, 0);
+      for (int s = 0; s < 3; ++s) {
+        const int y = 4 * s + g;
+        const float dy = sd[dswz(y < NMOM ? y : NMOM - 1, 16 * bb4 + cl)];
+        dmv = __builtin_amdgcn_mfma_f32_16x16x4f32(y < NMOM ? dy : 0.f, yop[s], dmv, 0, 0, 0);
+      }
+    };
+    f32x4 ga, gd, dmv;
+    issue(0, ga, gd, dmv);
+#pragma unroll
+    for (int bb4 = 0; bb4 < 4; ++bb4) {
+      f32x4 ga_n, gd_n, dmv_n;
+      if (bb4 < 3) issue(bb4 + 1, ga_n, gd_n, dmv_n);
+      const int b = hb + bb4;
       const int c0 = 16 * b + 4 * g;   // the lane's four channels c0 .. c0+3
       const int l0 = 16 * bb4 + 4 * g;  // their index within the half
       float4 add = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -383,8 +419,8 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       }
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
-        const float dk = cl < 9 ? sd[(cl + 1) * kLdH + l0 + s4] : 0.f;
-        Gt = __builtin_amdgcn_mfma_f32_16x16x4f32(dk, mv[s4], Gt, 0, 0, 0);
+        const float dk = sd[dswz(kr, l0 + s4)];
+        Gt = __builtin_amdgcn_mfma_f32_16x16x4f32(cl < 9 ? dk : 0.f, mv[s4], Gt, 0, 0, 0);
       }
       if (LAYER == 2) {
         *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
@@ -396,7 +432,12 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         t.w += dav.w;
         *acc = t;
       }
-      // one channel block at a time: keeps the live accumulators to three MFMA tiles
+      if (bb4 < 3) {
+        ga = ga_n;
+        gd = gd_n;
+        dmv = dmv_n;
+      }
+      // one region per block: the live products are those of two blocks
       __builtin_amdgcn_sched_barrier(0);
     }
     // channel sums of the pair: in-lane above, then across the four groups
