@@ -260,19 +260,19 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
     append(P, m->o_U1, std::vector<float>(U1, U1 + (size_t)F * Q));
     append(P, m->o_U2T, transpose_block(U2, F, Q, 0, Q));
     append(P, m->o_U2, std::vector<float>(U2, U2 + (size_t)F * Q));
-    // [A | B] projection: B[k][n] = W_pair2[n][K+F+k] (sender) for n < F,
-    //                              W_pair2[n-F][K+k]  (receiver) otherwise.
-    std::vector<float> W2hT((size_t)F * 2 * F), W2hs((size_t)2 * F * F);
-    for (int k = 0; k < F; ++k)
-      for (int n = 0; n < 2 * F; ++n)
-        W2hT[(size_t)k * 2 * F + n] = n < F ? Wp2[(size_t)n * cols2 + K + F + k]
-                                            : Wp2[(size_t)(n - F) * cols2 + K + k];
-    // reverse pass: dh[e] = sum_c R[c] W_pair2[c][K+e] + sum_c S[c] W_pair2[c][K+F+e]
-    for (int k = 0; k < 2 * F; ++k)
-      for (int e = 0; e < F; ++e)
-        W2hs[(size_t)k * F + e] = k < F ? Wp2[(size_t)k * cols2 + K + e]
-                                        : Wp2[(size_t)(k - F) * cols2 + K + F + e];
-    append(P, m->o_W2hT, W2hT);
+    // [A | B] projection as [out][in]: row n < F is W_pair2[n][K+F+.] (sender), row F + n
+    // is W_pair2[n][K+.] (receiver); reverse pass dh[e] = sum_c R[c] W_pair2[c][K+e] +
+    // sum_c S[c] W_pair2[c][K+F+e], as [out = e][in = 2F].
+    std::vector<float> W2h((size_t)2 * F * F), W2hs((size_t)F * 2 * F);
+    for (int nn = 0; nn < 2 * F; ++nn)
+      for (int k = 0; k < F; ++k)
+        W2h[(size_t)nn * F + k] = nn < F ? Wp2[(size_t)nn * cols2 + K + F + k]
+                                         : Wp2[(size_t)(nn - F) * cols2 + K + k];
+    for (int e = 0; e < F; ++e)
+      for (int k = 0; k < 2 * F; ++k)
+        W2hs[(size_t)e * 2 * F + k] = k < F ? Wp2[(size_t)k * cols2 + K + e]
+                                            : Wp2[(size_t)(k - F) * cols2 + K + F + e];
+    append(P, m->o_W2h, W2h);
     append(P, m->o_W2hs, W2hs);
     append(P, m->o_WoT, transpose_block(Wo, F, F, 0, F));
     append(P, m->o_Wo, std::vector<float>(Wo, Wo + (size_t)F * F));

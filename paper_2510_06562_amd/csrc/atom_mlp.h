@@ -5,17 +5,17 @@
 
 namespace dmts {
 
-// Weight views (row-major [K x N], K = input width, N = output width).
+// Weight views, row-major [out][in] (the input index contiguous).
 struct AtomMlpParams {
-  const float* U1T;   // [384][128]  z1 = U1 q1
-  const float* W2hT;  // [128][256]  [A | B] = [W_s | W_r] h1
-  const float* U2T;   // [384][128]
-  const float* WoT;   // [128][128]  y = W_o h2
+  const float* U1;    // [128][384]  z1 = U1 q1
+  const float* W2h;   // [256][128]  [A | B] = [W_s | W_r] h1
+  const float* U2;    // [128][384]  z2 = U2 q2
+  const float* Wo;    // [128][128]  y = W_o h2
   const float* wo;    // [128]
-  const float* Wo;    // [128][128]  dh2 = W_o^T dy
-  const float* U2;    // [128][384]  dq2 = U2^T dz2
-  const float* W2hs;  // [256][128]  dh1 = W_r^T R + W_s^T S
-  const float* U1;    // [128][384]  dq1 = U1^T dz1
+  const float* WoT;   // [128][128]  dh2 = W_o^T dy
+  const float* U2T;   // [384][128]  dq2 = U2^T dz2
+  const float* W2hs;  // [128][256]  dh1 = W_r^T R + W_s^T S
+  const float* U1T;   // [384][128]  dq1 = U1^T dz1
   // BF16 form (all null for FP32): the same layers as bfloat16 [out][in]
   const __bf16* h_U1 = nullptr;    // [128][384]
   const __bf16* h_W2h = nullptr;   // [256][128]

@@ -4,7 +4,7 @@
 // of layers between two pair kernels runs in one launch: a work-group owns a tile of 16
 // atoms, keeps the activations of the tile in LDS between layers and streams the weights
 // (at most 384 x 384 floats, L2-resident) from global memory.  Contractions use
-// v_mfma_f32_16x16x4_f32; the four waves of the work-group split the output columns in
+// v_mfma_f32_16x16x4_f32; the eight waves of the work-group split the output columns in
 // blocks of 16.
 //
 //   chain 1 (after interaction 1):  z1 = U1 q1, h1 = SiLU(z1), [A|B] = [W_s|W_r] h1
@@ -30,20 +30,29 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRows = 16;
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;   // eight waves: one or more 16-column blocks each
 constexpr int kLd = 388;     // LDS row stride (floats) for activations up to 384 wide
 
-// acc[16 x 16] block = X[16 x K] (LDS, stride kLd) * B[K x ...] (global, stride ldb),
-// columns n0 .. n0+15.
-__device__ __forceinline__ f32x4 mfma_block(const float* X, int K, const float* __restrict__ B,
-                                            int ldb, int n0, int lane) {
+// acc[16 x 16] block = X[16 x K] (LDS, stride kLd) * W^T with W [N x K] FP32 (global, input
+// index contiguous), columns n0 .. n0+15.  In each 32-wide slice of K, step s of group g
+// takes k = 8 g + s (both operands agree), so a lane reads its eight X and eight W values
+// as two 16-byte loads each.
+__device__ __forceinline__ f32x4 mfma_block(const float* X, int K, const float* __restrict__ W,
+                                            int n0, int lane) {
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  const int r = lane & 15, kk = lane >> 4;
-  const float* xp = X + r * kLd + kk;
-  const float* bp = B + (size_t)kk * ldb + n0 + r;
-#pragma unroll 8
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xp[k0], bp[(size_t)k0 * ldb], acc, 0, 0, 0);
+  const int r = lane & 15, g = lane >> 4;
+  const float* xp = X + r * kLd + 8 * g;
+  const float* wp = W + (size_t)(n0 + r) * K + 8 * g;
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const float4 x0 = *reinterpret_cast<const float4*>(xp + k0);
+    const float4 x1 = *reinterpret_cast<const float4*>(xp + k0 + 4);
+    const float4 w0 = *reinterpret_cast<const float4*>(wp + k0);
+    const float4 w1 = *reinterpret_cast<const float4*>(wp + k0 + 4);
+    const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[s], wv[s], acc, 0, 0, 0);
   }
   return acc;
 }
@@ -75,7 +84,7 @@ __device__ __forceinline__ f32x4 mfma_block_bf16(const float* X, int K,
   return acc;
 }
 
-// Weights of one layer: FP32 [K][N] or BF16 [N][K].
+// Weights of one layer, [N][K]: FP32 or BF16.
 struct LayerW {
   const float* f32;
   const __bf16* b16;
@@ -88,7 +97,7 @@ __device__ __forceinline__ void layer(const float* X, int K, LayerW Wt, int N, E
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int nb = wave; nb < N / 16; nb += kThreads / 64) {
     f32x4 acc = Wt.b16 ? mfma_block_bf16(X, K, Wt.b16, nb * 16, lane)
-                       : mfma_block(X, K, Wt.f32, N, nb * 16, lane);
+                       : mfma_block(X, K, Wt.f32, nb * 16, lane);
 #pragma unroll
     for (int r = 0; r < 4; ++r) epi(4 * (lane >> 4) + r, nb * 16 + (lane & 15), acc[r]);
   }
@@ -111,7 +120,7 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
   const int m0 = blockIdx.x * kRows;
   stage_rows(X, q1, 384, 384, m0, M);
   __syncthreads();
-  layer(X, 384, LayerW{P.U1T, P.h_U1}, 128, [&](int r, int c, float v) {
+  layer(X, 384, LayerW{P.U1, P.h_U1}, 128, [&](int r, int c, float v) {
     const float h = silu_f(v);
     H[r * kLd + c] = h;
     if (m0 + r < M) {
@@ -120,7 +129,7 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
     }
   });
   __syncthreads();
-  layer(H, 128, LayerW{P.W2hT, P.h_W2h}, 256, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.W2h, P.h_W2h}, 256, [&](int r, int c, float v) {
     if (m0 + r < M) P2[(size_t)(m0 + r) * 256 + c] = v;
   });
 }
@@ -136,14 +145,14 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
   const int m0 = blockIdx.x * kRows;
   stage_rows(X, q2, 384, 384, m0, M);
   __syncthreads();
-  layer(X, 384, LayerW{P.U2T, P.h_U2}, 128, [&](int r, int c, float v) {
+  layer(X, 384, LayerW{P.U2, P.h_U2}, 128, [&](int r, int c, float v) {
     Z[r * 128 + c] = v;
     const float hp = (m0 + r) < M ? h1[(size_t)(m0 + r) * 128 + c] : 0.f;
     H[r * kLd + c] = hp + silu_f(v);
   });
   __syncthreads();
   // y = W_o h2; energy terms and dy (dy overwrites the X buffer)
-  layer(H, 128, LayerW{P.WoT, P.h_Wo}, 128, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.Wo, P.h_Wo}, 128, [&](int r, int c, float v) {
     float s, ds;
     silu_and_grad(v, s, ds);
     const float w = P.wo[c];
@@ -162,12 +171,12 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
   }
   if (!backward) return;
   // dh2 = W_o^T dy, dz2 = dh2 SiLU'(z2)   (dz2 goes to H)
-  layer(X, 128, LayerW{P.Wo, P.h_WoT}, 128, [&](int r, int c, float v) {
+  layer(X, 128, LayerW{P.WoT, P.h_WoT}, 128, [&](int r, int c, float v) {
     if (m0 + r < M) dh2_out[(size_t)(m0 + r) * 128 + c] = v;
     H[r * kLd + c] = v * dsilu_f(Z[r * 128 + c]);
   });
   __syncthreads();
-  layer(H, 128, LayerW{P.U2, P.h_U2T}, 384, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.U2T, P.h_U2T}, 384, [&](int r, int c, float v) {
     if (m0 + r < M) dq2[(size_t)(m0 + r) * 384 + c] = v;
   });
 }
@@ -189,7 +198,7 @@ k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __re
     H[r * kLd + c] = dz;
   });
   __syncthreads();
-  layer(H, 128, LayerW{P.U1, P.h_U1T}, 384, [&](int r, int c, float v) {
+  layer(H, 128, LayerW{P.U1T, P.h_U1T}, 384, [&](int r, int c, float v) {
     if (m0 + r < M) dq1[(size_t)(m0 + r) * 384 + c] = v;
   });
 }

@@ -89,8 +89,9 @@ struct Model {
   size_t o_WbT = 0, o_Td = 0, o_Ts = 0;                  // pair block, species tables
   size_t o_W1 = 0, o_W1T = 0, o_w2 = 0;                   // kind 0 readout
   size_t o_W2bT = 0;                                      // kind 1 second interaction
+  // kind 1 per-atom layers, [out][in]: U1, U2 (forward), U1T, U2T (their transposes)
   size_t o_U1T = 0, o_U1 = 0, o_U2T = 0, o_U2 = 0;        // kind 1 updates
-  size_t o_W2hT = 0, o_W2hs = 0;                          // kind 1 h projections
+  size_t o_W2h = 0, o_W2hs = 0;                           // kind 1 h projections
   size_t o_WoT = 0, o_Wo = 0, o_wo = 0;                   // kind 1 readout
   // BF16 form: operands rounded to bfloat16 (round to nearest even)
   bool bf16 = false;

@@ -581,9 +581,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                  m->p(m->o_Ts), m->rc, m->sigma, m->Z};
   LargeParams P2{m->p(m->o_W2bT), m->bf16 ? m->p16(m->h_Wb2) : nullptr, nullptr, nullptr, m->rc,
                  m->sigma, m->Z};
-  AtomMlpParams A{m->p(m->o_U1T), m->p(m->o_W2hT), m->p(m->o_U2T), m->p(m->o_WoT),
-                  m->p(m->o_wo),  m->p(m->o_Wo),   m->p(m->o_U2),  m->p(m->o_W2hs),
-                  m->p(m->o_U1)};
+  AtomMlpParams A{m->p(m->o_U1),  m->p(m->o_W2h), m->p(m->o_U2),   m->p(m->o_Wo),
+                  m->p(m->o_wo),  m->p(m->o_WoT), m->p(m->o_U2T),  m->p(m->o_W2hs),
+                  m->p(m->o_U1T)};
   if (m->bf16) {
     A.h_U1 = m->p16(m->h_U1);
     A.h_W2h = m->p16(m->h_W2h);
