@@ -159,6 +159,20 @@ void append16(std::vector<uint16_t>& dst, size_t& off, const std::vector<float>&
   while (dst.size() % 128) dst.push_back(0);
 }
 
+// Three bfloat16 terms per value, stored as three consecutive tensors: x = t1 + t2 + t3
+// exactly for finite x (t1 = bf16(x), t2 = bf16(x - t1), t3 = bf16(x - t1 - t2)).
+void append16_terms3(std::vector<uint16_t>& dst, size_t& off, const std::vector<float>& src) {
+  off = dst.size();
+  std::vector<float> r = src;
+  for (int t = 0; t < 3; ++t)
+    for (float& x : r) {
+      const float h = bf16_round(x);
+      dst.push_back(bf16_bits(x));
+      x -= h;
+    }
+  while (dst.size() % 128) dst.push_back(0);
+}
+
 void append(std::vector<float>& dst, size_t& off, const std::vector<float>& src) {
   off = dst.size();
   dst.insert(dst.end(), src.begin(), src.end());
@@ -252,10 +266,8 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
     const float* U2 = b.take((size_t)F * Q);
     const float* Wo = b.take((size_t)F * F);
     const float* wo = b.take(F);
-    append(P, m->o_WbT, transpose_block(Wp1, F, cols1, 0, K));
     append(P, m->o_Td, species_table(Wp1, F, cols1, K, emb, Z, D));
     append(P, m->o_Ts, species_table(Wp1, F, cols1, K + D, emb, Z, D));
-    append(P, m->o_W2bT, transpose_block(Wp2, F, cols2, 0, K));
     append(P, m->o_U1T, transpose_block(U1, F, Q, 0, Q));
     append(P, m->o_U1, std::vector<float>(U1, U1 + (size_t)F * Q));
     append(P, m->o_U2T, transpose_block(U2, F, Q, 0, Q));
@@ -321,6 +333,20 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
       append16(H, m->h_W2hs, W2hs);
       append16(H, m->h_U1T, transpose_block(U1, F, Q, 0, Q));
     }
+  }
+  if (d.kind == NNP_KIND_TWO_INTERACTION && d.precision == NNP_PREC_FP32) {
+    // FP32 form: the radial blocks W_pair[:, :K] as three bfloat16 terms ([3][F][K])
+    const int cols1 = K + 2 * D, cols2 = K + 2 * F, Q = 3 * F;
+    const float* Wp1 = host_weights + (size_t)Z * D;
+    const float* Wp2 = Wp1 + (size_t)F * cols1 + (size_t)F * Q;
+    std::vector<float> b1((size_t)F * K), b2((size_t)F * K);
+    for (int c = 0; c < F; ++c)
+      for (int k = 0; k < K; ++k) {
+        b1[(size_t)c * K + k] = Wp1[(size_t)c * cols1 + k];
+        b2[(size_t)c * K + k] = Wp2[(size_t)c * cols2 + k];
+      }
+    append16_terms3(H, m->h_Wb1, b1);
+    append16_terms3(H, m->h_Wb2, b2);
   }
   if (m->params.reserve(P.size() * sizeof(float), nullptr) != DMTS_OK) {
     delete m;

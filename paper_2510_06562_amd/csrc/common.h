@@ -88,15 +88,14 @@ struct Model {
   // offsets (in floats) into params
   size_t o_WbT = 0, o_Td = 0, o_Ts = 0;                  // pair block, species tables
   size_t o_W1 = 0, o_W1T = 0, o_w2 = 0;                   // kind 0 readout
-  size_t o_W2bT = 0;                                      // kind 1 second interaction
   // kind 1 per-atom layers, [out][in]: U1, U2 (forward), U1T, U2T (their transposes)
   size_t o_U1T = 0, o_U1 = 0, o_U2T = 0, o_U2 = 0;        // kind 1 updates
   size_t o_W2h = 0, o_W2hs = 0;                           // kind 1 h projections
   size_t o_WoT = 0, o_Wo = 0, o_wo = 0;                   // kind 1 readout
   // BF16 form: operands rounded to bfloat16 (round to nearest even)
   bool bf16 = false;
-  DevBuf params16;    // bfloat16 tensors, [out][in] (input index contiguous)
-  size_t h_Wb1 = 0, h_Wb2 = 0;                            // radial blocks [F][K]
+  DevBuf params16;    // bfloat16 tensors, [out][in] (input index contiguous), both forms
+  size_t h_Wb1 = 0, h_Wb2 = 0;   // kind 1 radial blocks [F][K]: one term (BF16), three (FP32)
   size_t h_U1 = 0, h_W2h = 0, h_U2 = 0, h_Wo = 0;         // forward chain layers
   size_t h_WoT = 0, h_U2T = 0, h_W2hs = 0, h_U1T = 0;     // reverse chain layers
   size_t o_WbR = 0, o_W1R = 0, o_W1TR = 0;                // kind 0: bf16-valued floats

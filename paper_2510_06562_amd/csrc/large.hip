@@ -28,15 +28,16 @@ namespace dmts {
 namespace {
 
 constexpr int kWaves = 4;
-constexpr int kAtomsPerWg = 2;   // pair kernels: two waves (channel halves) per receiver
+// Pair kernels: a work-group owns one channel half (64 channels) of kWaves receivers, one
+// wave each; work-group b takes half b & 1, so the grid is even and a work-group keeps its
+// half (and the staged weights of that half) over its grid-stride loop.
 constexpr int K_L = 32;
 constexpr int F_L = 128;
 constexpr int Z_MAX = 8;
 constexpr int NMOM = 10;   // M0, M1 (x, y, z), M2 (xx, yy, zz, xy, xz, yz)
 
 struct LargeParams {
-  const float* WbT;   // [K][F] radial block of the interaction
-  const __bf16* Wb16; // [F][K] the same block as bfloat16 (BF16 form only)
+  const __bf16* Wb;   // [NP][F][K] radial block of the interaction as NP bfloat16 terms
   const float* Td;    // [Z][F] layer 1 receiver table
   const float* Ts;    // [Z][F] layer 1 sender table
   float rc, sigma;
@@ -44,20 +45,21 @@ struct LargeParams {
 };
 
 // ------------------------------------------------------------------ MFMA pair kernels
-// One wavefront per receiver, 16-pair row tiles (rows are padded to 16).  Pair geometry
-// (d, r) comes from the neighbor list, which is built at the evaluation's positions.
-// Lane l has group g = l / 16 and column cl = l % 16; v_mfma_f32_16x16x4f32 layout:
-//   A operand: A[cl][k0 + g], B operand: B[k0 + g][cl], D register r: D[4 g + r][cl].
+// One wavefront per receiver and channel half (64 channels), 16-pair row tiles (rows are
+// padded to 16).  Pair geometry (d, r) comes from the neighbor list, which is built at the
+// evaluation's positions.  Lane l has group g = l / 16 and column cl = l % 16.
 //
-// The radial contraction over K = 32 takes, in step s = 0..7, the K index k = 8 g + s in
-// group g (both operands agree on it), so that a lane's eight weights W_b[c][8g .. 8g+7]
-// are two 16-byte LDS reads.
+// Radial contraction a = W_b b (K = 32) on v_mfma_f32_16x16x32_bf16 (A operand: lane l
+// holds A[l % 16][8 g + e], B operand B[8 g + e][l % 16], e = 0..7).  The operands are
+// given as NP bfloat16 terms: NP = 1 in the BF16 form (b and W_b rounded to nearest even),
+// NP = 3 in the FP32 form, where x = x1 + x2 + x3 exactly (x1 = bf16(x), x2 = bf16(x - x1),
+// x3 = bf16(x - x1 - x2)) and the six products x_i y_j with i + j <= 4 are accumulated in
+// FP32, smallest first; the dropped terms are below 2^-24 |W||b|, the size of FP32
+// rounding.  The other contractions use v_mfma_f32_16x16x4f32 (A: A[cl][k0 + g],
+// B: B[k0 + g][cl], D register r: D[4 g + r][cl]) in FP32.
 // Forward: a = b W_b as D[pair][channel] (pair 4g + r, channel 16 blk + cl).  The moments
 // M^T[y][c] = sum_p Y[p][y] m[p][c] then use that accumulator as their B operand: in step
 // s the K index g stands for pair 4g + s, i.e. register s of the lane.
-// BF16 form: the radial contraction is one v_mfma_f32_16x16x32_bf16 per 16 x 16 block (A
-// operand: lane l holds A[l % 16][8 g + e], B operand B[8 g + e][l % 16], e = 0..7), with
-// b and W_b rounded to bfloat16; moments, their reverse and all elementwise math stay FP32.
 // Reverse pass: the transposed product a^T = W_b b^T as D[channel][pair] (channel
 // 16 blk + 4g + r, pair cl): each lane owns one pair and 32 channels, so the channel sums
 // of a pair are in-lane plus two cross-group shuffles; dm^T = D_i^T Y^T likewise.  The
@@ -67,10 +69,73 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTile = 16;
-constexpr int kLdK = 40;    // LDS stride (bfloat16) of W_b rows [c][k] in the BF16 form
 constexpr int kLdM = 68;    // LDS stride of the per-wave moment rows (64 channels)
-constexpr int kLdT = 36;    // LDS stride of W_b rows [c][k]
-constexpr int kLdH = 80;    // LDS stride of per-half rows (64 channels)
+
+// W_b rows [c][k] in LDS, 32 bfloat16 per row; the 16-byte chunk index k / 8 is XORed with
+// bits 2..3 of the row so that the 16 rows read by one lane group fall in distinct banks.
+__device__ __forceinline__ int wsw(int row, int chunk) {
+  return row * K_L + 8 * (chunk ^ ((row >> 2) & 3));
+}
+
+// Per-wave adjoint rows D[y][cc] (64 channels, stride kLdH = 80): the low two bits of the
+// column are XORed with bits 2..3 of the row, so that both the row-wise reads of dm^T
+// (row 4 s + g in group g) and the column-wise reads of the angular sums (row cl + 1 in
+// lane cl) fall in distinct banks, with addresses affine in the channel block.
+constexpr int kLdH = 80;
+__device__ __forceinline__ int dswz(int y, int cc) { return y * kLdH + (cc ^ ((y >> 2) & 3)); }
+
+// The lane's bfloat16 terms of eight radial values.
+template <int NP>
+__device__ __forceinline__ void split_terms(const float (&x)[8], bf16x8 (&t)[NP]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    t[0][e] = h;
+    if (NP == 3) {
+      const float r1 = x[e] - (float)h;
+      const __bf16 m = (__bf16)r1;
+      t[1][e] = m;
+      t[2][e] = (__bf16)(r1 - (float)m);
+    }
+  }
+}
+
+// acc += W_b . b over K = 32 for one 16 x 16 block from NP-term operands; w_is_a selects
+// the transposed product (W_b rows as the A operand).
+template <int NP>
+__device__ __forceinline__ f32x4 radial_block(const bf16x8 (&w)[NP], const bf16x8 (&b)[NP],
+                                              f32x4 acc, bool w_is_a) {
+  auto mf = [&](const bf16x8& wv, const bf16x8& bv, f32x4 c) {
+    return w_is_a ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, bv, c, 0, 0, 0)
+                  : __builtin_amdgcn_mfma_f32_16x16x32_bf16(bv, wv, c, 0, 0, 0);
+  };
+  if (NP == 3) {
+    acc = mf(w[2], b[0], acc);
+    acc = mf(w[1], b[1], acc);
+    acc = mf(w[0], b[2], acc);
+    acc = mf(w[1], b[0], acc);
+    acc = mf(w[0], b[1], acc);
+  }
+  return mf(w[0], b[0], acc);
+}
+
+// The NP terms of W_b local row `row` (of the staged half), chunk g, from LDS.
+template <int NP>
+__device__ __forceinline__ void load_w(const __bf16* sW, int row, int g, bf16x8 (&w)[NP]) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    w[p] = *reinterpret_cast<const bf16x8*>(&sW[p * (F_L / 2) * K_L + wsw(row, g)]);
+}
+
+// Rows 64 h .. 64 h + 63 of the W_b terms (channel half h), as local rows 0..63.
+template <int NP>
+__device__ __forceinline__ void stage_w(__bf16* sW, const __bf16* __restrict__ Wb, int h) {
+  constexpr int kHalf = F_L / 2;
+  for (int e = threadIdx.x; e < NP * K_L * kHalf; e += blockDim.x) {
+    const int p = e / (K_L * kHalf), c = (e / K_L) % kHalf, k = e % K_L;
+    sW[p * kHalf * K_L + wsw(c, k / 8) + k % 8] = Wb[(size_t)p * F_L * K_L + (size_t)(kHalf * h + c) * K_L + k];
+  }
+}
 
 // Y = [1, u, u u^T - |u|^2/3 (xx, yy, zz), xy, xz, yz], zero beyond the ten components.
 __device__ __forceinline__ float ycomp(int y, float ux, float uy, float uz) {
@@ -89,21 +154,6 @@ __device__ __forceinline__ float ycomp(int y, float ux, float uy, float uz) {
   return v;
 }
 
-// Sum over the 16 lanes of a DPP row; every lane gets the same bits.
-__device__ __forceinline__ float row16_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
-  return v;
-}
-
-// Column swizzle of the per-wave adjoint rows D[y][cc] (64 channels, stride kLdH): the low
-// two bits of the column are XORed with bits 2..3 of the row, so that both the row-wise
-// reads of dm^T (fixed y per group) and the column-wise reads of the angular sums (row
-// cl + 1 per lane) fall in distinct banks.
-__device__ __forceinline__ int dswz(int y, int cc) { return y * kLdH + (cc ^ ((y >> 2) & 3)); }
-
 // Cosine cutoff and its derivative (zero outside); pi_rc = pi / r_c.
 __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, float& fc,
                                           float& dfc) {
@@ -116,31 +166,24 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
 // Both pair kernels are latency bound at low occupancy: the registers of the forward kernel
 // are capped so that four waves share a SIMD, those of the reverse kernel for three (as
 // many work-groups per CU as their LDS allows).
-template <int LAYER, bool BF16>
+template <int LAYER, int NP>
 __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
-  __shared__ float sWt[BF16 ? 1 : F_L * kLdT];       // W_b [c][k]
-  __shared__ __bf16 sW16[BF16 ? F_L * kLdK : 1];
+  __shared__ __bf16 sW[NP * (F_L / 2) * K_L];   // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   __shared__ float sM[kWaves][NMOM * kLdM];
-  if (BF16) {
-    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
-      sW16[(e / K_L) * kLdK + e % K_L] = P.Wb16[e];
-  } else {
-    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
-      sWt[(e % F_L) * kLdT + e / F_L] = P.WbT[e];
-  }
+  const int half = blockIdx.x & 1, hb = 4 * half;   // hb: first channel block of the half
+  stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int n_wg = (n + kAtomsPerWg - 1) / kAtomsPerWg;
-  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
-  const int i = wg * kAtomsPerWg + (w >> 1);
+  const int n_ag = (n + kWaves - 1) / kWaves;
+  for (int ag = blockIdx.x >> 1; ag < n_ag; ag += gridDim.x >> 1) {
+  const int i = ag * kWaves + w;
   if (i >= n) continue;
-  const int hb = 4 * (w & 1);   // first channel block of this wave's half
   const int zi_s = species[i];
   float base[4];
 #pragma unroll
@@ -155,15 +198,17 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float pi_rc = 3.14159265358979f * irc;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
-    // A operand of a = b W_b: b_k of pair cl at k = 8 g + s
+    // A operand of a = b W_b: b_k of pair cl at k = 8 g + e, as NP bfloat16 terms
     const float rp = geo[t0 + cl].w;
     const bool vp = nbr[t0 + cl] >= 0 && rp < P.rc;
-    float bop[8];
+    float bk[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const float x = rp - P.sigma * (8 * g + s);
-      bop[s] = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+    for (int e = 0; e < 8; ++e) {
+      const float x = rp - P.sigma * (8 * g + e);
+      bk[e] = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
     }
+    bf16x8 bt[NP];
+    split_terms<NP>(bk, bt);
     // the lane's four pairs of the D layout: 4 g + r
     float fc[4], yop[4];
     int jj[4], zz[4];
@@ -179,41 +224,31 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       zz[r] = LAYER == 1 ? species[v ? j : i] : 0;
       yop[r] = v ? ycomp(cl, gv.x * irc, gv.y * irc, gv.z * irc) : (cl == 0 ? 1.f : 0.f);
     }
+    // sender terms of the lane's sixteen (pair, channel) values, all requested before the
+    // products so that their latencies overlap
+    float snd[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * (hb + b) + cl;
+        snd[b][r] = LAYER == 1 ? sTs[zz[r] * F_L + c]
+                               : P2[(size_t)(jj[r] >= 0 ? jj[r] : i) * 2 * F_L + c];
+      }
+    __builtin_amdgcn_sched_barrier(0);
     f32x4 acc[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (BF16) {
-      bf16x8 a8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a8[e] = (__bf16)bop[e];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const bf16x8 w8 =
-            *reinterpret_cast<const bf16x8*>(&sW16[(16 * (hb + b) + cl) * kLdK + 8 * g]);
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, w8, acc[b], 0, 0, 0);
-      }
-    } else {
-      // step s, group g <-> k = 8 g + s: the lane's weights W_b[c][8 g .. 8 g + 7]
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const float* wr = &sWt[(16 * (hb + b) + cl) * kLdT + 8 * g];
-        const float4 w0 = *reinterpret_cast<const float4*>(wr);
-        const float4 w1 = *reinterpret_cast<const float4*>(wr + 4);
-        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bop[s], wv[s], acc[b], 0, 0, 0);
-      }
+    for (int b = 0; b < 4; ++b) {
+      bf16x8 wt[NP];
+      load_w<NP>(sW, 16 * b + cl, g, wt);
+      acc[b] = radial_block<NP>(wt, bt, f32x4{0.f, 0.f, 0.f, 0.f}, false);
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int c = 16 * (hb + b) + cl;
       f32x4 mv;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float a = acc[b][r] + base[b];
-        if (LAYER == 1) a += sTs[zz[r] * F_L + c];
-        else a += P2[(size_t)(jj[r] >= 0 ? jj[r] : i) * 2 * F_L + c];   // f_c = 0 if invalid
+        const float a = acc[b][r] + base[b] + snd[b][r];   // f_c = 0 if invalid
         mv[r] = fc[r] * silu_f(a);
       }
 #pragma unroll
@@ -249,43 +284,39 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   }  // grid-stride loop over work-groups of atoms
 }
 
-template <int LAYER, bool BF16>
+// Per-pair-slot sums of dE/da (receiver sums), [slot][64 channels], stride 68.
+constexpr int kLdR = 68;
+
+constexpr bool kAhead = true;
+
+template <int LAYER, int NP>
 __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, const float* __restrict__ Mall,
                 const float* __restrict__ dq, float* __restrict__ dA, float* __restrict__ RS,
                 float* __restrict__ v, int64_t cap) {
-  __shared__ float sWt[BF16 ? 1 : F_L * kLdT];       // W_b [c][k]
-  __shared__ __bf16 sW16[BF16 ? F_L * kLdK : 1];      // W_b [c][k] as bfloat16
+  __shared__ __bf16 sW[NP * (F_L / 2) * K_L];         // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   // per wave, over its 64 channels (local index cc = c - 64 half)
-  __shared__ float sD[kWaves][NMOM * kLdH];          // D[y][cc] of the receiver
+  __shared__ float sD[kWaves][NMOM * kLdH];          // D[y][cc] of the receiver (dswz)
   __shared__ float sB[kWaves][F_L / 2];              // receiver term S_i of a_ij
-  __shared__ float sR[LAYER == 2 ? kWaves : 1][kTile][F_L / 2 + 4];  // per-pair-slot sums of dE/da
-  if (BF16) {
-    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x)
-      sW16[(e / K_L) * kLdK + e % K_L] = P.Wb16[e];
-  } else {
-    for (int e = threadIdx.x; e < K_L * F_L; e += blockDim.x) {
-      const int k = e / F_L, c = e % F_L;
-      sWt[c * kLdT + k] = P.WbT[e];
-    }
-  }
+  __shared__ float sR[LAYER == 2 ? kWaves : 1][LAYER == 2 ? kTile * kLdR : 1];
+  const int half = blockIdx.x & 1, hb = 4 * half;
+  stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int n_wg = (n + kAtomsPerWg - 1) / kAtomsPerWg;
-  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
-  const int i = wg * kAtomsPerWg + (w >> 1);
+  const int n_ag = (n + kWaves - 1) / kWaves;
+  for (int ag = blockIdx.x >> 1; ag < n_ag; ag += gridDim.x >> 1) {
+  const int i = ag * kWaves + w;
   if (i >= n) continue;
-  const int half = w & 1, hb = 4 * half;
   float* sd = sD[w];
   float* vh = v + (size_t)half * 3 * cap;   // this half's share of v_ij
   const int zi_s = species[i];
   // D[y][c]: dE/dq folded with dq/dM, off-diagonal M2 components doubled, so that
-  // dm = sum_y Y[y] D[y].  Stored with the column swizzle dswz(y, cc).
+  // dm = sum_y Y[y] D[y]
   {
     const float* Mi = Mall + (size_t)i * NMOM * F_L;
     const float* dqi = dq + (size_t)i * 3 * F_L;
@@ -305,7 +336,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     const float* src = LAYER == 1 ? P.Td + zi_s * F_L : P2 + (size_t)i * 2 * F_L + F_L;
     sB[w][lane] = src[16 * hb + lane];
     if (LAYER == 2)
-      for (int e = lane; e < kTile * (F_L / 2); e += 64) sR[w][e / (F_L / 2)][e % (F_L / 2)] = 0.f;
+      for (int e = lane; e < kTile * kLdR; e += 64) sR[w][e] = 0.f;
   }
   wave_sync();
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
@@ -325,22 +356,19 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float fc, dfc;
     cutoff_fn(gv.w, pi_rc, vp, fc, dfc);
     const float ux = vp ? gv.x * irc : 0.f, uy = vp ? gv.y * irc : 0.f, uz = vp ? gv.z * irc : 0.f;
-    // radial operands b_k(r), b'_k(r) at k = 8 g + s
-    float bop[8], dbop[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const float x = gv.w - P.sigma * (8 * g + s);
-      const float bk = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
-      bop[s] = bk;
-      dbop[s] = -x * inv_s2 * bk;
-    }
-    bf16x8 b8, db8;
-    if (BF16) {
+    // radial operands b_k(r), b'_k(r) at k = 8 g + e, as NP bfloat16 terms
+    bf16x8 bt[NP], dbt[NP];
+    {
+      float bk[8], dbk[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        b8[e] = (__bf16)bop[e];
-        db8[e] = (__bf16)dbop[e];
+        const float x = gv.w - P.sigma * (8 * g + e);
+        const float b = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+        bk[e] = b;
+        dbk[e] = -x * inv_s2 * b;
       }
+      split_terms<NP>(bk, bt);
+      split_terms<NP>(dbk, dbt);
     }
     float yop[3];   // B operand of dm^T: Y^T[4 s + g][pair cl]
 #pragma unroll
@@ -353,28 +381,19 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     // channels (index g <-> channel 16 b + 4 g + s, register s of m^T), the A operand is
     // D[16 b + 4 g + s][k + 1] for row k = cl < 9.
     f32x4 Gt = {0.f, 0.f, 0.f, 0.f};
-    // The three products of channel block bb4: a^T and a'^T = W_b b^T, W_b b'^T (step s,
-    // group g <-> k = 8 g + s) and dm^T = D^T Y^T.  They are issued one block ahead, so
-    // that the matrix cores work on block bb4 + 1 while the vector units finish bb4.
-    auto issue = [&](int bb4, f32x4& ga, f32x4& gd, f32x4& dmv) {
-      const int b = hb + bb4;
-      ga = f32x4{0.f, 0.f, 0.f, 0.f};
-      gd = ga;
-      dmv = ga;
-      if (BF16) {
-        const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(&sW16[(16 * b + cl) * kLdK + 8 * g]);
-        ga = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, b8, ga, 0, 0, 0);
-        gd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, db8, gd, 0, 0, 0);
-      } else {
-        const float4 w0 = *reinterpret_cast<const float4*>(&sWt[(16 * b + cl) * kLdT + 8 * g]);
-        const float4 w1 = *reinterpret_cast<const float4*>(&sWt[(16 * b + cl) * kLdT + 8 * g + 4]);
-        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          ga = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[s], bop[s], ga, 0, 0, 0);
-          gd = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[s], dbop[s], gd, 0, 0, 0);
-        }
-      }
+    // The three products of channel block bb4: a^T and a'^T = W_b b^T, W_b b'^T and
+    // dm^T = D^T Y^T.  They are issued one block ahead, so that the matrix cores work on
+    // block bb4 + 1 while the vector units finish bb4.
+    auto issue = [&](int bb4, f32x4& ga, f32x4& gd, f32x4& dmv, float4& add) {
+      // sender term of the lane's four channels 16 b + 4 g .. + 3
+      const int c0 = 16 * (hb + bb4) + 4 * g;
+      add = LAYER == 2 ? *reinterpret_cast<const float4*>(Aj + c0)
+                       : *reinterpret_cast<const float4*>(Tj + c0);
+      bf16x8 wt[NP];
+      load_w<NP>(sW, 16 * bb4 + cl, g, wt);
+      ga = radial_block<NP>(wt, bt, f32x4{0.f, 0.f, 0.f, 0.f}, true);
+      gd = radial_block<NP>(wt, dbt, f32x4{0.f, 0.f, 0.f, 0.f}, true);
+      dmv = f32x4{0.f, 0.f, 0.f, 0.f};
       // K index 4 s + g = y runs over the ten components; rows 10 and 11 are zero and
       // rows 12..15 (s = 3) are left out
 #pragma unroll
@@ -385,20 +404,17 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       }
     };
     f32x4 ga, gd, dmv;
-    issue(0, ga, gd, dmv);
+    float4 add;
+    if (kAhead) issue(0, ga, gd, dmv, add);
 #pragma unroll
     for (int bb4 = 0; bb4 < 4; ++bb4) {
       f32x4 ga_n, gd_n, dmv_n;
-      if (bb4 < 3) issue(bb4 + 1, ga_n, gd_n, dmv_n);
+      float4 add_n;
+      if (!kAhead) issue(bb4, ga, gd, dmv, add);
+      else if (bb4 < 3) issue(bb4 + 1, ga_n, gd_n, dmv_n, add_n);
       const int b = hb + bb4;
       const int c0 = 16 * b + 4 * g;   // the lane's four channels c0 .. c0+3
       const int l0 = 16 * bb4 + 4 * g;  // their index within the half
-      float4 add = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (LAYER == 2) {
-        add = *reinterpret_cast<const float4*>(Aj + c0);
-      } else {
-        add = *reinterpret_cast<const float4*>(Tj + c0);
-      }
       const float4 bb = *reinterpret_cast<const float4*>(&sB[w][l0]);
       f32x4 mv;
       float4 dav;
@@ -424,7 +440,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       }
       if (LAYER == 2) {
         *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
-        float4* acc = reinterpret_cast<float4*>(&sR[w][cl][l0]);
+        float4* acc = reinterpret_cast<float4*>(&sR[w][cl * kLdR + l0]);
         float4 t = *acc;
         t.x += dav.x;
         t.y += dav.y;
@@ -432,10 +448,11 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         t.w += dav.w;
         *acc = t;
       }
-      if (bb4 < 3) {
+      if (kAhead && bb4 < 3) {
         ga = ga_n;
         gd = gd_n;
         dmv = dmv_n;
+        add = add_n;
       }
       // one region per block: the live products are those of two blocks
       __builtin_amdgcn_sched_barrier(0);
@@ -479,7 +496,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     // receiver sums: add the 16 pair slots in a fixed order
     wave_sync();
     float t = 0.f;
-    for (int k = 0; k < kTile; ++k) t += sR[w][k][lane];
+    for (int k = 0; k < kTile; ++k) t += sR[w][k * kLdR + lane];
     RS[(size_t)i * 2 * F_L + 16 * hb + lane] = t;
   }
   }  // grid-stride loop over work-groups of atoms
@@ -577,10 +594,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   }
   float* W = m->atom_ws.as<float>();
   float* e_atom = atom_energy ? atom_energy : W + o_e;
-  LargeParams P1{m->p(m->o_WbT), m->bf16 ? m->p16(m->h_Wb1) : nullptr, m->p(m->o_Td),
-                 m->p(m->o_Ts), m->rc, m->sigma, m->Z};
-  LargeParams P2{m->p(m->o_W2bT), m->bf16 ? m->p16(m->h_Wb2) : nullptr, nullptr, nullptr, m->rc,
-                 m->sigma, m->Z};
+  LargeParams P1{m->p16(m->h_Wb1), m->p(m->o_Td), m->p(m->o_Ts), m->rc, m->sigma, m->Z};
+  LargeParams P2{m->p16(m->h_Wb2), nullptr, nullptr, m->rc, m->sigma, m->Z};
   AtomMlpParams A{m->p(m->o_U1),  m->p(m->o_W2h), m->p(m->o_U2),   m->p(m->o_Wo),
                   m->p(m->o_wo),  m->p(m->o_WoT), m->p(m->o_U2T),  m->p(m->o_W2hs),
                   m->p(m->o_U1T)};
@@ -595,19 +610,22 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
     A.h_U1T = m->p16(m->h_U1T);
   }
   const int blocks = ceil_div(n, kWaves);
-  const int pblocks = m->launch_grid(ceil_div(n, kAtomsPerWg));
-  // the whole evaluation, instantiated for the FP32 and the BF16 form
-  auto run = [&](auto bf_tag) -> dmts_status {
-    constexpr bool BF = decltype(bf_tag)::value;
+  // two work-groups (channel halves) per kWaves receivers; an even grid of at least two
+  int pblocks = m->launch_grid(2 * ceil_div(n, kWaves));
+  pblocks = pblocks < 2 ? 2 : pblocks + (pblocks & 1);
+  // the whole evaluation, instantiated for the FP32 (three-term radial operands) and the
+  // BF16 form (one term)
+  auto run = [&](auto np_tag) -> dmts_status {
+    constexpr int NP = decltype(np_tag)::value;
     dmts_status st;
     if (n > 0) {
       { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
-      k_pair_fwd_mfma<1, BF><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
+      k_pair_fwd_mfma<1, NP><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
                                                         nullptr, W + o_M1, W + o_q1); }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
       { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
-      k_pair_fwd_mfma<2, BF><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
+      k_pair_fwd_mfma<2, NP><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
                                                         W + o_P2, W + o_M2, W + o_q2); }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
@@ -616,7 +634,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         float* dA = m->pair_ws.as<float>();
         float* v = dA + (size_t)cap * F;
         { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
-        k_pair_bwd_mfma<2, BF><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
+        k_pair_bwd_mfma<2, NP><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
                                                           n, W + o_P2, W + o_M2, W + o_dq2, dA,
                                                           W + o_RS, v, cap); }
         DMTS_CHECK_LAUNCH();
@@ -626,7 +644,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
           return st;
         { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
-        k_pair_bwd_mfma<1, BF><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
+        k_pair_bwd_mfma<1, NP><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
                                                           n, nullptr, W + o_M1, W + o_dq1, nullptr,
                                                           nullptr, v, cap); }
         DMTS_CHECK_LAUNCH();
@@ -638,7 +656,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
 
     return DMTS_OK;
   };
-  const dmts_status rs = m->bf16 ? run(std::true_type{}) : run(std::false_type{});
+  const dmts_status rs = m->bf16 ? run(std::integral_constant<int, 1>{})
+                                 : run(std::integral_constant<int, 3>{});
   if (rs != DMTS_OK) return rs;
   if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, s);
   return DMTS_OK;
