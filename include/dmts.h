@@ -114,7 +114,7 @@ void nnp_model_destroy(nnp_model* model);
  * changes speed only, never results.  nnp_model_set_grid sets it (0 = one work-group per
  * group of receivers, the default; k > 0 = a persistent grid of at most k work-groups).
  * nnp_autotune times one energy+force evaluation on the given system for each candidate
- * (0, 256, 512, 1024, 2048, 4096; median of `reps` after a warm-up, HIP events on
+ * (0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096; median of `reps` after a warm-up, HIP events on
  * `stream`), keeps the fastest in the model and returns it in *chosen (host) with its time
  * in *best_ms (host).  Blocking: synchronizes the stream and allocates scratch. */
 dmts_status nnp_model_set_grid(nnp_model* model, int32_t work_groups);

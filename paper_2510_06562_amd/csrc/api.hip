@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -103,6 +105,25 @@ k_reduce_energy(const float* __restrict__ atom_e, int n, const int32_t* __restri
 }
 
 }  // namespace
+
+int resident_groups(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({dev, kernel});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int r = per_cu * cus;
+  cache[{dev, kernel}] = r;
+  return r;
+}
 
 dmts_status reduce_energy(const float* atom_e, int32_t n, const int32_t* sys_offsets,
                           int32_t n_sys, double* energy, hipStream_t s) {
@@ -481,7 +502,8 @@ extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* 
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const int32_t cands[] = {0, 256, 512, 1024, 2048, 4096};
+  // the natural grid, then multiples of the 256 compute units
+  const int32_t cands[] = {0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096};
   const int32_t saved = m->grid;
   int32_t best = saved;
   double best_t = 1e300;

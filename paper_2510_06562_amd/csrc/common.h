@@ -105,9 +105,19 @@ struct Model {
   int32_t grid = 0;
   // workspace
   DevBuf atom_ws, pair_ws, sys_ws;
-  int launch_grid(int natural) const { return grid > 0 && grid < natural ? grid : natural; }
+  // natural: work-groups for one pass over the receivers; resident: how many the GPU holds
+  // at once.  With the default grid, a pass that would take between one and two rounds of
+  // work-groups runs as one persistent round instead of a full and a partly filled one.
+  int launch_grid(int natural, int resident = 0) const {
+    if (grid > 0) return grid < natural ? grid : natural;
+    return resident > 0 && natural > resident && natural < 2 * resident ? resident : natural;
+  }
   const float* p(size_t off) const { return params.as<float>() + off; }
 };
+
+// Work-groups of `kernel` (launched with `threads` threads each) that the current device
+// holds at once, from the occupancy calculator; cached per device and kernel.
+int resident_groups(const void* kernel, int threads);
 
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos,
                                 const int32_t* species, int32_t n, double box,

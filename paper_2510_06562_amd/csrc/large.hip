@@ -52,10 +52,10 @@ struct LargeParams {
 // Radial contraction a = W_b b (K = 32) on v_mfma_f32_16x16x32_bf16 (A operand: lane l
 // holds A[l % 16][8 g + e], B operand B[8 g + e][l % 16], e = 0..7).  The operands are
 // given as NP bfloat16 terms: NP = 1 in the BF16 form (b and W_b rounded to nearest even),
-// NP = 3 in the FP32 form, where x = x1 + x2 + x3 exactly (x1 = bf16(x), x2 = bf16(x - x1),
-// x3 = bf16(x - x1 - x2)) and the six products x_i y_j with i + j <= 4 are accumulated in
-// FP32, smallest first; the dropped terms are below 2^-24 |W||b|, the size of FP32
-// rounding.  The other contractions use v_mfma_f32_16x16x4f32 (A: A[cl][k0 + g],
+// NP = 3 in the FP32 form, where x = x1 + x2 + x3 exactly (each term carries the next
+// eight significant bits of x) and the six products x_i y_j with i + j <= 4 are
+// accumulated in FP32, smallest first; the dropped terms are below 2^-24 |W||b|, the size
+// of FP32 rounding.  The other contractions use v_mfma_f32_16x16x4f32 (A: A[cl][k0 + g],
 // B: B[k0 + g][cl], D register r: D[4 g + r][cl]) in FP32.
 // Forward: a = b W_b as D[pair][channel] (pair 4g + r, channel 16 blk + cl).  The moments
 // M^T[y][c] = sum_p Y[p][y] m[p][c] then use that accumulator as their B operand: in step
@@ -84,19 +84,35 @@ __device__ __forceinline__ int wsw(int row, int chunk) {
 constexpr int kLdH = 80;
 __device__ __forceinline__ int dswz(int y, int cc) { return y * kLdH + (cc ^ ((y >> 2) & 3)); }
 
-// The lane's bfloat16 terms of eight radial values.
+// The lane's bfloat16 terms of eight radial values.  NP = 1: round to nearest even.
+// NP = 3: truncating split, x = t1 + t2 + t3 exactly (t1 = x with the low 16 bits cleared,
+// t2 likewise of x - t1, t3 = x - t1 - t2, which has at most eight significant bits); a
+// term's bfloat16 is then the high half of its FP32 bits, packed two at a time.
 template <int NP>
 __device__ __forceinline__ void split_terms(const float (&x)[8], bf16x8 (&t)[NP]) {
+  if (NP == 1) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[0][e] = (__bf16)x[e];
+    return;
+  }
+  uint32_t u[3][8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)x[e];
-    t[0][e] = h;
-    if (NP == 3) {
-      const float r1 = x[e] - (float)h;
-      const __bf16 m = (__bf16)r1;
-      t[1][e] = m;
-      t[2][e] = (__bf16)(r1 - (float)m);
-    }
+    const uint32_t h = __float_as_uint(x[e]) & 0xffff0000u;
+    const float r1 = x[e] - __uint_as_float(h);
+    const uint32_t m = __float_as_uint(r1) & 0xffff0000u;
+    u[0][e] = h;
+    u[1][e] = m;
+    u[2][e] = __float_as_uint(r1 - __uint_as_float(m));
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)   // high halves of elements 2q (low) and 2q + 1 (high)
+      w[q] = __builtin_amdgcn_perm(u[p][2 * q + 1], u[p][2 * q], 0x07060302u);
+    t[p] = __builtin_bit_cast(bf16x8, w);
   }
 }
 
@@ -611,8 +627,10 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   }
   const int blocks = ceil_div(n, kWaves);
   // two work-groups (channel halves) per kWaves receivers; an even grid of at least two
-  int pblocks = m->launch_grid(2 * ceil_div(n, kWaves));
-  pblocks = pblocks < 2 ? 2 : pblocks + (pblocks & 1);
+  auto pgrid = [&](const void* kernel) {
+    const int b = m->launch_grid(2 * ceil_div(n, kWaves), resident_groups(kernel, kWaves * 64));
+    return b < 2 ? 2 : b + (b & 1);
+  };
   // the whole evaluation, instantiated for the FP32 (three-term radial operands) and the
   // BF16 form (one term)
   auto run = [&](auto np_tag) -> dmts_status {
@@ -620,12 +638,12 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
     dmts_status st;
     if (n > 0) {
       { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
-      k_pair_fwd_mfma<1, NP><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
+      k_pair_fwd_mfma<1, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_fwd_mfma<1, NP>)), kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
                                                         nullptr, W + o_M1, W + o_q1); }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
       { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
-      k_pair_fwd_mfma<2, NP><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
+      k_pair_fwd_mfma<2, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_fwd_mfma<2, NP>)), kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
                                                         W + o_P2, W + o_M2, W + o_q2); }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
@@ -634,7 +652,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         float* dA = m->pair_ws.as<float>();
         float* v = dA + (size_t)cap * F;
         { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
-        k_pair_bwd_mfma<2, NP><<<pblocks, kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
+        k_pair_bwd_mfma<2, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_bwd_mfma<2, NP>)), kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
                                                           n, W + o_P2, W + o_M2, W + o_dq2, dA,
                                                           W + o_RS, v, cap); }
         DMTS_CHECK_LAUNCH();
@@ -644,7 +662,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
           return st;
         { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
-        k_pair_bwd_mfma<1, NP><<<pblocks, kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
+        k_pair_bwd_mfma<1, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_bwd_mfma<1, NP>)), kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
                                                           n, nullptr, W + o_M1, W + o_dq1, nullptr,
                                                           nullptr, v, cap); }
         DMTS_CHECK_LAUNCH();

@@ -21,6 +21,8 @@
 // BF16 form: v_mfma_f32_16x16x16_bf16 (A: A[l%16][4 (l/16) + e], B: B[4 (l/16) + e][l%16],
 // e = 0..3) with b, b' and W_r rounded to bfloat16; the readout uses bfloat16-valued W1 and
 // activations with FP32 accumulation.  Geometry and elementwise math are FP32.
+#include <type_traits>
+
 #include "common.h"
 
 namespace dmts {
@@ -337,26 +339,25 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
                 m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
                 m->p(m->o_w2), m->rc, m->sigma, m->escale, m->Z};
   if (n > 0) {
-    const int blocks = m->launch_grid(ceil_div(n, kWaves));
-    { ProfScope ps(DMTS_K_SMALL_FORWARD, s);
-    if (m->bf16)
-      k_small_fwd<true><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n, box,
+    const int natural = ceil_div(n, kWaves);
+    auto run = [&](auto bf_tag) {
+      constexpr bool BF = decltype(bf_tag)::value;
+      {
+        ProfScope ps(DMTS_K_SMALL_FORWARD, s);
+        const int blocks = m->launch_grid(
+            natural, resident_groups(reinterpret_cast<const void*>(&k_small_fwd<BF>), kWaves * 64));
+        k_small_fwd<BF><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n, box,
                                                        e_atom, g, ell_j, ell_g, ell_n, nl->flags);
-    else
-      k_small_fwd<false><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n,
-                                                        box, e_atom, g, ell_j, ell_g, ell_n,
-                                                        nl->flags); }
+      }
+      if (hipPeekAtLastError() != hipSuccess || !forces) return;
+      ProfScope ps(DMTS_K_SMALL_BACKWARD, s);
+      const int blocks = m->launch_grid(
+          natural, resident_groups(reinterpret_cast<const void*>(&k_small_bwd<BF>), kWaves * 64));
+      k_small_bwd<BF><<<blocks, kWaves * 64, 0, s>>>(P, species, n, g, ell_j, ell_g, ell_n, forces);
+    };
+    if (m->bf16) run(std::true_type{});
+    else run(std::false_type{});
     DMTS_CHECK_LAUNCH();
-    if (forces) {
-      { ProfScope ps(DMTS_K_SMALL_BACKWARD, s);
-      if (m->bf16)
-        k_small_bwd<true><<<blocks, kWaves * 64, 0, s>>>(P, species, n, g, ell_j, ell_g, ell_n,
-                                                         forces);
-      else
-        k_small_bwd<false><<<blocks, kWaves * 64, 0, s>>>(P, species, n, g, ell_j, ell_g, ell_n,
-                                                          forces); }
-      DMTS_CHECK_LAUNCH();
-    }
   }
   if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, s);
   return DMTS_OK;

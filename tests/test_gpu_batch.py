@@ -61,7 +61,7 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
     E0, F0 = pot(pos, sp)
     g, t = api.autotune(pot, pos, sp, reps=2)
-    assert g in (0, 256, 512, 1024, 2048, 4096) and t > 0
+    assert g in (0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096) and t > 0
     assert model.grid == g
     E, F = pot(pos, sp)
     assert torch.equal(E, E0) and torch.equal(F, F0)
