@@ -101,6 +101,54 @@ __global__ void k_cell_scatter(const int32_t* __restrict__ cell_of, int32_t n,
   cell_atoms[slot] = i;
 }
 
+// All three binning steps in one work-group, for cell grids that fit in LDS: cell ids and
+// counts (LDS atomics), the exclusive scan into cell_start, then the scatter through LDS
+// cursors.  The order of the atoms inside a cell is arbitrary; rows are sorted afterwards.
+constexpr int kBinThreads = 1024;
+constexpr int kBinCells = 4096;
+constexpr int kBinAtoms = 32768;   // above this, the multi-work-group binning is faster
+__global__ void __launch_bounds__(kBinThreads)
+k_bin_one(const double* __restrict__ pos, int32_t n, double box, double inv_cell, int nc,
+          int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_start,
+          int32_t* __restrict__ cell_atoms) {
+  __shared__ int32_t cnt[kBinCells];
+  __shared__ int32_t part[kBinThreads];
+  const int t = threadIdx.x, n_cells = nc * nc * nc;
+  for (int c = t; c < n_cells; c += kBinThreads) cnt[c] = 0;
+  __syncthreads();
+  for (int i = t; i < n; i += kBinThreads) {
+    const int c = (cell_coord(pos[2 * n + i], box, inv_cell, nc) * nc +
+                   cell_coord(pos[n + i], box, inv_cell, nc)) * nc +
+                  cell_coord(pos[i], box, inv_cell, nc);
+    cell_of[i] = c;
+    atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  // exclusive scan: contiguous chunks per thread, Hillis-Steele over the chunk sums
+  const int per = (n_cells + kBinThreads - 1) / kBinThreads;
+  const int lo = min(n_cells, t * per), hi = min(n_cells, lo + per);
+  int sum = 0;
+  for (int c = lo; c < hi; ++c) sum += cnt[c];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kBinThreads; off <<= 1) {
+    const int add = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int run = t == 0 ? 0 : part[t - 1];
+  for (int c = lo; c < hi; ++c) {
+    const int k = cnt[c];
+    cell_start[c] = run;
+    cnt[c] = run;   // becomes the cursor
+    run += k;
+  }
+  if (t == 0) cell_start[n_cells] = n;
+  __syncthreads();
+  for (int i = t; i < n; i += kBinThreads) cell_atoms[atomicAdd(&cnt[cell_of[i]], 1)] = i;
+}
+
 struct Geo {
   const double* pos;
   int32_t n;
@@ -163,14 +211,21 @@ __device__ __forceinline__ void walk_candidates(int i, int lo, int hi, const Cel
   }
   const int total = __shfl(incl, 26, 64);
   wave_sync();
-  for (int base = 0; base < total; base += 64) {
-    int t = base + lane;
-    int j = -1;
-    if (t < total) {
-      int k = 0;
-      while (k < 26 && s_pref[k + 1] <= t) ++k;
-      j = cc.cell_atoms[s_first[k] + (t - s_pref[k])];
+  // candidate t: the last stencil cell k with s_pref[k] <= t (binary search over 27)
+  auto cand = [&](int t) {
+    if (t >= total) return -1;
+    int a = 0, b = 27;
+    while (b - a > 1) {
+      const int m = (a + b) >> 1;
+      if (s_pref[m] <= t) a = m; else b = m;
     }
+    return cc.cell_atoms[s_first[a] + (t - s_pref[a])];
+  };
+  // the next batch's candidates are looked up while this batch is tested
+  int jn = cand(lane);
+  for (int base = 0; base < total; base += 64) {
+    const int j = jn;
+    if (base + 64 < total) jn = cand(base + 64 + lane);
     bool ok = j >= 0 && j != i;
     visit(j, ok);
   }
@@ -260,12 +315,21 @@ k_compact(Geo gm, const int32_t* __restrict__ ell, const int32_t* __restrict__ l
     int r = -1;
     if (j >= 0) {
       const int32_t* rj = ell + (size_t)j * kRowCap;
-      int a = 0, b = len[j];        // lower bound of i in rj[0 .. len_j)
-      while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (rj[mid] < i) a = mid + 1; else b = mid;
+      const int lj = len[j];
+      // lower bound of i in rj[0 .. lj): rj[a - 1] < i <= rj[b] (bounds excluded); three
+      // independent probes per round narrow the range four-fold
+      int a = 0, b = lj;
+      while (b - a >= 4) {
+        const int q = (b - a) >> 2;
+        const int m1 = a + q, m2 = a + 2 * q, m3 = a + 3 * q;
+        const int v1 = rj[m1], v2 = rj[m2], v3 = rj[m3];
+        if (v3 < i) a = m3 + 1;
+        else if (v2 < i) { a = m2 + 1; b = m3; }
+        else if (v1 < i) { a = m1 + 1; b = m2; }
+        else b = m1;
       }
-      r = (a < len[j] && rj[a] == i) ? offs[j] + a : -1;
+      while (a < b && rj[a] < i) ++a;
+      r = (a < lj && rj[a] == i) ? offs[j] + a : -1;
     }
     float4 gv = make_float4(0.f, 0.f, 0.f, 0.f);
     if (j >= 0) {
@@ -330,14 +394,20 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
     int32_t* cell_start = cell_count + nl->n_cells_cap;
     int32_t* cursor = cell_start + nl->n_cells_cap + 1;
     const double inv_cell = nc / box;
-    k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
-                                                   cell_count);
-    DMTS_CHECK_LAUNCH();
-    k_scan<<<1, kScanThreads, 0, s>>>(cell_count, cell_start, cursor, n_cells, INT64_MAX,
-                                      nullptr, true);
-    DMTS_CHECK_LAUNCH();
-    k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms);
-    DMTS_CHECK_LAUNCH();
+    if (n_cells <= kBinCells && n <= kBinAtoms) {
+      k_bin_one<<<1, kBinThreads, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of, cell_start,
+                                          nl->cell_atoms);
+      DMTS_CHECK_LAUNCH();
+    } else {
+      k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
+                                                     cell_count);
+      DMTS_CHECK_LAUNCH();
+      k_scan<<<1, kScanThreads, 0, s>>>(cell_count, cell_start, cursor, n_cells, INT64_MAX,
+                                        nullptr, true);
+      DMTS_CHECK_LAUNCH();
+      k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms);
+      DMTS_CHECK_LAUNCH();
+    }
     cc = CellCtx{cell_start, nl->cell_atoms, nl->cell_of, nc};
   }
   const int blocks = ceil_div(n, kNbWaves);

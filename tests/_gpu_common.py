@@ -31,6 +31,10 @@ def system(name):
         b = synth.molecule_batch(1, seed=12, lo=30, hi=30)
         b.sys_offsets = None
         return b
+    if name == "water21k":
+        # 7,000 molecules in a 59.6 A box: 17^3 cells at 3.5 A, above the one-work-group
+        # binning limit of 4,096 cells, so the list takes the multi-kernel binning
+        return synth.water_box(7000, 59.6, seed=21)
     if name == "wrapped1500":
         rng = np.random.default_rng(5)
         pos = rng.uniform(-30.0, 50.0, size=(1500, 3))

@@ -45,7 +45,7 @@ def _pairs_of(nl, n):
 @pytest.mark.parametrize("sysname,cut,align", [("water192", 3.5, 4), ("water192", 5.2, 16),
                                                ("water4500", 3.5, 4), ("water4500", 5.2, 16),
                                                ("batch16", 5.2, 16), ("open60", 3.5, 32),
-                                               ("wrapped1500", 5.2, 4)])
+                                               ("wrapped1500", 5.2, 4), ("water21k", 3.5, 4)])
 def test_neighbor_set_matches_oracle(sysname, cut, align):
     say(f"nlist {sysname} rc={cut} align={align}")
     sy = system(sysname)
