@@ -62,21 +62,46 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
+// Weights in LDS: W_r [c][k], the species tables and (forward kernel only) W1 [c][e].
+template <bool kReadout>
 struct SmallLds {
-  float W[F_S * kLdW];        // W_r [c][k]
+  float W[F_S * kLdW];
   float Td[Z_MAX][F_S], Ts[Z_MAX][F_S];
-  float W1[F_S][F_S + 1];     // W1 [c][e]
+  float W1[kReadout ? F_S : 1][F_S + 1];
 };
 
-__device__ void load_params(SmallLds& L, const SmallParams& P) {
-  for (int e = threadIdx.x; e < K_S * F_S; e += blockDim.x)
-    L.W[(e % F_S) * kLdW + e / F_S] = P.WbT[e];
-  for (int e = threadIdx.x; e < P.Z * F_S; e += blockDim.x) {
-    L.Td[e / F_S][e % F_S] = P.Td[e];
-    L.Ts[e / F_S][e % F_S] = P.Ts[e];
+// Staging of the LDS weights in two halves: fetch() issues the thread's global loads into
+// registers, store() writes them to LDS, so that independent work (the first receiver's
+// neighbor loads) can overlap the loads.
+template <bool kReadout>
+struct Stager {
+  static constexpr int kW = K_S * F_S, kT = Z_MAX * F_S, kR = kReadout ? F_S * F_S : 0;
+  static constexpr int kN = kW + 2 * kT + kR;
+  static constexpr int kPer = (kN + kWaves * 64 - 1) / (kWaves * 64);
+  float v[kPer];
+  __device__ __forceinline__ void fetch(const SmallParams& P) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + kWaves * 64 * u;
+      float x = 0.f;
+      if (e < kW) x = P.WbT[e];
+      else if (e < kW + kT) x = e - kW < P.Z * F_S ? P.Td[e - kW] : 0.f;
+      else if (e < kW + 2 * kT) x = e - kW - kT < P.Z * F_S ? P.Ts[e - kW - kT] : 0.f;
+      else if (e < kN) x = P.W1[e - kW - 2 * kT];
+      v[u] = x;
+    }
   }
-  for (int e = threadIdx.x; e < F_S * F_S; e += blockDim.x) L.W1[e / F_S][e % F_S] = P.W1[e];
-}
+  __device__ __forceinline__ void store(SmallLds<kReadout>& L) const {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + kWaves * 64 * u;
+      if (e < kW) L.W[(e % F_S) * kLdW + e / F_S] = v[u];
+      else if (e < kW + kT) L.Td[(e - kW) / F_S][(e - kW) % F_S] = v[u];
+      else if (e < kW + 2 * kT) L.Ts[(e - kW - kT) / F_S][(e - kW - kT) % F_S] = v[u];
+      else if (kReadout && e < kN) L.W1[(e - kW - 2 * kT) / F_S][(e - kW - 2 * kT) % F_S] = v[u];
+    }
+  }
+};
 
 // 16 x 16 tile over K = 16 radial functions.  bk(e) / wk(e) give the lane's radial and
 // weight operands for k = 4 e + g (FP32, e = step) or k = 4 g + e (BF16, e = element);
@@ -102,38 +127,42 @@ __device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
   return acc;
 }
 
-// Five waves per SIMD: the registers are capped at 96, and five work-groups fit the LDS.
+// Four waves per SIMD: the registers are capped at 128.
 template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
             const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
             double box, float* __restrict__ atom_e, float* __restrict__ g_out,
             int32_t* __restrict__ ell_j, float4* __restrict__ ell_g, int32_t* __restrict__ ell_n,
             uint32_t* __restrict__ flags) {
-  __shared__ SmallLds L;
+  __shared__ SmallLds<true> L;
   __shared__ int sZ[kWaves][kCap];
   __shared__ float4 sG[kWaves][kCap];
   __shared__ float sVec[kWaves][F_S];
-  load_params(L, P);
-  __syncthreads();
+  Stager<true> stage;
+  stage.fetch(P);
+  bool staged = false;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float pi_rc = 3.14159265358979f / P.rc;
   const int n_wg = (n + kWaves - 1) / kWaves;
-  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {   // uniform over the work-group
     const int i = wg * kWaves + w;
-    if (i >= n) continue;
+    const bool act = i < n;
+    int cnt = 0;
+    if (act) {
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     // 1. pairs inside the cutoff, in row order, compacted into LDS and the table
-    int cnt = 0;
     const int row0 = offs[i], row1 = offs[i + 1];
     for (int base = row0; base < row1; base += 64) {
       const int p = base + lane;
       const int j = p < row1 ? nbr[p] : -1;
       float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
       bool ok = false;
+      int zj = 0;
       if (j >= 0) {
+        zj = species[j];
         dx = static_cast<float>(minimage(pos[j] - xi, box, inv_box));
         dy = static_cast<float>(minimage(pos[n + j] - yi, box, inv_box));
         dz = static_cast<float>(minimage(pos[2 * n + j] - zi, box, inv_box));
@@ -144,7 +173,7 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
       const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
       if (ok && k < kCap) {
         const float4 gv = make_float4(dx, dy, dz, r);
-        sZ[w][k] = species[j];
+        sZ[w][k] = zj;
         sG[w][k] = gv;
         ell_j[(size_t)i * kCap + k] = j;
         ell_g[(size_t)i * kCap + k] = gv;
@@ -156,6 +185,13 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
       cnt = kCap;
     }
     if (lane == 0) ell_n[i] = cnt;
+    }
+    if (!staged) {   // the weights, once per work-group, after the first receivers' loads
+      stage.store(L);
+      __syncthreads();
+      staged = true;
+    }
+    if (!act) continue;
     wave_sync();
     // 2. messages on MFMA tiles, summed over pairs in registers
     const int zi_s = species[i];
@@ -231,40 +267,55 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
             const float* __restrict__ g, const int32_t* __restrict__ ell_j,
             const float4* __restrict__ ell_g, const int32_t* __restrict__ ell_n,
             float* __restrict__ forces) {
-  __shared__ SmallLds L;
-  load_params(L, P);
-  __syncthreads();
+  __shared__ SmallLds<false> L;
+  Stager<false> stage;
+  stage.fetch(P);
+  bool staged = false;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, cl = lane & 15;
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float pi_rc = 3.14159265358979f / P.rc;
   const int n_wg = (n + kWaves - 1) / kWaves;
-  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {   // uniform over the work-group
     const int i = wg * kWaves + w;
-    if (i >= n) continue;
-    const int cnt = ell_n[i];
-    const int zi_s = species[i];
-    // the lane's 16 channels: c = 16 b + 4 gq + r
-    float gi[16];
+    const bool act = i < n;
+    // the receiver's whole compact row, one entry per lane (the row holds at most 64)
+    int cnt = 0, zi_s = 0, jl = 0, zl = 0;
+    float4 gl = make_float4(0.f, 0.f, 0.f, 0.f);
+    float gi[16];   // the lane's 16 channels: c = 16 b + 4 gq + r
+    if (act) {
+      cnt = ell_n[i];
+      zi_s = species[i];
+      jl = lane < cnt ? ell_j[(size_t)i * kCap + lane] : i;
+      gl = lane < cnt ? ell_g[(size_t)i * kCap + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+      zl = species[jl];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const float4 t = *reinterpret_cast<const float4*>(g + (size_t)i * F_S + 16 * b + 4 * gq);
-      gi[4 * b] = t.x;
-      gi[4 * b + 1] = t.y;
-      gi[4 * b + 2] = t.z;
-      gi[4 * b + 3] = t.w;
+      for (int b = 0; b < 4; ++b) {
+        const float4 t = *reinterpret_cast<const float4*>(g + (size_t)i * F_S + 16 * b + 4 * gq);
+        gi[4 * b] = t.x;
+        gi[4 * b + 1] = t.y;
+        gi[4 * b + 2] = t.z;
+        gi[4 * b + 3] = t.w;
+      }
     }
+    if (!staged) {   // the weights, once per work-group, after the first receivers' loads
+      stage.store(L);
+      __syncthreads();
+      staged = true;
+    }
+    if (!act) continue;
     float fx = 0.f, fy = 0.f, fz = 0.f;
     for (int t0 = 0; t0 < cnt; t0 += kTile) {
-      const int pc = t0 + cl;            // the lane's pair
+      const int pc = t0 + cl;            // the lane's pair, taken from lane pc
       const bool vp = pc < cnt;
-      const int j = vp ? ell_j[(size_t)i * kCap + pc] : i;
-      const float4 gv = vp ? ell_g[(size_t)i * kCap + pc] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int j = __shfl(jl, pc, 64);
+      const int zj = __shfl(zl, pc, 64);
+      const float4 gv = make_float4(__shfl(gl.x, pc, 64), __shfl(gl.y, pc, 64),
+                                    __shfl(gl.z, pc, 64), __shfl(gl.w, pc, 64));
       const float rp = gv.w;
       float sn, cs;
       __sincosf(pi_rc * rp, &sn, &cs);
       const float fc = vp ? 0.5f * (cs + 1.0f) : 0.f;
       const float dfc = vp ? -0.5f * pi_rc * sn : 0.f;
-      const int zj = species[j];
       auto bk = [&](int e) {
         const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
         const float x = rp - P.sigma * kk;
