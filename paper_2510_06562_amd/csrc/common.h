@@ -115,22 +115,192 @@ struct Model {
   const float* p(size_t off) const { return params.as<float>() + off; }
 };
 
+// ------------------------------------------------------------------ integrator program
+// Kicks and drifts between two force evaluations, applied per atom in the algorithm's
+// order with exactly the arithmetic of separate steps:
+//   kick:  v <- v + c / m * F      (c = tau * KAPPA; F = F_small, F_large or F_large - F_small)
+//   drift: x <- x + c * v          (c = tau)
+// A force evaluation that is followed by such a program applies it to atom i as soon as
+// F_i is final (the epilogue of its last kernel); the positions it moves are read by the
+// next evaluation only.
+enum IntegOp : int { kKickSlow = 0, kKickFast = 1, kKickLarge = 2, kDrift = 3 };
+constexpr int kMaxOps = 8;
+constexpr uint32_t kFlagStale = 0x100u;   // internal: shared list no longer complete
+
+struct Prog {
+  int nops;
+  int op[kMaxOps];
+  double c[kMaxOps];
+};
+
+struct Epilogue {
+  Prog prog;
+  double* x;                 // [3][n] float64
+  double* v;                 // [3][n] float64
+  const float* FL;           // [3][n] reference-model forces
+  const float* Fs;           // [3][n] fast-model forces
+  const int32_t* species;
+  double inv_mass[8];        // per species (kernel argument: no memory round trip)
+  const double* x_ref;       // positions of the shared list's build (displacement check) or null
+  double max_disp2;
+  uint32_t* flags;
+};
+
+// 1 / m of species z, from the kernel argument by selection (no dynamic indexing).
+__device__ inline double inv_mass_of(const Epilogue& E, int z) {
+  double im = E.inv_mass[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) im = z == k ? E.inv_mass[k] : im;
+  return im;
+}
+
+__device__ inline void apply_atom(const Epilogue& E, int i, int n) {
+  const double im = inv_mass_of(E, E.species[i]);
+  double vv[3], xx[3];
+  bool moved = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) vv[d] = E.v[(size_t)d * n + i];
+  for (int k = 0; k < E.prog.nops; ++k) {
+    const int op = E.prog.op[k];
+    const double c = E.prog.c[k];
+    if (op == kDrift) {
+      if (!moved) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xx[d] = E.x[(size_t)d * n + i];
+        moved = true;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xx[d] = xx[d] + c * vv[d];
+    } else {
+      const double ci = c * im;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double f;
+        if (op == kKickSlow) f = (double)E.FL[(size_t)d * n + i] - (double)E.Fs[(size_t)d * n + i];
+        else if (op == kKickFast) f = (double)E.Fs[(size_t)d * n + i];
+        else f = (double)E.FL[(size_t)d * n + i];
+        vv[d] = vv[d] + ci * f;
+      }
+    }
+  }
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    E.v[(size_t)d * n + i] = vv[d];
+    bad |= !isfinite(vv[d]);
+  }
+  uint32_t f = 0;
+  if (moved) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      E.x[(size_t)d * n + i] = xx[d];
+      bad |= !isfinite(xx[d]);
+      if (E.x_ref) {
+        const double u = xx[d] - E.x_ref[(size_t)d * n + i];
+        d2 += u * u;
+      }
+    }
+    if (E.x_ref && !(d2 <= E.max_disp2)) f |= kFlagStale;
+  }
+  if (bad) f |= DMTS_FLAG_NONFINITE;
+  if (f) atomicOr(E.flags, f);
+}
+
+// The same program for one coordinate d of atom i, spread over lanes 0..2 of a wave: the
+// caller loads the coordinate's inputs early (prefetch) and passes the force it has just
+// computed as `fresh`; fresh_small tells whether that is the program's F_small (else
+// F_large), whichever model produced it.
+struct CoordIn {
+  double x, v, xr, fother;
+  int z;
+};
+
+__device__ inline CoordIn prefetch_coord(const Epilogue& E, int i, int n, int d, bool fresh_small) {
+  CoordIn c;
+  const size_t o = (size_t)d * n + i;
+  c.x = E.x[o];
+  c.v = E.v[o];
+  c.xr = E.x_ref ? E.x_ref[o] : 0.0;
+  c.fother = fresh_small ? (double)E.FL[o] : (double)E.Fs[o];
+  c.z = E.species[i];
+  return c;
+}
+
+// Runs the program on lanes 0..2 (coordinate d = lane) of the calling wave, which must all
+// be active; writes x, v and raises the flags exactly as apply_atom does.
+__device__ inline void apply_coords(const Epilogue& E, int i, int n, int lane, const CoordIn& c,
+                                    float fresh, bool fresh_small) {
+  double vv = c.v, xx = c.x;
+  bool moved = false;
+  const double im = inv_mass_of(E, c.z);
+  const double fl = fresh_small ? c.fother : (double)fresh;
+  const double fs = fresh_small ? (double)fresh : c.fother;
+  for (int k = 0; k < E.prog.nops; ++k) {
+    const int op = E.prog.op[k];
+    const double cc = E.prog.c[k];
+    if (op == kDrift) {
+      moved = true;
+      xx = xx + cc * vv;
+    } else {
+      const double ci = cc * im;
+      const double f = op == kKickSlow ? fl - fs : op == kKickFast ? fs : fl;
+      vv = vv + ci * f;
+    }
+  }
+  const int d = lane;
+  bool bad = false;
+  double u2 = 0.0;
+  if (d < 3) {
+    E.v[(size_t)d * n + i] = vv;
+    bad = !isfinite(vv);
+    if (moved) {
+      E.x[(size_t)d * n + i] = xx;
+      bad |= !isfinite(xx);
+      const double u = xx - c.xr;
+      u2 = u * u;
+    }
+  }
+  const double u2y = __shfl(u2, 1, 64), u2z = __shfl(u2, 2, 64);
+  const bool any_bad = __ballot(bad) != 0;
+  if (lane == 0) {
+    uint32_t f = 0;
+    if (moved && E.x_ref) {
+      double d2 = 0.0;
+      d2 += u2;
+      d2 += u2y;
+      d2 += u2z;
+      if (!(d2 <= E.max_disp2)) f |= kFlagStale;
+    }
+    if (any_bad) f |= DMTS_FLAG_NONFINITE;
+    if (f) atomicOr(E.flags, f);
+  }
+}
+
+// The program applied to atoms 0..n-1 by a launch of its own.
+dmts_status apply_program(const Epilogue& E, int32_t n, hipStream_t s);
+
 // Work-groups of `kernel` (launched with `threads` threads each) that the current device
 // holds at once, from the occupancy calculator; cached per device and kernel.
 int resident_groups(const void* kernel, int threads);
 
+// `ep` (optional, needs `forces`): integrator program applied to every atom once its force
+// is final; `forces` must then be the program's F_small (fast model) or F_large.
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos,
                                 const int32_t* species, int32_t n, double box,
                                 const int32_t* sys_offsets, int32_t n_sys, double* energy,
-                                float* forces, float* atom_energy, hipStream_t s);
+                                float* forces, float* atom_energy, hipStream_t s,
+                                const Epilogue* ep = nullptr);
 dmts_status large_energy_forces(Model* m, NList* nl, const double* pos,
                                 const int32_t* species, int32_t n, double box,
                                 const int32_t* sys_offsets, int32_t n_sys, double* energy,
-                                float* forces, float* atom_energy, hipStream_t s);
+                                float* forces, float* atom_energy, hipStream_t s,
+                                const Epilogue* ep = nullptr);
 
 dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
                           int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
-                          double* energy, float* forces, float* atom_energy, hipStream_t s);
+                          double* energy, float* forces, float* atom_energy, hipStream_t s,
+                          const Epilogue* ep = nullptr);
 
 // Deterministic FP64 sum of per-atom FP32 energies per system: energy[s] = sum over the
 // atoms of system s (one system when sys_offsets is NULL).

@@ -2,9 +2,11 @@
 // single-time-step baseline, in float64 on the device.
 //
 // Kicks and drifts are per-atom streaming work (x, v float64 [3][N], forces float32).
-// Consecutive kicks/drifts between two force evaluations are fused into one launch that
-// applies them in the algorithm's order with exactly the arithmetic of separate steps,
-// so fusion never changes a bit of the trajectory:
+// Consecutive kicks/drifts between two force evaluations form one program, applied to
+// each atom in the algorithm's order with exactly the arithmetic of separate steps, so
+// fusion never changes a bit of the trajectory.  After a two-interaction evaluation it runs
+// in the epilogue of the last kernel (the force gather), as soon as the atom's force is
+// final; otherwise it gets one launch of its own:
 //   kick:  v <- v + (tau * KAPPA / m) * F      (F = F_small, F_large or F_large - F_small)
 //   drift: x <- x + tau * v
 // KAPPA converts eV/(A amu) into A/fs^2.
@@ -18,6 +20,7 @@
 // launch checks that bound on the device.  If it is ever exceeded, the call is rolled back
 // to its starting state and repeated with a fresh list for every fast evaluation.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -29,75 +32,13 @@ namespace {
 // constant.
 constexpr double kKappa = 1.602176634e-19 / (1.0e-10 * 1.66053906660e-27) * 1.0e-20;
 
-enum Op : int { kKickSlow = 0, kKickFast = 1, kKickLarge = 2, kDrift = 3 };
-constexpr int kMaxOps = 8;
-
-struct Prog {
-  int nops;
-  int op[kMaxOps];
-  double c[kMaxOps];   // kicks: tau * KAPPA; drifts: tau
-};
-
-constexpr uint32_t kFlagStale = 0x100u;   // internal: shared list no longer complete
 constexpr double kMinSkin = 1.0;           // A between the fast cutoff and the shared list
 
-__global__ void __launch_bounds__(256)
-k_apply(Prog prog, int n, double* __restrict__ x, double* __restrict__ v,
-        const float* __restrict__ FL, const float* __restrict__ Fs,
-        const int32_t* __restrict__ species, const double* __restrict__ inv_mass,
-        const double* __restrict__ x_ref, double max_disp2, uint32_t* __restrict__ flags) {
+// Integrator ops as a launch of their own (the start of a call, or after a model whose
+// kernels do not take the program as an epilogue).
+__global__ void __launch_bounds__(256) k_apply(Epilogue E, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double im = inv_mass[species[i]];
-  double vv[3], xx[3];
-  bool moved = false;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) vv[d] = v[(size_t)d * n + i];
-  for (int k = 0; k < prog.nops; ++k) {
-    const int op = prog.op[k];
-    const double c = prog.c[k];
-    if (op == kDrift) {
-      if (!moved) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xx[d] = x[(size_t)d * n + i];
-        moved = true;
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) xx[d] = xx[d] + c * vv[d];
-    } else {
-      const double ci = c * im;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double f;
-        if (op == kKickSlow) f = (double)FL[(size_t)d * n + i] - (double)Fs[(size_t)d * n + i];
-        else if (op == kKickFast) f = (double)Fs[(size_t)d * n + i];
-        else f = (double)FL[(size_t)d * n + i];
-        vv[d] = vv[d] + ci * f;
-      }
-    }
-  }
-  bool bad = false;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    v[(size_t)d * n + i] = vv[d];
-    bad |= !isfinite(vv[d]);
-  }
-  uint32_t f = 0;
-  if (moved) {
-    double d2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      x[(size_t)d * n + i] = xx[d];
-      bad |= !isfinite(xx[d]);
-      if (x_ref) {
-        const double u = xx[d] - x_ref[(size_t)d * n + i];
-        d2 += u * u;
-      }
-    }
-    if (x_ref && !(d2 <= max_disp2)) f |= kFlagStale;
-  }
-  if (bad) f |= DMTS_FLAG_NONFINITE;
-  if (f) atomicOr(flags, f);
+  if (i < n) apply_atom(E, i, n);
 }
 
 __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -161,6 +102,7 @@ struct State {
   double* bak = nullptr;    // [6][n] x, v at the start of a call; then FL, Fs as [3][n] floats
   double* mass = nullptr;   // [Z]
   double* inv_mass = nullptr;
+  double host_inv_mass[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the same, for kernel arguments
   double* e_models = nullptr;   // {E_large, E_small}
   uint32_t* flags = nullptr;
   // models the carried forces belong to
@@ -171,117 +113,163 @@ struct State {
 
 namespace {
 
+// One call's schedule: integrator ops and force evaluations in the algorithm's order.  It
+// is built first, so that every evaluation is given the ops that follow it (up to the next
+// evaluation) as the epilogue of its last kernel; only ops before the first evaluation of a
+// call get a launch of their own.
+enum EvalKind : int { kEvalLarge = 0, kEvalSmall = 1, kEvalPlain = 2 };
+
+struct Item {
+  bool eval;
+  int op_or_kind;
+  double c;       // op: coefficient
+  bool want_e;    // eval: sum the energies (last evaluation of its model in the call)
+};
+
 struct Runner {
   State* st;
   double* x;
   double* v;
   hipStream_t s;
-  Prog pending{};
   // shared-list mode: the fast model runs on the reference model's list
   bool shared = false;
   double list_cut = 0.0;
   double max_disp2 = 0.0;
+  Model* small = nullptr;
+  Model* large = nullptr;
+  std::vector<Item> sched;
 
-  dmts_status flush() {
-    if (pending.nops == 0) return DMTS_OK;
-    ProfScope ps(DMTS_K_INTEGRATE, s);
-    k_apply<<<ceil_div(st->n, 256), 256, 0, s>>>(pending, st->n, x, v, st->FL, st->Fs,
-                                                 st->species, st->inv_mass,
-                                                 shared ? st->x_ref : nullptr, max_disp2,
-                                                 st->flags);
-    DMTS_CHECK_LAUNCH();
-    pending.nops = 0;
-    return DMTS_OK;
-  }
-  dmts_status push(int op, double c) {
-    if (pending.nops == kMaxOps) {
-      dmts_status r = flush();
-      if (r != DMTS_OK) return r;
-    }
-    pending.op[pending.nops] = op;
-    pending.c[pending.nops] = c;
-    ++pending.nops;
-    return DMTS_OK;
+  void op(int o, double c) { sched.push_back(Item{false, o, c, false}); }
+  void eval(int kind, bool want_e) { sched.push_back(Item{true, kind, 0.0, want_e}); }
+
+  Epilogue epilogue(const Prog& p) const {
+    Epilogue e{};
+    e.prog = p;
+    e.x = x;
+    e.v = v;
+    e.FL = st->FL;
+    e.Fs = st->Fs;
+    e.species = st->species;
+    for (int z = 0; z < 8; ++z) e.inv_mass[z] = st->host_inv_mass[z];
+    e.x_ref = shared ? st->x_ref : nullptr;
+    e.max_disp2 = max_disp2;
+    e.flags = st->flags;
+    return e;
   }
   // The model energies are only reported for the positions a call ends at, so an
-  // evaluation sums them (want_e) only when it is the last one of its model in the call.
-  dmts_status eval(Model* m, NList* nl, float* F, double* e, bool want_e) {
-    dmts_status r = flush();
+  // evaluation sums them only when it is the last one of its model in the call.
+  // The ops that follow an evaluation are handed to it as its epilogue (the model decides
+  // whether they run inside its last kernel or right after it).
+  dmts_status run_eval(const Item& it, const Prog& after) {
+    const Epilogue E = epilogue(after);
+    const Epilogue* ep = after.nops > 0 ? &E : nullptr;
+    dmts_status r;
+    if (it.op_or_kind == kEvalSmall) {
+      if (!shared) {
+        r = build_neighbors(st->nl_small, x, st->n, st->box, nullptr, 1,
+                            (double)small->desc.cutoff, s);
+        if (r != DMTS_OK) return r;
+      }
+      return energy_forces(small, shared ? st->nl_large : st->nl_small, x, st->species, st->n,
+                           st->box, nullptr, 1, it.want_e ? st->e_models + 1 : nullptr, st->Fs,
+                           nullptr, s, ep);
+    }
+    // reference model (Algorithm 1) or the plain single-time-step model: builds its list
+    // (at list_cut in shared mode, recording x_ref for the fast model's displacement check)
+    r = build_neighbors(st->nl_large, x, st->n, st->box, nullptr, 1,
+                        shared ? list_cut : (double)large->desc.cutoff, s);
     if (r != DMTS_OK) return r;
-    r = build_neighbors(nl, x, st->n, st->box, nullptr, 1, (double)m->desc.cutoff, s);
-    if (r != DMTS_OK) return r;
-    return energy_forces(m, nl, x, st->species, st->n, st->box, nullptr, 1,
-                         want_e ? e : nullptr, F, nullptr, s);
+    if (shared) {
+      const int64_t n3 = 3 * (int64_t)st->n;
+      k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(x, st->x_ref, n3);
+      DMTS_CHECK_LAUNCH();
+    }
+    return energy_forces(large, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
+                         it.want_e ? st->e_models : nullptr, st->FL, nullptr, s, ep);
   }
-  // reference model: builds the list (at list_cut in shared mode) and records x_ref
-  dmts_status eval_large(Model* m, bool want_e) {
-    if (!shared) return eval(m, st->nl_large, st->FL, st->e_models, want_e);
-    dmts_status r = flush();
-    if (r != DMTS_OK) return r;
-    r = build_neighbors(st->nl_large, x, st->n, st->box, nullptr, 1, list_cut, s);
-    if (r != DMTS_OK) return r;
-    const int64_t n3 = 3 * (int64_t)st->n;
-    k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(x, st->x_ref, n3);
-    DMTS_CHECK_LAUNCH();
-    return energy_forces(m, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
-                         want_e ? st->e_models : nullptr, st->FL, nullptr, s);
+  // ops [k, next evaluation) as one program
+  Prog collect(size_t& k) const {
+    Prog p{};
+    while (k < sched.size() && !sched[k].eval) {
+      if (p.nops == kMaxOps) break;
+      p.op[p.nops] = sched[k].op_or_kind;
+      p.c[p.nops] = sched[k].c;
+      ++p.nops;
+      ++k;
+    }
+    return p;
   }
-  dmts_status eval_small(Model* m, bool want_e) {
-    if (!shared) return eval(m, st->nl_small, st->Fs, st->e_models + 1, want_e);
-    dmts_status r = flush();
-    if (r != DMTS_OK) return r;
-    return energy_forces(m, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
-                         want_e ? st->e_models + 1 : nullptr, st->Fs, nullptr, s);
+  dmts_status apply(const Prog& p) { return apply_program(epilogue(p), st->n, s); }
+  dmts_status execute() {
+    size_t k = 0;
+    dmts_status r;
+    while (k < sched.size() && !sched[k].eval) {   // ops before the first evaluation
+      if ((r = apply(collect(k))) != DMTS_OK) return r;
+    }
+    while (k < sched.size()) {
+      const Item it = sched[k++];
+      Prog after = collect(k);
+      if ((r = run_eval(it, after)) != DMTS_OK) return r;
+      while (k < sched.size() && !sched[k].eval) {   // more ops than one program holds
+        if ((r = apply(collect(k))) != DMTS_OK) return r;
+      }
+    }
+    sched.clear();
+    return DMTS_OK;
   }
 };
 
 // Algorithm 1 (or velocity Verlet when small is NULL) for n_outer outer steps.
 dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_outer) {
-  dmts_status r;
   const double kappa = kKappa;
+  R.small = small;
+  R.large = large;
+  R.sched.clear();
+  const double dt = st->dt;
   if (!small) {
     // single-time-step baseline: velocity Verlet (BAOAB with the O-step off)
-    const double dt = st->dt;
+    if (st->first) R.eval(kEvalPlain, n_outer == 0);
+    for (int o = 0; o < n_outer; ++o) {
+      R.op(kKickLarge, 0.5 * dt * kappa);
+      R.op(kDrift, 0.5 * dt);
+      R.op(kDrift, 0.5 * dt);
+      R.eval(kEvalPlain, o == n_outer - 1);
+      R.op(kKickLarge, 0.5 * dt * kappa);
+    }
+  } else {
+    const int n = st->n_inner;
+    const double h_in = dt / n;
     if (st->first) {
-      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models, n_outer == 0)) != DMTS_OK)
-        return r;
-      st->first = false;
+      R.eval(kEvalLarge, n_outer == 0);
+      R.eval(kEvalSmall, n_outer == 0);
     }
     for (int o = 0; o < n_outer; ++o) {
-      R.push(kKickLarge, 0.5 * dt * kappa);
-      R.push(kDrift, 0.5 * dt);
-      R.push(kDrift, 0.5 * dt);
-      if ((r = R.eval(large, st->nl_large, st->FL, st->e_models, o == n_outer - 1)) != DMTS_OK)
-        return r;
-      R.push(kKickLarge, 0.5 * dt * kappa);
+      const bool last = o == n_outer - 1;
+      R.op(kKickSlow, 0.5 * dt * kappa);
+      for (int k = 0; k < n; ++k) {
+        R.op(kKickFast, 0.5 * h_in * kappa);
+        R.op(kDrift, 0.5 * h_in);
+        R.op(kDrift, 0.5 * h_in);
+        R.eval(kEvalSmall, last && k == n - 1);
+        R.op(kKickFast, 0.5 * h_in * kappa);
+      }
+      R.eval(kEvalLarge, last);
+      R.op(kKickSlow, 0.5 * dt * kappa);
     }
-    return R.flush();
   }
-  const double dt = st->dt;
-  const int n = st->n_inner;
-  const double h_in = dt / n;
-  if (st->first) {
-    if ((r = R.eval_large(large, n_outer == 0)) != DMTS_OK) return r;
-    if ((r = R.eval_small(small, n_outer == 0)) != DMTS_OK) return r;
-    st->first = false;
-  }
-  for (int o = 0; o < n_outer; ++o) {
-    const bool last = o == n_outer - 1;
-    R.push(kKickSlow, 0.5 * dt * kappa);
-    for (int k = 0; k < n; ++k) {
-      R.push(kKickFast, 0.5 * h_in * kappa);
-      R.push(kDrift, 0.5 * h_in);
-      R.push(kDrift, 0.5 * h_in);
-      if ((r = R.eval_small(small, last && k == n - 1)) != DMTS_OK) return r;
-      R.push(kKickFast, 0.5 * h_in * kappa);
-    }
-    if ((r = R.eval_large(large, last)) != DMTS_OK) return r;
-    R.push(kKickSlow, 0.5 * dt * kappa);
-  }
-  return R.flush();
+  st->first = false;
+  return R.execute();
 }
 
 }  // namespace
+
+dmts_status apply_program(const Epilogue& E, int32_t n, hipStream_t s) {
+  if (E.prog.nops == 0 || n <= 0) return DMTS_OK;
+  ProfScope ps(DMTS_K_INTEGRATE, s);
+  k_apply<<<ceil_div(n, 256), 256, 0, s>>>(E, n);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
 
 }  // namespace dmts
 
@@ -322,6 +310,7 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
   for (int z = 0; z < n_species; ++z) {
     hm[z] = host_mass_by_species[z];
     him[z] = 1.0 / host_mass_by_species[z];
+    st->host_inv_mass[z] = him[z];
   }
   hipError_t e = hipSuccess;
   if (r == DMTS_OK) {

@@ -561,10 +561,12 @@ k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nb
 __global__ void __launch_bounds__(256)
 k_force_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                const int32_t* __restrict__ rev, int n, const float* __restrict__ v, int64_t cap,
-               float* __restrict__ forces) {
+               float* __restrict__ forces, Epilogue E, bool has_ep, bool fresh_small) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
+  CoordIn ein{};   // this atom's integrator inputs, coordinate d = lane (lanes 0..2)
+  if (has_ep && lane < 3) ein = prefetch_coord(E, i, n, lane, fresh_small);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int p = row0 + lane; p < row1; p += 64) {
@@ -584,11 +586,16 @@ k_force_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr
     forces[n + i] = fy;
     forces[2 * n + i] = fz;
   }
+  if (has_ep) {   // F_i is final: the integrator step of atom i, with lane 0's sums
+    const float f0x = __shfl(fx, 0, 64), f0y = __shfl(fy, 0, 64), f0z = __shfl(fz, 0, 64);
+    apply_coords(E, i, n, lane, ein, lane == 0 ? f0x : lane == 1 ? f0y : f0z, fresh_small);
+  }
 }
 
 dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
                                 int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
-                                double* energy, float* forces, float* atom_energy, hipStream_t s) {
+                                double* energy, float* forces, float* atom_energy, hipStream_t s,
+                                const Epilogue* ep) {
   DMTS_REQUIRE(m->K == K_L && m->F == F_L, DMTS_E_ARG, "large model: unsupported shape");
   DMTS_REQUIRE(nl->row_align % kTile == 0, DMTS_E_ARG,
                "large model: the neighbor list needs row_align 16 (or a multiple), got %d",
@@ -667,7 +674,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                                                           nullptr, v, cap); }
         DMTS_CHECK_LAUNCH();
         { ProfScope ps(DMTS_K_GATHER, s);
-        k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces); }
+        k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces,
+                                              ep ? *ep : Epilogue{}, ep != nullptr,
+                                              ep && forces == ep->Fs); }
         DMTS_CHECK_LAUNCH();
       }
     }

@@ -371,7 +371,8 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
 
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
                                 int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
-                                double* energy, float* forces, float* atom_energy, hipStream_t s) {
+                                double* energy, float* forces, float* atom_energy, hipStream_t s,
+                                const Epilogue* ep) {
   DMTS_REQUIRE(m->K == K_S && m->F == F_S, DMTS_E_ARG, "small model: unsupported shape");
   // workspace: compact pair table [n][kCap] (geometry, senders, counts), adjoint g [n][F],
   // atom energies [n]
@@ -409,6 +410,12 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
     if (m->bf16) run(std::true_type{});
     else run(std::false_type{});
     DMTS_CHECK_LAUNCH();
+    // the integrator program runs as a launch of its own here: in the reverse kernel's
+    // epilogue it would lengthen every wave by more than the launch costs
+    if (ep) {
+      const dmts_status st = apply_program(*ep, n, s);
+      if (st != DMTS_OK) return st;
+    }
   }
   if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, s);
   return DMTS_OK;
