@@ -75,10 +75,21 @@ ProfScope::ProfScope(int kernel_class, hipStream_t stream) : kid(kernel_class), 
 
 ProfScope::~ProfScope() {
   if (!a) return;
-  hipEvent_t b = get_event();
-  if (!b) return;
-  (void)hipEventRecord(b, s);
+  if (!b) {
+    b = get_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+  }
   g_prof[kid].push_back({a, b});
+}
+
+bool ProfScope::packet(hipEvent_t& start, hipEvent_t& stop) {
+  if (!a) return false;
+  b = get_event();
+  if (!b) return false;
+  start = a;
+  stop = b;
+  return true;
 }
 
 namespace {

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -316,9 +317,25 @@ struct ProfScope {
   int kid;
   hipStream_t s;
   hipEvent_t a = nullptr;
+  hipEvent_t b = nullptr;   // set when the launch itself records the stop event
   ProfScope(int kernel_class, hipStream_t stream);
   ~ProfScope();
+  // When this class is timed: start and stop events for a launch that records them in its
+  // own dispatch (the kernel's start and end), instead of around it.
+  bool packet(hipEvent_t& start, hipEvent_t& stop);
 };
+
+// Launch of one kernel of a timed class: with hipExtLaunchKernelGGL when the class is being
+// timed (events taken at the kernel's own start and end), a plain launch otherwise.
+template <typename... KArgs, typename... Args>
+void launch_timed(ProfScope& ps, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                  hipStream_t s, Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ps.packet(e0, e1))
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, static_cast<KArgs>(args)...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, static_cast<KArgs>(args)...);
+}
 
 // ------------------------------------------------------------------ device helpers
 // logistic(t) = 1 / (1 + e^-t) with the hardware reciprocal (v_rcp_f32, 1 ulp); for

@@ -644,39 +644,54 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
     constexpr int NP = decltype(np_tag)::value;
     dmts_status st;
     if (n > 0) {
-      { ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
-      k_pair_fwd_mfma<1, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_fwd_mfma<1, NP>)), kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species, n,
-                                                        nullptr, W + o_M1, W + o_q1); }
+      auto grid_of = [&](auto kernel) { return dim3(pgrid(reinterpret_cast<const void*>(kernel))); };
+      const dim3 wg(kWaves * 64);
+      {
+        ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
+        launch_timed(ps, &k_pair_fwd_mfma<1, NP>, grid_of(&k_pair_fwd_mfma<1, NP>), wg, s, P1,
+                     nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_q1);
+      }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
-      { ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
-      k_pair_fwd_mfma<2, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_fwd_mfma<2, NP>)), kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species, n,
-                                                        W + o_P2, W + o_M2, W + o_q2); }
+      {
+        ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
+        launch_timed(ps, &k_pair_fwd_mfma<2, NP>, grid_of(&k_pair_fwd_mfma<2, NP>), wg, s, P2,
+                     nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_q2);
+      }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
                             forces != nullptr, s)) != DMTS_OK) return st;
       if (forces) {
         float* dA = m->pair_ws.as<float>();
         float* v = dA + (size_t)cap * F;
-        { ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
-        k_pair_bwd_mfma<2, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_bwd_mfma<2, NP>)), kWaves * 64, 0, s>>>(P2, nl->offs, nl->nbr, nl->geo, species,
-                                                          n, W + o_P2, W + o_M2, W + o_dq2, dA,
-                                                          W + o_RS, v, cap); }
+        {
+          ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
+          launch_timed(ps, &k_pair_bwd_mfma<2, NP>, grid_of(&k_pair_bwd_mfma<2, NP>), wg, s, P2,
+                       nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_dq2, dA,
+                       W + o_RS, v, cap);
+        }
         DMTS_CHECK_LAUNCH();
-        { ProfScope ps(DMTS_K_GATHER, s);
-        k_sender_gather<<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, dA, W + o_RS); }
+        {
+          ProfScope ps(DMTS_K_GATHER, s);
+          k_sender_gather<<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, dA,
+                                                         W + o_RS);
+        }
         DMTS_CHECK_LAUNCH();
         if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
           return st;
-        { ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
-        k_pair_bwd_mfma<1, NP><<<pgrid(reinterpret_cast<const void*>(&k_pair_bwd_mfma<1, NP>)), kWaves * 64, 0, s>>>(P1, nl->offs, nl->nbr, nl->geo, species,
-                                                          n, nullptr, W + o_M1, W + o_dq1, nullptr,
-                                                          nullptr, v, cap); }
+        {
+          ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
+          launch_timed(ps, &k_pair_bwd_mfma<1, NP>, grid_of(&k_pair_bwd_mfma<1, NP>), wg, s, P1,
+                       nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_dq1,
+                       nullptr, nullptr, v, cap);
+        }
         DMTS_CHECK_LAUNCH();
-        { ProfScope ps(DMTS_K_GATHER, s);
-        k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces,
-                                              ep ? *ep : Epilogue{}, ep != nullptr,
-                                              ep && forces == ep->Fs); }
+        {
+          ProfScope ps(DMTS_K_GATHER, s);
+          k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces,
+                                                ep ? *ep : Epilogue{}, ep != nullptr,
+                                                ep && forces == ep->Fs);
+        }
         DMTS_CHECK_LAUNCH();
       }
     }

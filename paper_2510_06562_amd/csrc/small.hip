@@ -398,14 +398,15 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
         ProfScope ps(DMTS_K_SMALL_FORWARD, s);
         const int blocks = m->launch_grid(
             natural, resident_groups(reinterpret_cast<const void*>(&k_small_fwd<BF>), kWaves * 64));
-        k_small_fwd<BF><<<blocks, kWaves * 64, 0, s>>>(P, nl->offs, nl->nbr, pos, species, n, box,
-                                                       e_atom, g, ell_j, ell_g, ell_n, nl->flags);
+        launch_timed(ps, &k_small_fwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, nl->offs,
+                     nl->nbr, pos, species, n, box, e_atom, g, ell_j, ell_g, ell_n, nl->flags);
       }
       if (hipPeekAtLastError() != hipSuccess || !forces) return;
       ProfScope ps(DMTS_K_SMALL_BACKWARD, s);
       const int blocks = m->launch_grid(
           natural, resident_groups(reinterpret_cast<const void*>(&k_small_bwd<BF>), kWaves * 64));
-      k_small_bwd<BF><<<blocks, kWaves * 64, 0, s>>>(P, species, n, g, ell_j, ell_g, ell_n, forces);
+      launch_timed(ps, &k_small_bwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, species, n, g,
+                   ell_j, ell_g, ell_n, forces);
     };
     if (m->bf16) run(std::true_type{});
     else run(std::false_type{});
