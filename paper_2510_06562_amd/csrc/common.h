@@ -145,6 +145,7 @@ struct Epilogue {
   const double* x_ref;       // positions of the shared list's build (displacement check) or null
   double max_disp2;
   uint32_t* flags;
+  hipEvent_t wait = nullptr;   // host side: the launch that runs the program waits for it
 };
 
 // 1 / m of species z, from the kernel argument by selection (no dynamic indexing).

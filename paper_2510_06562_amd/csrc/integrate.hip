@@ -96,6 +96,10 @@ struct State {
   bool first = true;
   NList* nl_small = nullptr;
   NList* nl_large = nullptr;
+  NList* nl_large2 = nullptr;   // the shared list is double-buffered: nl_large / nl_large2
+  int shared_cur = 0;           // which of the two is the fast model's current list
+  hipStream_t side = nullptr;   // fast evaluations overlapped with reference evaluations
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* FL = nullptr;      // [3][n]
   float* Fs = nullptr;      // [3][n]
   double* x_ref = nullptr;  // [3][n] positions of the last shared-list build
@@ -160,32 +164,39 @@ struct Runner {
   // evaluation sums them only when it is the last one of its model in the call.
   // The ops that follow an evaluation are handed to it as its epilogue (the model decides
   // whether they run inside its last kernel or right after it).
-  dmts_status run_eval(const Item& it, const Prog& after) {
-    const Epilogue E = epilogue(after);
+  NList* shared_list(int which) const { return which ? st->nl_large2 : st->nl_large; }
+  dmts_status run_eval(const Item& it, const Prog& after, hipStream_t stream = nullptr,
+                       hipEvent_t wait = nullptr) {
+    hipStream_t q = stream ? stream : s;
+    Epilogue E = epilogue(after);
+    E.wait = wait;
     const Epilogue* ep = after.nops > 0 ? &E : nullptr;
     dmts_status r;
     if (it.op_or_kind == kEvalSmall) {
       if (!shared) {
         r = build_neighbors(st->nl_small, x, st->n, st->box, nullptr, 1,
-                            (double)small->desc.cutoff, s);
+                            (double)small->desc.cutoff, q);
         if (r != DMTS_OK) return r;
       }
-      return energy_forces(small, shared ? st->nl_large : st->nl_small, x, st->species, st->n,
-                           st->box, nullptr, 1, it.want_e ? st->e_models + 1 : nullptr, st->Fs,
-                           nullptr, s, ep);
+      return energy_forces(small, shared ? shared_list(st->shared_cur) : st->nl_small, x,
+                           st->species, st->n, st->box, nullptr, 1,
+                           it.want_e ? st->e_models + 1 : nullptr, st->Fs, nullptr, q, ep);
     }
     // reference model (Algorithm 1) or the plain single-time-step model: builds its list
-    // (at list_cut in shared mode, recording x_ref for the fast model's displacement check)
-    r = build_neighbors(st->nl_large, x, st->n, st->box, nullptr, 1,
-                        shared ? list_cut : (double)large->desc.cutoff, s);
+    // (in shared mode at list_cut into the other buffer of the shared list, recording x_ref
+    // for the fast model's displacement check, after which it becomes the current one)
+    NList* nl = shared ? shared_list(st->shared_cur ^ 1) : st->nl_large;
+    r = build_neighbors(nl, x, st->n, st->box, nullptr, 1,
+                        shared ? list_cut : (double)large->desc.cutoff, q);
     if (r != DMTS_OK) return r;
     if (shared) {
       const int64_t n3 = 3 * (int64_t)st->n;
-      k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(x, st->x_ref, n3);
+      k_copy_f64<<<ceil_div(n3, 256), 256, 0, q>>>(x, st->x_ref, n3);
       DMTS_CHECK_LAUNCH();
+      st->shared_cur ^= 1;
     }
-    return energy_forces(large, st->nl_large, x, st->species, st->n, st->box, nullptr, 1,
-                         it.want_e ? st->e_models : nullptr, st->FL, nullptr, s, ep);
+    return energy_forces(large, nl, x, st->species, st->n, st->box, nullptr, 1,
+                         it.want_e ? st->e_models : nullptr, st->FL, nullptr, q, ep);
   }
   // ops [k, next evaluation) as one program
   Prog collect(size_t& k) const {
@@ -208,14 +219,44 @@ struct Runner {
     }
     while (k < sched.size()) {
       const Item it = sched[k++];
+      size_t k_ops = k;
       Prog after = collect(k);
-      if ((r = run_eval(it, after)) != DMTS_OK) return r;
+      // A fast evaluation followed, with kicks only in between, by a reference evaluation
+      // at the same positions: the fast evaluation and its kicks run on the side stream
+      // while the reference model builds its list and runs its kernels; the reference
+      // model's force gather (whose epilogue reads F_small and v) waits for them.
+      if (overlap_ok(it, after, k_ops, k)) {
+        const Item next = sched[k++];
+        Prog after2 = collect(k);
+        DMTS_HIP(hipEventRecord(st->ev_fork, s));
+        DMTS_HIP(hipStreamWaitEvent(st->side, st->ev_fork, 0));
+        if ((r = run_eval(it, after, st->side)) != DMTS_OK) return r;
+        DMTS_HIP(hipEventRecord(st->ev_join, st->side));
+        if (after2.nops == 0) DMTS_HIP(hipStreamWaitEvent(s, st->ev_join, 0));
+        if ((r = run_eval(next, after2, nullptr, after2.nops ? st->ev_join : nullptr)) != DMTS_OK)
+          return r;
+        after = after2;
+      } else if ((r = run_eval(it, after)) != DMTS_OK) {
+        return r;
+      }
       while (k < sched.size() && !sched[k].eval) {   // more ops than one program holds
         if ((r = apply(collect(k))) != DMTS_OK) return r;
       }
     }
     sched.clear();
     return DMTS_OK;
+  }
+  // The overlap needs the shared list (the fast model reads the current buffer while the
+  // reference model builds the other), two distinct models (separate workspaces), and no
+  // drift between the two evaluations.
+  bool overlap_ok(const Item& it, const Prog& after, size_t k_ops, size_t k_next) const {
+    if (!shared || !st->side || small == large || it.op_or_kind != kEvalSmall) return false;
+    if (k_next >= sched.size() || !sched[k_next].eval || sched[k_next].op_or_kind != kEvalLarge)
+      return false;
+    if (k_next - k_ops != (size_t)after.nops) return false;   // all ops fit one program
+    for (int q = 0; q < after.nops; ++q)
+      if (after.op[q] == kDrift) return false;
+    return true;
   }
 };
 
@@ -306,6 +347,9 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
   if (r == DMTS_OK)
     r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 16), 16,
                          reinterpret_cast<nnp_nlist**>(&st->nl_large));
+  if (r == DMTS_OK)
+    r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 16), 16,
+                         reinterpret_cast<nnp_nlist**>(&st->nl_large2));
   double hm[16] = {0}, him[16] = {0};
   for (int z = 0; z < n_species; ++z) {
     hm[z] = host_mass_by_species[z];
@@ -326,6 +370,10 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     if (e == hipSuccess) e = hipMemcpy(st->inv_mass, him, sizeof(him), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(st->e_models, 0, sizeof(double) * 4);
     if (e == hipSuccess) e = hipMemset(st->flags, 0, sizeof(uint32_t));
+    // side stream at the default priority, synchronised with the caller's stream by events
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       dmts::set_error("dmts_state_create: %s", hipGetErrorString(e));
@@ -346,6 +394,10 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   (void)hipDeviceSynchronize();
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_small));
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large));
+  nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large2));
+  if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
+  if (st->ev_join) (void)hipEventDestroy(st->ev_join);
+  if (st->side) (void)hipStreamDestroy(st->side);
   (void)hipFree(st->FL);
   (void)hipFree(st->Fs);
   (void)hipFree(st->x_ref);
@@ -385,12 +437,14 @@ extern "C" dmts_status dmts_state_flags(dmts_state* h, void* stream, uint32_t* h
   DMTS_REQUIRE(st && host_flags, DMTS_E_ARG, "dmts_state_flags: null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   dmts::k_merge_flags<<<1, 64, 0, s>>>(st->flags, st->nl_small->flags, st->nl_large->flags);
+  dmts::k_merge_flags<<<1, 64, 0, s>>>(st->flags, st->nl_large2->flags, st->nl_large2->flags);
   DMTS_CHECK_LAUNCH();
   DMTS_HIP(hipMemcpyAsync(host_flags, st->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   DMTS_HIP(hipStreamSynchronize(s));
   dmts_status r = dmts::fill_u32(st->flags, 0u, 1, s);
   if (r == DMTS_OK) r = dmts::fill_u32(st->nl_small->flags, 0u, 1, s);
   if (r == DMTS_OK) r = dmts::fill_u32(st->nl_large->flags, 0u, 1, s);
+  if (r == DMTS_OK) r = dmts::fill_u32(st->nl_large2->flags, 0u, 1, s);
   if (r != DMTS_OK) return r;
   DMTS_HIP(hipStreamSynchronize(s));
   return DMTS_OK;
@@ -457,6 +511,9 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
       dmts::Runner E{st, x, v, s};
       ++st->n_fallbacks;
       if ((r = dmts::run_steps(st, E, small, large, n_outer)) != DMTS_OK) return r;
+      // the exact lists of this call are not the shared list: the next call starts by
+      // evaluating both models (building a fresh shared list); the forces are the same
+      st->first = true;
     }
   }
   dmts::k_energies<<<1, 256, 0, s>>>(st->n, v, st->species, st->mass, st->e_models,

@@ -686,6 +686,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                        nullptr, nullptr, v, cap);
         }
         DMTS_CHECK_LAUNCH();
+        if (ep && ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
         {
           ProfScope ps(DMTS_K_GATHER, s);
           k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces,

@@ -414,6 +414,7 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
     // the integrator program runs as a launch of its own here: in the reverse kernel's
     // epilogue it would lengthen every wave by more than the launch costs
     if (ep) {
+      if (ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
       const dmts_status st = apply_program(*ep, n, s);
       if (st != DMTS_OK) return st;
     }
