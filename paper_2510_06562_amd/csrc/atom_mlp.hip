@@ -103,14 +103,31 @@ __device__ __forceinline__ void layer(const float* X, int K, LayerW Wt, int N, E
   }
 }
 
-// Stage rows [m0, m0+16) of a global row-major array (ld floats, K used) into LDS.
-__device__ __forceinline__ void stage_rows(float* X, const float* __restrict__ G, int ld, int K,
-                                           int m0, int M) {
-  for (int e = threadIdx.x; e < kRows * K; e += kThreads) {
-    const int r = e / K, k = e - r * K;
-    X[r * kLd + k] = (m0 + r) < M ? G[(size_t)(m0 + r) * ld + k] : 0.f;
+// Stage rows [m0, m0+16) of a global row-major array (ld floats, K used; K and ld
+// multiples of 4) into LDS with row stride `xld`, in two halves: load() issues the thread's
+// 16-byte loads, store() writes them, so that the loads of several arrays are in flight
+// together (one memory round trip).
+template <int K>
+struct RowStage {
+  static constexpr int kV = kRows * K / 4, kPer = (kV + kThreads - 1) / kThreads;
+  float4 t[kPer];
+  __device__ __forceinline__ void load(const float* __restrict__ G, int ld, int m0, int M) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * kThreads, r = e / (K / 4), k4 = e % (K / 4);
+      t[u] = e < kV && (m0 + r) < M
+                 ? *reinterpret_cast<const float4*>(G + (size_t)(m0 + r) * ld + 4 * k4)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
-}
+  __device__ __forceinline__ void store(float* X, int xld) const {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * kThreads, r = e / (K / 4), k4 = e % (K / 4);
+      if (e < kV) *reinterpret_cast<float4*>(X + r * xld + 4 * k4) = t[u];
+    }
+  }
+};
 
 __global__ void __launch_bounds__(kThreads)
 k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict__ z1,
@@ -118,7 +135,11 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
   __shared__ float X[kRows * kLd];
   __shared__ float H[kRows * kLd];
   const int m0 = blockIdx.x * kRows;
-  stage_rows(X, q1, 384, 384, m0, M);
+  {
+    RowStage<384> a;
+    a.load(q1, 384, m0, M);
+    a.store(X, kLd);
+  }
   __syncthreads();
   layer(X, 384, LayerW{P.U1, P.h_U1}, 128, [&](int r, int c, float v) {
     const float h = silu_f(v);
@@ -141,15 +162,22 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
   __shared__ float X[kRows * kLd];     // q2, later dz2
   __shared__ float H[kRows * kLd];     // h2, later dy
   __shared__ float Z[kRows * 128];     // z2
-  __shared__ float E[kRows * 128];     // per-column energy terms of y
+  __shared__ float E[kRows * 128];     // per-column energy terms of y, first h1
   const int m0 = blockIdx.x * kRows;
-  stage_rows(X, q2, 384, 384, m0, M);
+  {
+    RowStage<384> a;
+    RowStage<128> b;
+    a.load(q2, 384, m0, M);
+    b.load(h1, 128, m0, M);
+    a.store(X, kLd);
+    b.store(E, 128);
+  }
   __syncthreads();
   layer(X, 384, LayerW{P.U2, P.h_U2}, 128, [&](int r, int c, float v) {
     Z[r * 128 + c] = v;
-    const float hp = (m0 + r) < M ? h1[(size_t)(m0 + r) * 128 + c] : 0.f;
-    H[r * kLd + c] = hp + silu_f(v);
+    H[r * kLd + c] = E[r * 128 + c] + silu_f(v);
   });
+  __syncthreads();   // E (h1) is overwritten by the next layer
   __syncthreads();
   // y = W_o h2; energy terms and dy (dy overwrites the X buffer)
   layer(H, 128, LayerW{P.Wo, P.h_Wo}, 128, [&](int r, int c, float v) {
@@ -186,16 +214,22 @@ k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __re
          const float* __restrict__ z1, float* __restrict__ dq1) {
   __shared__ float X[kRows * kLd];
   __shared__ float H[kRows * kLd];
+  __shared__ float D2[kRows * 128], Z1[kRows * 128];   // dh2, z1 rows
   const int m0 = blockIdx.x * kRows;
-  stage_rows(X, RS, 256, 256, m0, M);
+  {
+    RowStage<256> a;
+    RowStage<128> b, c;
+    a.load(RS, 256, m0, M);
+    b.load(dh2, 128, m0, M);
+    c.load(z1, 128, m0, M);
+    a.store(X, kLd);
+    b.store(D2, 128);
+    c.store(Z1, 128);
+  }
   __syncthreads();
   layer(X, 256, LayerW{P.W2hs, P.h_W2hs}, 128, [&](int r, int c, float v) {
-    float dz = 0.f;
-    if (m0 + r < M) {
-      const size_t o = (size_t)(m0 + r) * 128 + c;
-      dz = (v + dh2[o]) * dsilu_f(z1[o]);
-    }
-    H[r * kLd + c] = dz;
+    const int o = r * 128 + c;
+    H[r * kLd + c] = m0 + r < M ? (v + D2[o]) * dsilu_f(Z1[o]) : 0.f;
   });
   __syncthreads();
   layer(H, 128, LayerW{P.U1T, P.h_U1T}, 384, [&](int r, int c, float v) {
