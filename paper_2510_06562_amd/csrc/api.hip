@@ -94,25 +94,37 @@ bool ProfScope::packet(hipEvent_t& start, hipEvent_t& stop) {
 
 namespace {
 
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceIlp = 8;
 
-// energy[s] = sum of atom_e over system s, float64, fixed reduction tree.
+// energy[s] = sum of atom_e over system s, float64.  The reduction order is fixed and
+// depends only on the position within the system (lane, then eight independent
+// accumulators per lane, then a butterfly within each wave and the wave sums in order),
+// so a system sums to the same bits alone or inside a batch.
 __global__ void __launch_bounds__(kReduceThreads)
 k_reduce_energy(const float* __restrict__ atom_e, int n, const int32_t* __restrict__ offs,
                 double* __restrict__ energy) {
-  __shared__ double part[kReduceThreads];
+  __shared__ double wsum[kReduceThreads / 64];
   const int sys = blockIdx.x;
   const int lo = offs ? max(0, offs[sys]) : 0;
   const int hi = offs ? min(n, offs[sys + 1]) : n;
-  double acc = 0.0;
-  for (int k = lo + threadIdx.x; k < hi; k += kReduceThreads) acc += (double)atom_e[k];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-    __syncthreads();
+  double a[kReduceIlp] = {};
+  for (int base = lo + (int)threadIdx.x; base < hi; base += kReduceThreads * kReduceIlp) {
+#pragma unroll
+    for (int j = 0; j < kReduceIlp; ++j) {
+      const int k = base + j * kReduceThreads;
+      if (k < hi) a[j] += (double)atom_e[k];
+    }
   }
-  if (threadIdx.x == 0) energy[sys] = part[0];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int w = 0; w < kReduceThreads / 64; ++w) e += wsum[w];
+    energy[sys] = e;
+  }
 }
 
 }  // namespace

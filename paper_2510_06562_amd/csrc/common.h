@@ -67,6 +67,7 @@ struct NList {
   float4* geo = nullptr;     // [max_pairs] (dx, dy, dz, r) at the build positions
   int32_t* cnt = nullptr;    // [max_atoms] padded row lengths
   uint32_t* flags = nullptr; // [1]
+  int64_t* scan_part = nullptr;  // per-tile totals of the offset scans
   int32_t* len = nullptr;    // [max_atoms] real row lengths
   int32_t* ell = nullptr;    // [max_atoms][kNlistRowCap] sorted rows before compaction
   // cell list scratch

@@ -46,27 +46,35 @@ __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b,
   if (i < n) b[i] = a[i];
 }
 
-// Kinetic energy sum(m v^2)/2 / KAPPA in eV (single work-group, fixed tree), then
-// out = {E_large, E_small, KE, E_large + KE}.
-__global__ void __launch_bounds__(256)
+// Kinetic energy sum(m v^2)/2 / KAPPA in eV (single work-group, fixed order: eight
+// independent accumulators per lane, a butterfly within each wave, the wave sums in
+// order), then out = {E_large, E_small, KE, E_large + KE}.
+constexpr int kKeThreads = 1024;
+__global__ void __launch_bounds__(kKeThreads)
 k_energies(int n, const double* __restrict__ v, const int32_t* __restrict__ species,
            const double* __restrict__ mass, const double* __restrict__ e_models,
            double* __restrict__ out, uint32_t* __restrict__ flags) {
-  __shared__ double part[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const double m = mass[species[i]];
-    const double a = v[i], b = v[(size_t)n + i], c = v[2 * (size_t)n + i];
-    acc += m * (a * a + b * b + c * c);
+  __shared__ double wsum[kKeThreads / 64];
+  double a[8] = {};
+  for (int base = threadIdx.x; base < n; base += kKeThreads * 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j * kKeThreads;
+      if (i < n) {
+        const double m = mass[species[i]];
+        const double x = v[i], y = v[(size_t)n + i], z = v[2 * (size_t)n + i];
+        a[j] += m * (x * x + y * y + z * z);
+      }
+    }
   }
-  part[threadIdx.x] = acc;
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    const double ke = 0.5 * part[0] / kKappa;
+    double sum = 0.0;
+    for (int w = 0; w < kKeThreads / 64; ++w) sum += wsum[w];
+    const double ke = 0.5 * sum / kKappa;
     const double el = e_models[0], es = e_models[1];
     if (out) {
       out[0] = el;
@@ -516,8 +524,8 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
       st->first = true;
     }
   }
-  dmts::k_energies<<<1, 256, 0, s>>>(st->n, v, st->species, st->mass, st->e_models,
-                                     energies_out, st->flags);
+  dmts::k_energies<<<1, dmts::kKeThreads, 0, s>>>(st->n, v, st->species, st->mass,
+                                                  st->e_models, energies_out, st->flags);
   DMTS_CHECK_LAUNCH();
   uint32_t f = 0;
   if ((r = dmts_state_flags(h, stream, &f)) != DMTS_OK) return r;

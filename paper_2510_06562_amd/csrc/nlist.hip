@@ -28,49 +28,109 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-// Exclusive scan of in[0..n) into out[0..n]; single work-group.  When the total exceeds
-// `cap` the list would not fit: every offset is set to 0 (all rows empty) and the
-// overflow flag is raised, so no consumer can index past the capacity.
-// With `zero_in`, the input is cleared after it has been read (the cell counters are then
-// ready for the next build without a separate fill).
-__global__ void __launch_bounds__(kScanThreads) k_scan(int32_t* __restrict__ in,
-                                                      int32_t* __restrict__ out,
-                                                      int32_t* __restrict__ copy_to,
-                                                      int32_t n, int64_t cap,
-                                                      uint32_t* __restrict__ flags,
-                                                      bool zero_in) {
-  __shared__ int64_t part[kScanThreads];
-  __shared__ int64_t total_s;
-  const int t = threadIdx.x;
-  const int per = (n + kScanThreads - 1) / kScanThreads;
-  const int lo = min(n, t * per), hi = min(n, lo + per);
+// Exclusive scan of in[0..n) into out[0..n] in two launches over tiles of kScanTile
+// elements: k_scan_sums writes each tile's total, k_scan_tiles adds the totals of the
+// tiles before its own and scans its tile.  Every load and store is coalesced (lane-
+// contiguous runs) and the work per lane is a few elements, so the latency of a long
+// serial loop is gone.  When the total exceeds `cap` the list would not fit: every
+// offset is set to 0 (all rows empty) and the overflow flag is raised, so no consumer
+// can index past the capacity.  With `zero_in`, the input is cleared after it has been
+// read (the cell counters are then ready for the next build without a separate fill).
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();  // red may still be read by a previous call
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  int64_t t = 0;
+  for (int k = 0; k < kScanThreads / 64; ++k) t += red[k];
+  return t;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(const int32_t* __restrict__ in,
+                                                           int32_t n,
+                                                           int64_t* __restrict__ part) {
+  __shared__ int64_t red[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
   int64_t s = 0;
-  for (int k = lo; k < hi; ++k) s += in[k];
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the per-thread sums
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    int64_t add = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    const int64_t k = base + i * kScanThreads + threadIdx.x;
+    s += k < n ? in[k] : 0;
   }
-  if (t == kScanThreads - 1) total_s = part[t];
-  __syncthreads();
-  const int64_t total = total_s;
+  s = block_sum_i64(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int32_t* __restrict__ in,
+                                                            int32_t* __restrict__ out,
+                                                            int32_t* __restrict__ copy_to,
+                                                            int32_t n, int64_t cap,
+                                                            uint32_t* __restrict__ flags,
+                                                            bool zero_in,
+                                                            const int64_t* __restrict__ part,
+                                                            int n_tiles) {
+  __shared__ int64_t red[kScanThreads / 64];
+  __shared__ int64_t wsum[kScanThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // offset of this tile and the grand total
+  int64_t before = 0, all = 0;
+  for (int k = t; k < n_tiles; k += kScanThreads) {
+    const int64_t v = part[k];
+    all += v;
+    before += k < (int)blockIdx.x ? v : 0;
+  }
+  before = block_sum_i64(before, red);
+  const int64_t total = block_sum_i64(all, red);
   const bool overflow = total > cap;
-  int64_t run = (t == 0) ? 0 : part[t - 1];
-  for (int k = lo; k < hi; ++k) {
-    int32_t o = overflow ? 0 : static_cast<int32_t>(run);
-    out[k] = o;
-    if (copy_to) copy_to[k] = o;
-    run += in[k];
-    if (zero_in) in[k] = 0;
+  // this lane's run of kScanPer consecutive elements
+  const int64_t k0 = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanPer;
+  int32_t v[kScanPer];
+  int64_t run = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = k0 + i < n ? in[k0 + i] : 0;
+    run += v[i];
   }
-  if (t == 0) {
+  // inclusive scan of the lane sums within the wave, then across the waves
+  int64_t incl = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int64_t wbase = 0;
+  for (int k = 0; k < w; ++k) wbase += wsum[k];
+  int64_t o = before + wbase + incl - run;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (k0 + i < n) {
+      const int32_t r = overflow ? 0 : static_cast<int32_t>(o);
+      out[k0 + i] = r;
+      if (copy_to) copy_to[k0 + i] = r;
+      if (zero_in) in[k0 + i] = 0;
+    }
+    o += v[i];
+  }
+  if (blockIdx.x == 0 && t == 0) {
     out[n] = overflow ? 0 : static_cast<int32_t>(total);
     if (overflow && flags) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
   }
+}
+
+int scan_tiles(int64_t n) { return n <= 0 ? 1 : (int)((n + kScanTile - 1) / kScanTile); }
+
+// The two scan launches; `part` holds at least scan_tiles(n) values.
+void scan(int32_t* in, int32_t* out, int32_t* copy_to, int32_t n, int64_t cap, uint32_t* flags,
+          bool zero_in, int64_t* part, hipStream_t s) {
+  const int tiles = scan_tiles(n);
+  k_scan_sums<<<tiles, kScanThreads, 0, s>>>(in, n, part);
+  k_scan_tiles<<<tiles, kScanThreads, 0, s>>>(in, out, copy_to, n, cap, flags, zero_in, part,
+                                              tiles);
 }
 
 __device__ __forceinline__ int cell_coord(double x, double box, double inv_cell, int nc) {
@@ -402,8 +462,7 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
       k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
                                                      cell_count);
       DMTS_CHECK_LAUNCH();
-      k_scan<<<1, kScanThreads, 0, s>>>(cell_count, cell_start, cursor, n_cells, INT64_MAX,
-                                        nullptr, true);
+      scan(cell_count, cell_start, cursor, n_cells, INT64_MAX, nullptr, true, nl->scan_part, s);
       DMTS_CHECK_LAUNCH();
       k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms);
       DMTS_CHECK_LAUNCH();
@@ -418,8 +477,7 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
     k_rows<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align,
                                                     nl->ell, nl->len, nl->cnt, nl->flags);
   DMTS_CHECK_LAUNCH();
-  k_scan<<<1, kScanThreads, 0, s>>>(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags,
-                                    false);
+  scan(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags, false, nl->scan_part, s);
   DMTS_CHECK_LAUNCH();
   k_compact<<<blocks, kNbWaves * 64, 0, s>>>(g, nl->ell, nl->len, nl->offs, nl->nbr, nl->rev,
                                              nl->geo);
@@ -457,6 +515,10 @@ extern "C" dmts_status nnp_nlist_create(int32_t max_atoms, int64_t max_pairs,
   e = e == hipSuccess ? hipMalloc(&nl->rev, sizeof(int32_t) * nl->max_pairs) : e;
   e = e == hipSuccess ? hipMalloc(&nl->geo, sizeof(float4) * nl->max_pairs) : e;
   e = e == hipSuccess ? hipMalloc(&nl->flags, sizeof(uint32_t)) : e;
+  const int tiles = std::max(dmts::scan_tiles(max_atoms),
+                             dmts::scan_tiles(int64_t(dmts::kMaxCellsPerDim) *
+                                              dmts::kMaxCellsPerDim * dmts::kMaxCellsPerDim));
+  e = e == hipSuccess ? hipMalloc(&nl->scan_part, sizeof(int64_t) * tiles) : e;
   e = e == hipSuccess ? hipMemset(nl->flags, 0, sizeof(uint32_t)) : e;
   e = e == hipSuccess ? hipMemset(nl->offs, 0, sizeof(int32_t) * (a + 1)) : e;
   e = e == hipSuccess ? hipDeviceSynchronize() : e;
@@ -483,6 +545,7 @@ extern "C" void nnp_nlist_destroy(nnp_nlist* h) {
   (void)hipFree(nl->rev);
   (void)hipFree(nl->geo);
   (void)hipFree(nl->flags);
+  (void)hipFree(nl->scan_part);
   nl->cell_buf.release();
   delete nl;
 }

@@ -77,9 +77,10 @@ def test_neighbor_set_matches_oracle(sysname, cut, align):
     assert np.array_equal(offs, offs2) and np.array_equal(nbr, nbr2) and np.array_equal(rev, rev2)
 
 
-def test_neighbor_overflow_sets_flag_and_empties_rows():
-    say("nlist overflow")
-    sy = system("water192")
+@pytest.mark.parametrize("sysname", ["water192", "water21k"])
+def test_neighbor_overflow_sets_flag_and_empties_rows(sysname):
+    say(f"nlist overflow {sysname}")
+    sy = system(sysname)
     pos, _, _ = _dev(sy)
     nl = api.NeighborList(sy.n_atoms, 1000, 4)
     nl.build(pos, sy.box, 5.2)
@@ -114,7 +115,7 @@ def _check_energy_forces(sysname, which, models):
     return E, F
 
 
-@pytest.mark.parametrize("sysname", ["water192", "water4500", "open60", "batch16"])
+@pytest.mark.parametrize("sysname", ["water192", "water4500", "open60", "batch16", "water21k"])
 def test_small_model_parity(sysname, models):
     say(f"small model {sysname}")
     _check_energy_forces(sysname, "small", models)
