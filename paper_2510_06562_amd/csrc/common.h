@@ -346,15 +346,15 @@ __device__ __forceinline__ float logistic_f(float t) {
   return __builtin_amdgcn_rcpf(1.0f + __expf(-t));
 }
 __device__ __forceinline__ float silu_f(float t) { return t * logistic_f(t); }
-// d/dt SiLU = s (1 + t (1 - s)), s = logistic(t)
+// d/dt SiLU = s (1 + t (1 - s)) = s + SiLU(t) (1 - s), s = logistic(t)
 __device__ __forceinline__ float dsilu_f(float t) {
   const float s = logistic_f(t);
-  return s * (1.0f + t * (1.0f - s));
+  return fmaf(t * s, 1.0f - s, s);
 }
 __device__ __forceinline__ void silu_and_grad(float t, float& y, float& dy) {
   const float s = logistic_f(t);
   y = t * s;
-  dy = s * (1.0f + t * (1.0f - s));
+  dy = fmaf(y, 1.0f - s, s);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {

@@ -116,6 +116,34 @@ __device__ __forceinline__ void split_terms(const float (&x)[8], bf16x8 (&t)[NP]
   }
 }
 
+// b_k(r) = exp(-(r - k sigma)^2 / (2 sigma^2)) at k = k0 .. k0 + 7 (zero for an invalid
+// pair).  NP = 3: eight exponentials.  NP = 1: the centres are sigma apart, so
+// b_{k+1} = b_k rho_k with rho_k = exp((r - k sigma) / sigma - 1/2) = rho_{k-1} / e; two
+// exponentials, at a relative error of a few 1e-6, far below the bfloat16 rounding of the
+// operand.  With r < r_c = (K - 1) sigma the ratio stays below e^K.
+template <int NP>
+__device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float sigma,
+                                             float inv_s2, float (&bk)[8]) {
+  if (NP == 1) {
+    const float x0 = r - sigma * k0;
+    float b = valid ? __expf(-0.5f * x0 * x0 * inv_s2) : 0.f;
+    float rho = valid ? __expf(x0 * (sigma * inv_s2) - 0.5f) : 0.f;
+    bk[0] = b;
+#pragma unroll
+    for (int e = 1; e < 8; ++e) {
+      b *= rho;
+      rho *= 0.36787944117144233f;   // e^-1
+      bk[e] = b;
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x = r - sigma * (k0 + e);
+    bk[e] = valid ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+  }
+}
+
 // acc += W_b . b over K = 32 for one 16 x 16 block from NP-term operands; w_is_a selects
 // the transposed product (W_b rows as the A operand).
 template <int NP>
@@ -218,11 +246,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     const float rp = geo[t0 + cl].w;
     const bool vp = nbr[t0 + cl] >= 0 && rp < P.rc;
     float bk[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float x = rp - P.sigma * (8 * g + e);
-      bk[e] = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
-    }
+    radial_basis<NP>(rp, vp, 8 * g, P.sigma, inv_s2, bk);
     bf16x8 bt[NP];
     split_terms<NP>(bk, bt);
     // the lane's four pairs of the D layout: 4 g + r
@@ -257,14 +281,14 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     for (int b = 0; b < 4; ++b) {
       bf16x8 wt[NP];
       load_w<NP>(sW, 16 * b + cl, g, wt);
-      acc[b] = radial_block<NP>(wt, bt, f32x4{0.f, 0.f, 0.f, 0.f}, false);
+      acc[b] = radial_block<NP>(wt, bt, f32x4{base[b], base[b], base[b], base[b]}, false);
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       f32x4 mv;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float a = acc[b][r] + base[b] + snd[b][r];   // f_c = 0 if invalid
+        const float a = acc[b][r] + snd[b][r];   // f_c = 0 if invalid
         mv[r] = fc[r] * silu_f(a);
       }
 #pragma unroll
@@ -316,7 +340,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   // per wave, over its 64 channels (local index cc = c - 64 half)
   __shared__ float sD[kWaves][NMOM * kLdH];          // D[y][cc] of the receiver (dswz)
-  __shared__ float sB[kWaves][F_L / 2];              // receiver term S_i of a_ij
+  __shared__ __align__(16) float sB[kWaves][F_L / 2];   // receiver term S_i of a_ij
   __shared__ float sR[LAYER == 2 ? kWaves : 1][LAYER == 2 ? kTile * kLdR : 1];
   const int half = blockIdx.x & 1, hb = 4 * half;
   stage_w<NP>(sW, P.Wb, half);
@@ -358,8 +382,9 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
   const float pi_rc = 3.14159265358979f * irc;
-  // row of D read by lane (cl, g) for the angular sums: k + 1 = cl + 1 (clamped; lanes
-  // cl >= 9 are masked)
+  // row of D read by lane (cl, g) for the angular sums: k + 1 = cl + 1, clamped to row 9
+  // for cl >= 9, whose output rows k >= 9 are not used (an MFMA output row depends only on
+  // the A row of the same index, so any finite value will do there)
   const int kr = cl < 9 ? cl + 1 : 9;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
@@ -376,12 +401,11 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     bf16x8 bt[NP], dbt[NP];
     {
       float bk[8], dbk[8];
+      radial_basis<NP>(gv.w, vp, 8 * g, P.sigma, inv_s2, bk);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const float x = gv.w - P.sigma * (8 * g + e);
-        const float b = vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
-        bk[e] = b;
-        dbk[e] = -x * inv_s2 * b;
+        dbk[e] = -x * inv_s2 * bk[e];
       }
       split_terms<NP>(bk, bt);
       split_terms<NP>(dbk, dbt);
@@ -407,16 +431,24 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
                        : *reinterpret_cast<const float4*>(Tj + c0);
       bf16x8 wt[NP];
       load_w<NP>(sW, 16 * bb4 + cl, g, wt);
-      ga = radial_block<NP>(wt, bt, f32x4{0.f, 0.f, 0.f, 0.f}, true);
+      // the BF16 form starts the accumulator from the receiver term of its four channels;
+      // the FP32 form adds it afterwards (fewer registers live across its 12 products)
+      f32x4 init = {0.f, 0.f, 0.f, 0.f};
+      if (NP == 1) {
+        const float4 br = *reinterpret_cast<const float4*>(&sB[w][16 * bb4 + 4 * g]);
+        init = f32x4{br.x, br.y, br.z, br.w};
+      }
+      ga = radial_block<NP>(wt, bt, init, true);
       gd = radial_block<NP>(wt, dbt, f32x4{0.f, 0.f, 0.f, 0.f}, true);
       dmv = f32x4{0.f, 0.f, 0.f, 0.f};
-      // K index 4 s + g = y runs over the ten components; rows 10 and 11 are zero and
-      // rows 12..15 (s = 3) are left out
+      // K index 4 s + g = y runs over the ten components; rows 12..15 (s = 3) are left
+      // out, and at y = 10, 11 the B operand (Y) is zero, so the A operand there may be
+      // any finite value: the clamped row 9
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int y = 4 * s + g;
         const float dy = sd[dswz(y < NMOM ? y : NMOM - 1, 16 * bb4 + cl)];
-        dmv = __builtin_amdgcn_mfma_f32_16x16x4f32(y < NMOM ? dy : 0.f, yop[s], dmv, 0, 0, 0);
+        dmv = __builtin_amdgcn_mfma_f32_16x16x4f32(dy, yop[s], dmv, 0, 0, 0);
       }
     };
     f32x4 ga, gd, dmv;
@@ -431,14 +463,15 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       const int b = hb + bb4;
       const int c0 = 16 * b + 4 * g;   // the lane's four channels c0 .. c0+3
       const int l0 = 16 * bb4 + 4 * g;  // their index within the half
-      const float4 bb = *reinterpret_cast<const float4*>(&sB[w][l0]);
+      const float4 bb = NP == 1 ? make_float4(0.f, 0.f, 0.f, 0.f)
+                                : *reinterpret_cast<const float4*>(&sB[w][l0]);
       f32x4 mv;
       float4 dav;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float addr = r == 0 ? add.x : r == 1 ? add.y : r == 2 ? add.z : add.w;
         const float br = r == 0 ? bb.x : r == 1 ? bb.y : r == 2 ? bb.z : bb.w;
-        const float a = ga[r] + br + addr;
+        const float a = NP == 1 ? ga[r] + addr : ga[r] + br + addr;
         float sv, dsv;
         silu_and_grad(a, sv, dsv);
         const float m = fc * sv;
@@ -452,7 +485,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const float dk = sd[dswz(kr, l0 + s4)];
-        Gt = __builtin_amdgcn_mfma_f32_16x16x4f32(cl < 9 ? dk : 0.f, mv[s4], Gt, 0, 0, 0);
+        Gt = __builtin_amdgcn_mfma_f32_16x16x4f32(dk, mv[s4], Gt, 0, 0, 0);
       }
       if (LAYER == 2) {
         *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
