@@ -94,13 +94,35 @@ bool ProfScope::packet(hipEvent_t& start, hipEvent_t& stop) {
 
 namespace {
 
-constexpr int kReduceThreads = 1024;
+constexpr int kReduceThreads = 256;
 constexpr int kReduceIlp = 8;
+constexpr int kEChunk = kReduceThreads * kReduceIlp;   // atoms per chunk
 
-// energy[s] = sum of atom_e over system s, float64.  The reduction order is fixed and
-// depends only on the position within the system (lane, then eight independent
-// accumulators per lane, then a butterfly within each wave and the wave sums in order),
-// so a system sums to the same bits alone or inside a batch.
+// FP64 sum of atom_e[base .. end) (end - base <= kEChunk) in a fixed order: lane t adds
+// elements t + 256 j into accumulator j, the eight accumulators pairwise, a butterfly
+// within each wave, then the four wave sums in order.  Valid in thread 0.
+__device__ double chunk_sum(const float* __restrict__ atom_e, int base, int end, double* wsum) {
+  double a[kReduceIlp];
+#pragma unroll
+  for (int j = 0; j < kReduceIlp; ++j) {
+    const int k = base + (int)threadIdx.x + j * kReduceThreads;
+    a[j] = k < end ? (double)atom_e[k] : 0.0;
+  }
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  __syncthreads();   // wsum may still be read for the previous chunk
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  double e = 0.0;
+  for (int w = 0; w < kReduceThreads / 64; ++w) e += wsum[w];
+  return e;
+}
+
+// energy[s] = sum of atom_e over system s, float64: the chunk sums of the system (chunks of
+// kEChunk atoms from its first atom) added in order.  The order depends only on the
+// position within the system, so a system sums to the same bits alone or inside a batch,
+// and whether its chunks are summed by one work-group (here) or by one each
+// (k_energy_chunks and k_energy_final).
 __global__ void __launch_bounds__(kReduceThreads)
 k_reduce_energy(const float* __restrict__ atom_e, int n, const int32_t* __restrict__ offs,
                 double* __restrict__ energy) {
@@ -108,23 +130,25 @@ k_reduce_energy(const float* __restrict__ atom_e, int n, const int32_t* __restri
   const int sys = blockIdx.x;
   const int lo = offs ? max(0, offs[sys]) : 0;
   const int hi = offs ? min(n, offs[sys + 1]) : n;
-  double a[kReduceIlp] = {};
-  for (int base = lo + (int)threadIdx.x; base < hi; base += kReduceThreads * kReduceIlp) {
-#pragma unroll
-    for (int j = 0; j < kReduceIlp; ++j) {
-      const int k = base + j * kReduceThreads;
-      if (k < hi) a[j] += (double)atom_e[k];
-    }
-  }
-  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double e = 0.0;
-    for (int w = 0; w < kReduceThreads / 64; ++w) e += wsum[w];
-    energy[sys] = e;
-  }
+  double e = 0.0;
+  for (int base = lo; base < hi; base += kEChunk) e += chunk_sum(atom_e, base, min(hi, base + kEChunk), wsum);
+  if (threadIdx.x == 0) energy[sys] = e;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_energy_chunks(const float* __restrict__ atom_e, int n, double* __restrict__ partial) {
+  __shared__ double wsum[kReduceThreads / 64];
+  const int base = blockIdx.x * kEChunk;
+  const double e = chunk_sum(atom_e, base, min(n, base + kEChunk), wsum);
+  if (threadIdx.x == 0) partial[blockIdx.x] = e;
+}
+
+__global__ void k_energy_final(const double* __restrict__ partial, int nc,
+                               double* __restrict__ energy) {
+  if (threadIdx.x != 0) return;
+  double e = 0.0;
+  for (int k = 0; k < nc; ++k) e += partial[k];
+  energy[0] = e;
 }
 
 }  // namespace
@@ -148,11 +172,20 @@ int resident_groups(const void* kernel, int threads) {
   return r;
 }
 
+size_t energy_partials(int32_t n) { return (size_t)(n + kEChunk - 1) / kEChunk + 1; }
+
 dmts_status reduce_energy(const float* atom_e, int32_t n, const int32_t* sys_offsets,
-                          int32_t n_sys, double* energy, hipStream_t s) {
+                          int32_t n_sys, double* energy, double* partial, hipStream_t s) {
   const int ns = sys_offsets ? n_sys : 1;
   if (ns <= 0) return DMTS_OK;
-  k_reduce_energy<<<ns, kReduceThreads, 0, s>>>(atom_e, n, sys_offsets, energy);
+  const int nc = (n + kEChunk - 1) / kEChunk;
+  if (!sys_offsets && nc > 1 && partial) {
+    // one system of several chunks: a work-group per chunk, then their sum in order
+    k_energy_chunks<<<nc, kReduceThreads, 0, s>>>(atom_e, n, partial);
+    k_energy_final<<<1, 64, 0, s>>>(partial, nc, energy);
+  } else {
+    k_reduce_energy<<<ns, kReduceThreads, 0, s>>>(atom_e, n, sys_offsets, energy);
+  }
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }

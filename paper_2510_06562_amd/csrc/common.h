@@ -306,9 +306,12 @@ dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t*
                           const Epilogue* ep = nullptr);
 
 // Deterministic FP64 sum of per-atom FP32 energies per system: energy[s] = sum over the
-// atoms of system s (one system when sys_offsets is NULL).
+// atoms of system s (one system when sys_offsets is NULL).  `partial` (energy_partials(n)
+// doubles, may be NULL) lets a single large system be summed by many work-groups; the
+// result has the same bits either way.
+size_t energy_partials(int32_t n);
 dmts_status reduce_energy(const float* atom_e, int32_t n, const int32_t* sys_offsets,
-                          int32_t n_sys, double* energy, hipStream_t s);
+                          int32_t n_sys, double* energy, double* partial, hipStream_t s);
 
 // Fill kernel (used instead of hipMemsetAsync so that streams can be captured).
 dmts_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

@@ -46,25 +46,27 @@ __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b,
   if (i < n) b[i] = a[i];
 }
 
-// Kinetic energy sum(m v^2)/2 / KAPPA in eV (single work-group, fixed order: eight
-// independent accumulators per lane, a butterfly within each wave, the wave sums in
-// order), then out = {E_large, E_small, KE, E_large + KE}.
-constexpr int kKeThreads = 1024;
+// Kinetic energy sum(m v^2)/2 / KAPPA in eV, in a fixed order: chunks of kKeChunk atoms
+// (one work-group each; lane t adds atoms t + 256 j into accumulator j, the eight
+// accumulators pairwise, a butterfly within each wave, the four wave sums in order), then
+// the chunk sums in order, and out = {E_large, E_small, KE, E_large + KE}.
+constexpr int kKeThreads = 256;
+constexpr int kKeChunk = kKeThreads * 8;
+
 __global__ void __launch_bounds__(kKeThreads)
-k_energies(int n, const double* __restrict__ v, const int32_t* __restrict__ species,
-           const double* __restrict__ mass, const double* __restrict__ e_models,
-           double* __restrict__ out, uint32_t* __restrict__ flags) {
+k_ke_chunks(int n, const double* __restrict__ v, const int32_t* __restrict__ species,
+            const double* __restrict__ mass, double* __restrict__ partial) {
   __shared__ double wsum[kKeThreads / 64];
-  double a[8] = {};
-  for (int base = threadIdx.x; base < n; base += kKeThreads * 8) {
+  const int base = blockIdx.x * kKeChunk;
+  double a[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = base + j * kKeThreads;
-      if (i < n) {
-        const double m = mass[species[i]];
-        const double x = v[i], y = v[(size_t)n + i], z = v[2 * (size_t)n + i];
-        a[j] += m * (x * x + y * y + z * z);
-      }
+  for (int j = 0; j < 8; ++j) {
+    const int i = base + (int)threadIdx.x + j * kKeThreads;
+    a[j] = 0.0;
+    if (i < n) {
+      const double m = mass[species[i]];
+      const double x = v[i], y = v[(size_t)n + i], z = v[2 * (size_t)n + i];
+      a[j] = m * (x * x + y * y + z * z);
     }
   }
   double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
@@ -72,18 +74,27 @@ k_energies(int n, const double* __restrict__ v, const int32_t* __restrict__ spec
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double sum = 0.0;
-    for (int w = 0; w < kKeThreads / 64; ++w) sum += wsum[w];
-    const double ke = 0.5 * sum / kKappa;
-    const double el = e_models[0], es = e_models[1];
-    if (out) {
-      out[0] = el;
-      out[1] = es;
-      out[2] = ke;
-      out[3] = el + ke;
-    }
-    if (!isfinite(el) || !isfinite(es) || !isfinite(ke)) atomicOr(flags, DMTS_FLAG_NONFINITE);
+    double e = 0.0;
+    for (int w = 0; w < kKeThreads / 64; ++w) e += wsum[w];
+    partial[blockIdx.x] = e;
   }
+}
+
+__global__ void k_energies(const double* __restrict__ partial, int nc,
+                           const double* __restrict__ e_models, double* __restrict__ out,
+                           uint32_t* __restrict__ flags) {
+  if (threadIdx.x != 0) return;
+  double sum = 0.0;
+  for (int k = 0; k < nc; ++k) sum += partial[k];
+  const double ke = 0.5 * sum / kKappa;
+  const double el = e_models[0], es = e_models[1];
+  if (out) {
+    out[0] = el;
+    out[1] = es;
+    out[2] = ke;
+    out[3] = el + ke;
+  }
+  if (!isfinite(el) || !isfinite(es) || !isfinite(ke)) atomicOr(flags, DMTS_FLAG_NONFINITE);
 }
 
 __global__ void k_merge_flags(uint32_t* dst, const uint32_t* a, const uint32_t* b) {
@@ -116,6 +127,7 @@ struct State {
   double* inv_mass = nullptr;
   double host_inv_mass[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the same, for kernel arguments
   double* e_models = nullptr;   // {E_large, E_small}
+  double* ke_part = nullptr;    // per-chunk kinetic energy sums
   uint32_t* flags = nullptr;
   // models the carried forces belong to
   Model* last_small = nullptr;
@@ -373,6 +385,8 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     if (e == hipSuccess) e = hipMalloc(&st->mass, sizeof(double) * 16);
     if (e == hipSuccess) e = hipMalloc(&st->inv_mass, sizeof(double) * 16);
     if (e == hipSuccess) e = hipMalloc(&st->e_models, sizeof(double) * 4);
+    if (e == hipSuccess)
+      e = hipMalloc(&st->ke_part, sizeof(double) * ((size_t)n_atoms / dmts::kKeChunk + 1));
     if (e == hipSuccess) e = hipMalloc(&st->flags, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(st->mass, hm, sizeof(hm), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(st->inv_mass, him, sizeof(him), hipMemcpyHostToDevice);
@@ -413,6 +427,7 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   (void)hipFree(st->mass);
   (void)hipFree(st->inv_mass);
   (void)hipFree(st->e_models);
+  (void)hipFree(st->ke_part);
   (void)hipFree(st->flags);
   delete st;
 }
@@ -524,8 +539,13 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
       st->first = true;
     }
   }
-  dmts::k_energies<<<1, dmts::kKeThreads, 0, s>>>(st->n, v, st->species, st->mass,
-                                                  st->e_models, energies_out, st->flags);
+  {
+    const int nc = (st->n + dmts::kKeChunk - 1) / dmts::kKeChunk;
+    if (nc > 0)
+      dmts::k_ke_chunks<<<nc, dmts::kKeThreads, 0, s>>>(st->n, v, st->species, st->mass,
+                                                         st->ke_part);
+    dmts::k_energies<<<1, 64, 0, s>>>(st->ke_part, nc, st->e_models, energies_out, st->flags);
+  }
   DMTS_CHECK_LAUNCH();
   uint32_t f = 0;
   if ((r = dmts_state_flags(h, stream, &f)) != DMTS_OK) return r;

@@ -67,6 +67,13 @@ struct LargeParams {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// dE/da of interaction 2 per pair slot, kept for the sender sums: FP32 in the FP32 form,
+// bfloat16 (round to nearest even) in the BF16 form, where the sums feed a BF16 product
+template <int NP>
+using DAType = std::conditional_t<NP == 1, __bf16, float>;
 
 constexpr int kTile = 16;
 constexpr int kLdM = 68;    // LDS stride of the per-wave moment rows (64 channels)
@@ -334,8 +341,8 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
 k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, const float* __restrict__ Mall,
-                const float* __restrict__ dq, float* __restrict__ dA, float* __restrict__ RS,
-                float* __restrict__ v, int64_t cap) {
+                const float* __restrict__ dq, DAType<NP>* __restrict__ dA,
+                float* __restrict__ RS, float* __restrict__ v, int64_t cap) {
   __shared__ __bf16 sW[NP * (F_L / 2) * K_L];         // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   // per wave, over its 64 channels (local index cc = c - 64 half)
@@ -488,7 +495,12 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         Gt = __builtin_amdgcn_mfma_f32_16x16x4f32(dk, mv[s4], Gt, 0, 0, 0);
       }
       if (LAYER == 2) {
-        *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
+        if constexpr (NP == 1) {
+          const bf16x4 h = {(__bf16)dav.x, (__bf16)dav.y, (__bf16)dav.z, (__bf16)dav.w};
+          *reinterpret_cast<bf16x4*>(dA + (size_t)p * F_L + c0) = h;
+        } else {
+          *reinterpret_cast<float4*>(dA + (size_t)p * F_L + c0) = dav;
+        }
         float4* acc = reinterpret_cast<float4*>(&sR[w][cl * kLdR + l0]);
         float4 t = *acc;
         t.x += dav.x;
@@ -551,19 +563,27 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   }  // grid-stride loop over work-groups of atoms
 }
 
-// S_j = sum over the rows of j of dA at the reverse positions (the sender sums).  One wave
-// per atom, lane l owns channels 2l and 2l+1.  The row's reverse positions are read 64 at a
-// time (one per lane) and broadcast, so the dA rows of eight pairs are in flight at once;
-// they are added in row order.
+// S_j = sum over the rows of j of dA at the reverse positions (the sender sums), in FP32.
+// One wave per atom, lane l owns channels 2l and 2l+1.  The row's reverse positions are
+// read 64 at a time (one per lane) and broadcast, so the dA rows of eight pairs are in
+// flight at once; they are added in row order.
+__device__ __forceinline__ float2 load_da2(const float* dA, size_t k) {
+  return reinterpret_cast<const float2*>(dA)[k];
+}
+__device__ __forceinline__ float2 load_da2(const __bf16* dA, size_t k) {
+  const bf16x2 t = reinterpret_cast<const bf16x2*>(dA)[k];
+  return make_float2((float)t[0], (float)t[1]);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kWaves * 64)
 k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-                const int32_t* __restrict__ rev, int n, const float* __restrict__ dA,
+                const int32_t* __restrict__ rev, int n, const T* __restrict__ dA,
                 float* __restrict__ RS) {
   constexpr int kU = 8;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kWaves + w;
   if (i >= n) return;
-  const float2* dA2 = reinterpret_cast<const float2*>(dA);
   float2 s = make_float2(0.f, 0.f);
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int base = row0; base < row1; base += 64) {
@@ -575,7 +595,7 @@ k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nb
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int qq = __builtin_amdgcn_readlane(q, k + u);
-        t[u] = qq >= 0 ? dA2[(size_t)qq * (F_L / 2) + lane] : make_float2(0.f, 0.f);
+        t[u] = qq >= 0 ? load_da2(dA, (size_t)qq * (F_L / 2) + lane) : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
@@ -640,7 +660,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   const size_t o_M2 = o_q2 + N * 3 * F, o_dh2 = o_M2 + N * NMOM * F;
   const size_t o_dq2 = o_dh2 + N * F, o_RS = o_dq2 + N * 3 * F;
   const size_t o_dq1 = o_RS + N * 2 * F, o_e = o_dq1 + N * 3 * F;
-  const size_t total = o_e + N;
+  const size_t o_part = o_e + N;   // FP64 partial energy sums (even offset: N % 64 == 0)
+  const size_t total = o_part + 2 * energy_partials(n);
   DMTS_REQUIRE(m->atom_ws.reserve(total * sizeof(float), s) == DMTS_OK, DMTS_E_OOM,
                "large model: atom workspace");
   const int64_t cap = nl->max_pairs;
@@ -695,8 +716,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
                             forces != nullptr, s)) != DMTS_OK) return st;
       if (forces) {
-        float* dA = m->pair_ws.as<float>();
-        float* v = dA + (size_t)cap * F;
+        // pair workspace: dA [cap][F] (FP32 or bfloat16), then v [2][3][cap] FP32
+        DAType<NP>* dA = m->pair_ws.as<DAType<NP>>();
+        float* v = m->pair_ws.as<float>() + (size_t)cap * F;
         {
           ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
           launch_timed(ps, &k_pair_bwd_mfma<2, NP>, grid_of(&k_pair_bwd_mfma<2, NP>), wg, s, P2,
@@ -706,8 +728,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         DMTS_CHECK_LAUNCH();
         {
           ProfScope ps(DMTS_K_GATHER, s);
-          k_sender_gather<<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, dA,
-                                                         W + o_RS);
+          k_sender_gather<DAType<NP>><<<blocks, kWaves * 64, 0, s>>>(nl->offs, nl->nbr, nl->rev,
+                                                                     n, dA, W + o_RS);
         }
         DMTS_CHECK_LAUNCH();
         if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
@@ -716,7 +738,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
           ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
           launch_timed(ps, &k_pair_bwd_mfma<1, NP>, grid_of(&k_pair_bwd_mfma<1, NP>), wg, s, P1,
                        nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_dq1,
-                       nullptr, nullptr, v, cap);
+                       static_cast<DAType<NP>*>(nullptr), nullptr, v, cap);
         }
         DMTS_CHECK_LAUNCH();
         if (ep && ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
@@ -735,7 +757,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
   const dmts_status rs = m->bf16 ? run(std::integral_constant<int, 1>{})
                                  : run(std::integral_constant<int, 3>{});
   if (rs != DMTS_OK) return rs;
-  if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, s);
+  if (energy)
+    return reduce_energy(e_atom, n, sys_offsets, n_sys, energy,
+                         reinterpret_cast<double*>(W + o_part), s);
   return DMTS_OK;
 }
 

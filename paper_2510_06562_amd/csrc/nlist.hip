@@ -20,7 +20,7 @@ namespace dmts {
 
 namespace {
 
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 256;
 constexpr int kMaxCellsPerDim = 64;
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {

@@ -378,7 +378,8 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
   // atom energies [n]
   const size_t N = (size_t)(n + 63) / 64 * 64;
   const size_t need = sizeof(float4) * N * kCap + sizeof(float) * (N * F_S + N) +
-                      sizeof(int32_t) * (N * kCap + N) + 256;
+                      sizeof(int32_t) * (N * kCap + N) + sizeof(double) * energy_partials(n) +
+                      256;
   DMTS_REQUIRE(m->atom_ws.reserve(need, s) == DMTS_OK, DMTS_E_OOM, "small model: workspace");
   char* base = m->atom_ws.as<char>();
   float4* ell_g = reinterpret_cast<float4*>(base);
@@ -386,6 +387,7 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
   float* e_ws = g + N * F_S;
   int32_t* ell_j = reinterpret_cast<int32_t*>(e_ws + N);
   int32_t* ell_n = ell_j + N * kCap;
+  double* e_part = reinterpret_cast<double*>(ell_n + N);   // 8-byte aligned: N % 64 == 0
   float* e_atom = atom_energy ? atom_energy : e_ws;
   SmallParams P{m->p(m->bf16 ? m->o_WbR : m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts),
                 m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
@@ -419,7 +421,7 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
       if (st != DMTS_OK) return st;
     }
   }
-  if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, s);
+  if (energy) return reduce_energy(e_atom, n, sys_offsets, n_sys, energy, e_part, s);
   return DMTS_OK;
 }
 

@@ -85,3 +85,20 @@ def test_batched_equals_per_molecule_loop(which):
         Em, Fm = one(pm, sm)
         assert Em.item() == E[m].item()
         assert torch.equal(Fm.cpu(), F[:, a:b])
+
+
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_single_system_sum_matches_one_system_batch(which):
+    """A large system's energy summed by one work-group per chunk (no system offsets) has
+    the same bits as the per-system reduction of a batch holding only that system, and the
+    forces do not depend on the offsets either."""
+    say(f"energy reduction forms {which}")
+    sy = system("batch256")   # all ~18,000 atoms as one open system (several chunks)
+    pos = api.to_soa(sy.pos)
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    model = api.Model.from_spec(SPECS[which], weights(which))
+    E1, F1 = api.Potential(model, sy.n_atoms, 0.0, 160)(pos, sp)
+    offs = torch.tensor([0, sy.n_atoms], dtype=torch.int32, device="cuda")
+    E2, F2 = api.Potential(model, sy.n_atoms, 0.0, 160, offs)(pos, sp)
+    assert E1.item() == E2.item()
+    assert torch.equal(F1, F2)
