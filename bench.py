@@ -32,14 +32,38 @@ sys.path.insert(0, ROOT)
 METRIC = "DMTS ns/day & atom-steps/s vs 1 fs Verlet, same GPU; force RMSE vs FP64"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
-# Algorithmic FP32 work per real pair of each pair kernel (kernel table):
-# dense contractions at 2 flops per multiply-add plus the per-channel elementwise chain.
-#   pair2_backward: F (4 K + 40)  with K = 32, F = 128  -> 21,504
-#   pair2_forward:  F (2 K + 44)                        -> 13,824
-#   small_backward: F (4 K + 56)  with K = 16, F = 64   ->  7,680 (both directions)
-PAIR_FLOPS = {"pair2_backward": 128 * (4 * 32 + 40), "pair1_backward": 128 * (4 * 32 + 40),
-              "pair2_forward": 128 * (2 * 32 + 44), "pair1_forward": 128 * (2 * 32 + 44),
-              "small_backward": 64 * (4 * 16 + 56), "small_forward": 64 * (2 * 16 + 14)}
+# Algorithmic work per real pair of each pair kernel, at 2 flops per multiply-add and one
+# per add, multiply or transcendental (exp, reciprocal, sine/cosine), counted once per
+# pair even where the kernels split the channels over two waves.
+# Reference model, interaction t, per channel c (F = 128 channels, K = 32 radial terms):
+#   forward:  a = (W_b b)_c + S_c + R_c          2K + 2
+#             SiLU(a) = a / (1 + e^-a)           4   (exp, add, reciprocal, multiply)
+#             m = f_c SiLU(a)                     1
+#             M[y] += m Y_y, 10 components       20
+#   backward: a recomputed (2K + 2), sigma = 1 / (1 + e^-a) (3), s = a sigma (1),
+#             s' = sigma + s (1 - sigma) (3), m = f_c s (1), dm = sum_y D_y Y_y (20),
+#             da = dm f_c s' (2), g' = (W_b b')_c (2K), dm s and da g' accumulated for
+#             the radial force (4), G_k += D_{k+1} m for the nine angular terms (18)
+#   per pair: b_k and b'_k (forward 4K: shift, square, scale, exp; backward 6K), f_c and
+#             f_c' (sine/cosine, forward 4, backward 6), Y (15), the force vector (backward
+#             about 30) -> forward 4K + 30, backward 6K + 50.
+# Fast model (F = 64, K = 16), both message directions of a pair in one pass:
+#   forward:  per channel 2K + 8 (radial, two table terms, SiLU, f_c, sum), per pair 4K + 10
+#   backward: per channel 4K + 30 (radial and its derivative, two SiLU-and-derivative
+#             chains of 7, the two directions' radial-force terms of 6 each, two table
+#             sums), per pair 6K + 30.
+def _ref_fwd(K=32, F=128):
+    return F * (2 * K + 27) + 4 * K + 30         # 11,806
+
+
+def _ref_bwd(K=32, F=128):
+    return F * (4 * K + 54) + 6 * K + 50         # 23,538
+
+
+PAIR_FLOPS = {"pair2_backward": _ref_bwd(), "pair1_backward": _ref_bwd(),
+              "pair2_forward": _ref_fwd(), "pair1_forward": _ref_fwd(),
+              "small_backward": 64 * (4 * 16 + 30) + 6 * 16 + 30,   # 6,142
+              "small_forward": 64 * (2 * 16 + 8) + 4 * 16 + 10}     # 2,634
 
 
 def measured_traffic(workload, precision, kernel):
@@ -89,6 +113,10 @@ def parse():
     ap.add_argument("--nve-ps", type=float, default=0.0,
                     help="instead of the throughput line: run DMTS and Verlet for this many ps "
                          "of NVE dynamics and report the drift of KE + E_reference")
+    ap.add_argument("--gamma", type=float, default=0.0,
+                    help="Langevin friction per fs for both timed runs (0: NVE; the paper's "
+                         "production value is 0.001)")
+    ap.add_argument("--temperature", type=float, default=300.0)
     ap.add_argument("--n-inner", type=int, default=4)
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,6 +295,8 @@ def main():
 
     # ---------------------------------------------------------------- DMTS timed region
     st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_out, n_inner, 64, 128)
+    if args.gamma > 0.0:
+        st.set_thermostat(args.gamma, args.temperature, 2025)
     x, v = api.to_soa(sy.pos), api.to_soa(v0)
     clock_ramp(lambda: st.step(x.clone(), v.clone(), small, large, 4))
     st.reset()
@@ -307,6 +337,8 @@ def main():
     vv = None
     if not args.no_verlet:
         st_v = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_in, 1, 64, 128)
+        if args.gamma > 0.0:
+            st_v.set_thermostat(args.gamma, args.temperature, 2026)
         xv, vvel = api.to_soa(sy.pos), api.to_soa(v0)
         st_v.step(xv, vvel, None, large, max(args.warmup, 1))
         torch.cuda.synchronize()
@@ -374,14 +406,16 @@ def main():
                    "dt_inner_fs": dt_in, "dt_outer_fs": dt_out,
                    "fast_model": "1 interaction, rc 3.5 A, K 16, F 64",
                    "reference_model": "2 interactions, rc 5.2 A, K 32, F 128, l<=2",
-                   "integration": "f64", "ensemble": "NVE",
+                   "integration": "f64",
+                   "ensemble": ("NVE" if args.gamma <= 0.0 else
+                                f"Langevin gamma {args.gamma} /fs, {args.temperature} K"),
                    "mlp_operands": args.precision},
         "atom_steps_per_s": round(atom_steps, 1),
         "verlet_ns_per_day": round(vv["ns_per_day"], 4) if vv else None,
         "verlet_ms_per_step": round(vv["ms_per_step"], 5) if vv else None,
         "speedup_vs_verlet": round(ns_day / vv["ns_per_day"], 3) if vv else None,
         "errors_vs_fp64": errors,
-        "energy_drift_per_atom": (H_end - H_start) / sy.n_atoms,
+        "energy_drift_per_atom": (H_end - H_start) / sy.n_atoms if args.gamma <= 0.0 else None,
         "pairs": {"fast": pairs_small, "reference": pairs_large},
         "roofline": roofline,
         "cpu_baseline": cpu,

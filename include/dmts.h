@@ -172,15 +172,18 @@ dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos
                               float* forces, float* atom_energy, void* stream);
 
 /* ---------------------------------------------------------------- the RESPA loop
- * Algorithm 1 (BAOAB-RESPA with force splitting), with the thermostat of its middle
- * step off (gamma = 0: NVE).  One outer step of length dt_outer:
+ * Algorithm 1 (BAOAB-RESPA with force splitting).  One outer step of length dt_outer:
  *   v += dt/2 (F - F_small)/m;
- *   n_inner times: v += h/2 F_small/m; x += h/2 v; x += h/2 v; F_small <- small(x);
- *                  v += h/2 F_small/m          (h = dt_outer / n_inner);
+ *   n_inner times: v += h/2 F_small/m; x += h/2 v; v <- O_h(v); x += h/2 v;
+ *                  F_small <- small(x); v += h/2 F_small/m   (h = dt_outer / n_inner);
  *   F <- large(x); v += dt/2 (F - F_small)/m.
+ * O_h is the thermostat of Algorithm 1's middle step, the exact Ornstein-Uhlenbeck update
+ * v <- c v + sqrt((1 - c^2) k_B T KAPPA / m) xi with c = exp(-gamma h), off (the
+ * identity: NVE) unless dmts_state_set_thermostat gave gamma > 0.
  * Both forces are evaluated on the first step only and carried between calls
  * afterwards.  With small == NULL the call runs the single-time-step baseline instead:
- * velocity Verlet with the large model at dt_outer (n_inner is ignored).
+ * BAOAB with the large model at dt_outer (velocity Verlet when gamma = 0; n_inner is
+ * ignored).
  *
  * dmts_state_create: n_atoms atoms in a periodic cube `box` (open boundaries: 0.0),
  *   species (device [n_atoms], borrowed for the life of the state), masses per species
@@ -215,6 +218,38 @@ dmts_status dmts_step(dmts_state* st, double* x, double* v, nnp_model* small,
                       void* stream);
 dmts_status dmts_state_reset(dmts_state* st);
 dmts_status dmts_state_fallbacks(dmts_state* st, int64_t* n_calls);
+
+/* Langevin thermostat of Algorithm 1 (the O-step; the paper's production runs use
+ * gamma = 1 ps^-1 = 0.001 fs^-1).  gamma_per_fs >= 0 (0 turns it off), temperature_K >= 0,
+ * seed: the key of the noise.  Resets the O-step counter to 0; DMTS_E_ARG for a negative
+ * or non-finite gamma or temperature.
+ * The k-th O-step of the state (k = 0, 1, ...) gives atom i the standard normals
+ * xi = (sqrt(-2 ln u0) cos(2 pi u1), sqrt(-2 ln u0) sin(2 pi u1), sqrt(-2 ln u2) cos(2 pi u3)),
+ * u_j = (r_j + 1/2) / 2^32, r = Philox4x32-10 (Salmon et al., SC 2011) of counter
+ * (i, k mod 2^32, k div 2^32, 0) and key (seed mod 2^32, seed div 2^32), so that any
+ * implementation of the generator reproduces the noise.  A call redone with exact lists
+ * reuses its O-step numbers.  dmts_state_o_steps returns the number of O-steps taken.
+ */
+dmts_status dmts_state_set_thermostat(dmts_state* st, double gamma_per_fs,
+                                      double temperature_K, uint64_t seed);
+dmts_status dmts_state_o_steps(dmts_state* st, uint64_t* n_o_steps);
+
+/* Force-difference monitor (the paper's guard against holes in the fast model: where
+ * |F - F_small| of an atom exceeds an unphysical threshold, 150 kcal/mol/A = 6.505 eV/A in
+ * the paper, the integrator temporarily reverts to single-time-step integration).
+ * dmts_state_set_fdiff_threshold: eV_per_A > 0 turns the check on (0, the default, off;
+ *   DMTS_E_ARG for a negative or non-finite value).  Every slow kick of dmts_step tests
+ *   |F_i - F_small,i| of each atom; when any atom exceeds the threshold, the call restores
+ *   its starting x, v and carried forces and redoes its n_outer outer steps as
+ *   n_outer * n_inner single-time-step steps of length dt_outer / n_inner with the
+ *   reference model (same O-step numbers; E_small is not refreshed by such a call), and the
+ *   next call evaluates both models afresh.  With the monitor on, every call backs up its
+ *   starting state and reads the device flags once more.
+ * dmts_state_fdiff: the number of calls redone that way, and the largest breaching
+ *   |F - F_small| (eV/A) of the last call that checked (0 if none breached).
+ */
+dmts_status dmts_state_set_fdiff_threshold(dmts_state* st, double eV_per_A);
+dmts_status dmts_state_fdiff(dmts_state* st, int64_t* n_sts_redos, double* last_breach);
 dmts_status dmts_state_forces(dmts_state* st, const float** f_large, const float** f_small);
 dmts_status dmts_state_flags(dmts_state* st, void* stream, uint32_t* host_flags);
 

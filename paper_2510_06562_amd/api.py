@@ -75,6 +75,10 @@ _SIGS = {
     "dmts_step": ([_P, _P, _P, _P, _P, _I32, _P, _P], _I32),
     "dmts_state_reset": ([_P], _I32),
     "dmts_state_fallbacks": ([_P, ctypes.POINTER(_I64)], _I32),
+    "dmts_state_set_thermostat": ([_P, _D, _D, ctypes.c_uint64], _I32),
+    "dmts_state_o_steps": ([_P, ctypes.POINTER(ctypes.c_uint64)], _I32),
+    "dmts_state_set_fdiff_threshold": ([_P, _D], _I32),
+    "dmts_state_fdiff": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_D)], _I32),
     "dmts_state_forces": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I32),
     "dmts_state_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
     "dmts_prof_enable": ([ctypes.c_uint32], _I32),
@@ -314,7 +318,8 @@ class NNPEnergy(torch.autograd.Function):
 
 # ------------------------------------------------------------------ dynamics
 class DMTS:
-    """Algorithm 1 (BAOAB-RESPA, gamma = 0) or, with small=None, velocity Verlet."""
+    """Algorithm 1 (BAOAB-RESPA) or, with small=None, single-time-step BAOAB with the
+    reference model; NVE (velocity Verlet steps) until set_thermostat gives gamma > 0."""
 
     def __init__(self, n_atoms: int, box: float, species: torch.Tensor, masses_by_species,
                  dt_outer: float, n_inner: int, max_nbrs_small: int = 48,
@@ -341,6 +346,30 @@ class DMTS:
 
     def reset(self):
         _check(lib().dmts_state_reset(self._h))
+
+    def set_thermostat(self, gamma_per_fs: float, temperature_K: float, seed: int):
+        """Langevin O-step of Algorithm 1 (gamma 0 = off); resets the O-step counter."""
+        _check(lib().dmts_state_set_thermostat(self._h, float(gamma_per_fs),
+                                               float(temperature_K), int(seed)))
+
+    def set_fdiff_threshold(self, eV_per_A: float):
+        """Redo a call as single-time-step steps when |F - F_small| of an atom exceeds
+        this (0 = off; the paper's threshold is 150 kcal/mol/A = 6.505 eV/A)."""
+        _check(lib().dmts_state_set_fdiff_threshold(self._h, float(eV_per_A)))
+
+    @property
+    def fdiff(self):
+        """(calls redone as single-time-step steps, largest breach of the last call)."""
+        n, b = ctypes.c_int64(), ctypes.c_double()
+        _check(lib().dmts_state_fdiff(self._h, ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    @property
+    def o_steps(self) -> int:
+        """O-steps taken since set_thermostat (the noise counter of the next one)."""
+        k = ctypes.c_uint64()
+        _check(lib().dmts_state_o_steps(self._h, ctypes.byref(k)))
+        return k.value
 
     @property
     def fallbacks(self) -> int:

@@ -125,14 +125,19 @@ struct Model {
 // A force evaluation that is followed by such a program applies it to atom i as soon as
 // F_i is final (the epilogue of its last kernel); the positions it moves are read by the
 // next evaluation only.
-enum IntegOp : int { kKickSlow = 0, kKickFast = 1, kKickLarge = 2, kDrift = 3 };
+enum IntegOp : int { kKickSlow = 0, kKickFast = 1, kKickLarge = 2, kDrift = 3, kThermo = 4 };
 constexpr int kMaxOps = 8;
 constexpr uint32_t kFlagStale = 0x100u;   // internal: shared list no longer complete
+constexpr uint32_t kFlagFdiff = 0x200u;   // internal: |F - F_small| above the threshold
 
+// Kick: v += c F / m.  Drift: x += c v.  Thermo: the O-step of Algorithm 1, the exact
+// Ornstein-Uhlenbeck update v <- e^(-gamma h) v + sd_z xi over the inner step h, xi the
+// normals of the state's O-step number ctr.
 struct Prog {
   int nops;
   int op[kMaxOps];
   double c[kMaxOps];
+  uint64_t ctr[kMaxOps];
 };
 
 struct Epilogue {
@@ -146,15 +151,80 @@ struct Epilogue {
   const double* x_ref;       // positions of the shared list's build (displacement check) or null
   double max_disp2;
   uint32_t* flags;
+  // O-step: velocity decay e^(-gamma h), per-species noise scale
+  // sqrt((1 - decay^2) k_B T KAPPA / m), Philox key words
+  double o_decay;
+  double o_sd[8];
+  uint32_t o_key[2];
+  // force-difference monitor of the slow kicks: squared threshold (0: off) and the word
+  // that keeps the largest breaching |F - F_small| (float bits, eV/A)
+  double fdiff_thr2;
+  uint32_t* fdiff_max;
   hipEvent_t wait = nullptr;   // host side: the launch that runs the program waits for it
 };
 
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC 2011): each round maps the
+// counter (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)) with M0 = 0xD2511F53, M1 = 0xCD9E8D57; the key is bumped by the Weyl
+// constants 0x9E3779B9, 0xBB67AE85 before every round after the first.
+__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Standard normal deviate d (0, 1, 2 = x, y, z) of atom i at O-step k: the Philox words
+// r of counter (i, k mod 2^32, k div 2^32, 0) and the key, u_j = (r_j + 1/2) 2^-32, and
+// Box-Muller: x = sqrt(-2 ln u0) cos(2 pi u1), y = sqrt(-2 ln u0) sin(2 pi u1),
+// z = sqrt(-2 ln u2) cos(2 pi u3).
+__device__ inline double o_normal(int i, uint64_t k, const uint32_t (&key)[2], int d) {
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)k, (uint32_t)(k >> 32), 0u};
+  philox4x32_10(c, key[0], key[1]);
+  const double ua = ((double)(d < 2 ? c[0] : c[2]) + 0.5) * 0x1p-32;
+  const double ub = ((double)(d < 2 ? c[1] : c[3]) + 0.5) * 0x1p-32;
+  const double rad = sqrt(-2.0 * log(ua));
+  const double a = 6.283185307179586 * ub;
+  return rad * (d == 1 ? sin(a) : cos(a));
+}
+
 // 1 / m of species z, from the kernel argument by selection (no dynamic indexing).
+inline bool has_thermo(const Prog& p) {
+  for (int k = 0; k < p.nops; ++k)
+    if (p.op[k] == kThermo) return true;
+  return false;
+}
+
 __device__ inline double inv_mass_of(const Epilogue& E, int z) {
   double im = E.inv_mass[0];
 #pragma unroll
   for (int k = 1; k < 8; ++k) im = z == k ? E.inv_mass[k] : im;
   return im;
+}
+__device__ inline double o_sd_of(const Epilogue& E, int z) {
+  double sd = E.o_sd[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) sd = z == k ? E.o_sd[k] : sd;
+  return sd;
+}
+
+// Slow kick of an atom with |F - F_small|^2 = df2: a breach of the threshold raises the
+// internal flag and records the size (rare, so the common path has no atomics).
+__device__ inline void fdiff_check(const Epilogue& E, double df2) {
+  if (E.fdiff_thr2 > 0.0 && df2 > E.fdiff_thr2) {
+    atomicOr(E.flags, kFlagFdiff);
+    atomicMax(E.fdiff_max, __float_as_uint((float)sqrt(df2)));
+  }
 }
 
 __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
@@ -174,8 +244,13 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) xx[d] = xx[d] + c * vv[d];
+    } else if (op == kThermo) {
+      const double sd = o_sd_of(E, E.species[i]);
+      for (int d = 0; d < 3; ++d)
+        vv[d] = E.o_decay * vv[d] + sd * o_normal(i, E.prog.ctr[k], E.o_key, d);
     } else {
       const double ci = c * im;
+      double df2 = 0.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double f;
@@ -183,7 +258,9 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
         else if (op == kKickFast) f = (double)E.Fs[(size_t)d * n + i];
         else f = (double)E.FL[(size_t)d * n + i];
         vv[d] = vv[d] + ci * f;
+        df2 += f * f;
       }
+      if (op == kKickSlow) fdiff_check(E, df2);
     }
   }
   bool bad = false;
@@ -231,7 +308,9 @@ __device__ inline CoordIn prefetch_coord(const Epilogue& E, int i, int n, int d,
 }
 
 // Runs the program on lanes 0..2 (coordinate d = lane) of the calling wave, which must all
-// be active; writes x, v and raises the flags exactly as apply_atom does.
+// be active; writes x, v and raises the flags exactly as apply_atom does.  Kicks and
+// drifts only: a program with an O-step runs through apply_program (has_thermo), which
+// keeps the registers of the Box-Muller deviates out of the kernels that fuse this.
 __device__ inline void apply_coords(const Epilogue& E, int i, int n, int lane, const CoordIn& c,
                                     float fresh, bool fresh_small) {
   double vv = c.v, xx = c.x;
@@ -249,6 +328,11 @@ __device__ inline void apply_coords(const Epilogue& E, int i, int n, int lane, c
       const double ci = cc * im;
       const double f = op == kKickSlow ? fl - fs : op == kKickFast ? fs : fl;
       vv = vv + ci * f;
+      if (op == kKickSlow && E.fdiff_thr2 > 0.0) {
+        const double f2 = lane < 3 ? f * f : 0.0;
+        const double df2 = f2 + __shfl(f2, 1, 64) + __shfl(f2, 2, 64);
+        if (lane == 0) fdiff_check(E, df2);
+      }
     }
   }
   const int d = lane;

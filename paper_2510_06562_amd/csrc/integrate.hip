@@ -20,6 +20,8 @@
 // launch checks that bound on the device.  If it is ever exceeded, the call is rolled back
 // to its starting state and repeated with a fresh list for every fast evaluation.
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -31,6 +33,7 @@ namespace {
 // 1 eV / (A amu) in A / fs^2 from the CODATA 2018 elementary charge and atomic mass
 // constant.
 constexpr double kKappa = 1.602176634e-19 / (1.0e-10 * 1.66053906660e-27) * 1.0e-20;
+constexpr double kBoltzmann = 8.617333262e-5;   // eV / K (CODATA 2018)
 
 constexpr double kMinSkin = 1.0;           // A between the fast cutoff and the shared list
 
@@ -126,6 +129,15 @@ struct State {
   double* mass = nullptr;   // [Z]
   double* inv_mass = nullptr;
   double host_inv_mass[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the same, for kernel arguments
+  double host_mass[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // Langevin O-step (gamma = 0: off, NVE); o_count numbers the state's O-steps
+  double gamma = 0.0, temperature = 0.0;
+  uint64_t seed = 0, o_count = 0;
+  // force-difference monitor (0: off) and the calls it had redone as single-time-step runs
+  double fdiff_thr = 0.0;
+  int64_t n_sts_redos = 0;
+  uint32_t* fdiff_max = nullptr;   // device word: largest breaching |F - F_small| (float bits)
+  float last_fdiff = 0.f;
   double* e_models = nullptr;   // {E_large, E_small}
   double* ke_part = nullptr;    // per-chunk kinetic energy sums
   uint32_t* flags = nullptr;
@@ -148,6 +160,7 @@ struct Item {
   int op_or_kind;
   double c;       // op: coefficient
   bool want_e;    // eval: sum the energies (last evaluation of its model in the call)
+  uint64_t ctr;   // O-step: its number
 };
 
 struct Runner {
@@ -163,8 +176,12 @@ struct Runner {
   Model* large = nullptr;
   std::vector<Item> sched;
 
-  void op(int o, double c) { sched.push_back(Item{false, o, c, false}); }
-  void eval(int kind, bool want_e) { sched.push_back(Item{true, kind, 0.0, want_e}); }
+  // O-step constants of this call
+  double o_decay = 1.0;
+  double o_sd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  void op(int o, double c, uint64_t ctr = 0) { sched.push_back(Item{false, o, c, false, ctr}); }
+  void eval(int kind, bool want_e) { sched.push_back(Item{true, kind, 0.0, want_e, 0}); }
 
   Epilogue epilogue(const Prog& p) const {
     Epilogue e{};
@@ -178,6 +195,12 @@ struct Runner {
     e.x_ref = shared ? st->x_ref : nullptr;
     e.max_disp2 = max_disp2;
     e.flags = st->flags;
+    e.o_decay = o_decay;
+    for (int z = 0; z < 8; ++z) e.o_sd[z] = o_sd[z];
+    e.o_key[0] = (uint32_t)st->seed;
+    e.o_key[1] = (uint32_t)(st->seed >> 32);
+    e.fdiff_thr2 = st->fdiff_thr * st->fdiff_thr;
+    e.fdiff_max = st->fdiff_max;
     return e;
   }
   // The model energies are only reported for the positions a call ends at, so an
@@ -225,6 +248,7 @@ struct Runner {
       if (p.nops == kMaxOps) break;
       p.op[p.nops] = sched[k].op_or_kind;
       p.c[p.nops] = sched[k].c;
+      p.ctr[p.nops] = sched[k].ctr;
       ++p.nops;
       ++k;
     }
@@ -281,18 +305,36 @@ struct Runner {
 };
 
 // Algorithm 1 (or velocity Verlet when small is NULL) for n_outer outer steps.
-dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_outer) {
+// The O-step over time h: decay e^(-gamma h) and the per-species noise scale
+// sqrt((1 - decay^2) k_B T KAPPA / m) (Algorithm 1's thermostat, exact Ornstein-Uhlenbeck).
+void o_constants(const State* st, Runner& R, double h) {
+  R.o_decay = std::exp(-st->gamma * h);
+  for (int z = 0; z < 8; ++z)
+    R.o_sd[z] = st->host_mass[z] > 0.0
+                    ? std::sqrt((1.0 - R.o_decay * R.o_decay) * kBoltzmann * st->temperature *
+                                kKappa / st->host_mass[z])
+                    : 0.0;
+}
+
+// n_outer steps of Algorithm 1, or with small == NULL n_outer single-time-step steps of
+// length dt_sts (the state's dt when <= 0).
+dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_outer,
+                      double dt_sts = 0.0) {
   const double kappa = kKappa;
   R.small = small;
   R.large = large;
   R.sched.clear();
-  const double dt = st->dt;
+  const double dt = small || dt_sts <= 0.0 ? st->dt : dt_sts;
+  const bool thermo = st->gamma > 0.0;
   if (!small) {
-    // single-time-step baseline: velocity Verlet (BAOAB with the O-step off)
+    // single-time-step baseline: BAOAB with the reference model (velocity Verlet when
+    // gamma = 0)
+    o_constants(st, R, dt);
     if (st->first) R.eval(kEvalPlain, n_outer == 0);
     for (int o = 0; o < n_outer; ++o) {
       R.op(kKickLarge, 0.5 * dt * kappa);
       R.op(kDrift, 0.5 * dt);
+      if (thermo) R.op(kThermo, 0.0, st->o_count++);
       R.op(kDrift, 0.5 * dt);
       R.eval(kEvalPlain, o == n_outer - 1);
       R.op(kKickLarge, 0.5 * dt * kappa);
@@ -300,6 +342,7 @@ dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_ou
   } else {
     const int n = st->n_inner;
     const double h_in = dt / n;
+    o_constants(st, R, h_in);
     if (st->first) {
       R.eval(kEvalLarge, n_outer == 0);
       R.eval(kEvalSmall, n_outer == 0);
@@ -310,6 +353,7 @@ dmts_status run_steps(State* st, Runner& R, Model* small, Model* large, int n_ou
       for (int k = 0; k < n; ++k) {
         R.op(kKickFast, 0.5 * h_in * kappa);
         R.op(kDrift, 0.5 * h_in);
+        if (thermo) R.op(kThermo, 0.0, st->o_count++);
         R.op(kDrift, 0.5 * h_in);
         R.eval(kEvalSmall, last && k == n - 1);
         R.op(kKickFast, 0.5 * h_in * kappa);
@@ -375,6 +419,7 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     hm[z] = host_mass_by_species[z];
     him[z] = 1.0 / host_mass_by_species[z];
     st->host_inv_mass[z] = him[z];
+    if (z < 8) st->host_mass[z] = hm[z];
   }
   hipError_t e = hipSuccess;
   if (r == DMTS_OK) {
@@ -388,6 +433,8 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     if (e == hipSuccess)
       e = hipMalloc(&st->ke_part, sizeof(double) * ((size_t)n_atoms / dmts::kKeChunk + 1));
     if (e == hipSuccess) e = hipMalloc(&st->flags, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&st->fdiff_max, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(st->fdiff_max, 0, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(st->mass, hm, sizeof(hm), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(st->inv_mass, him, sizeof(him), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(st->e_models, 0, sizeof(double) * 4);
@@ -428,6 +475,7 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   (void)hipFree(st->inv_mass);
   (void)hipFree(st->e_models);
   (void)hipFree(st->ke_part);
+  (void)hipFree(st->fdiff_max);
   (void)hipFree(st->flags);
   delete st;
 }
@@ -436,6 +484,48 @@ extern "C" dmts_status dmts_state_reset(dmts_state* h) {
   State* st = reinterpret_cast<State*>(h);
   DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_reset: null state");
   st->first = true;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_set_thermostat(dmts_state* h, double gamma_per_fs,
+                                                 double temperature_K, uint64_t seed) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_set_thermostat: null state");
+  DMTS_REQUIRE(std::isfinite(gamma_per_fs) && gamma_per_fs >= 0.0, DMTS_E_ARG,
+               "dmts_state_set_thermostat: gamma must be finite and >= 0, got %g", gamma_per_fs);
+  DMTS_REQUIRE(std::isfinite(temperature_K) && temperature_K >= 0.0, DMTS_E_ARG,
+               "dmts_state_set_thermostat: temperature must be finite and >= 0, got %g",
+               temperature_K);
+  st->gamma = gamma_per_fs;
+  st->temperature = temperature_K;
+  st->seed = seed;
+  st->o_count = 0;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_set_fdiff_threshold(dmts_state* h, double eV_per_A) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_set_fdiff_threshold: null state");
+  DMTS_REQUIRE(std::isfinite(eV_per_A) && eV_per_A >= 0.0, DMTS_E_ARG,
+               "dmts_state_set_fdiff_threshold: threshold must be finite and >= 0, got %g",
+               eV_per_A);
+  st->fdiff_thr = eV_per_A;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_fdiff(dmts_state* h, int64_t* n_sts_redos,
+                                        double* last_breach) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st && n_sts_redos && last_breach, DMTS_E_ARG, "dmts_state_fdiff: null argument");
+  *n_sts_redos = st->n_sts_redos;
+  *last_breach = st->last_fdiff;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_o_steps(dmts_state* h, uint64_t* n_o_steps) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st && n_o_steps, DMTS_E_ARG, "dmts_state_o_steps: null argument");
+  *n_o_steps = st->o_count;
   return DMTS_OK;
 }
 
@@ -500,9 +590,15 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
       R.max_disp2 = half_skin * half_skin;
     }
   }
-  // starting state, for the rare roll-back of a shared-list call
+  // starting state, for the rare roll-back of a shared-list call or of a call whose
+  // force difference breached the monitor's threshold
   const bool first0 = st->first;
-  if (R.shared) {
+  const uint64_t o_count0 = st->o_count;
+  const bool monitor = small && st->fdiff_thr > 0.0;
+  if (monitor) {
+    if ((r = dmts::fill_u32(st->fdiff_max, 0u, 1, s)) != DMTS_OK) return r;
+  }
+  if (R.shared || monitor) {
     double* b = st->bak;
     dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(x, b, n3);
     dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(v, b + n3, n3);
@@ -514,12 +610,23 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
     DMTS_CHECK_LAUNCH();
   }
   if ((r = dmts::run_steps(st, R, small, large, n_outer)) != DMTS_OK) return r;
-  if (R.shared) {
+  if (R.shared || monitor) {
     uint32_t f = 0;
     DMTS_HIP(hipMemcpyAsync(&f, st->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (monitor) {
+      uint32_t fm = 0;
+      DMTS_HIP(hipMemcpyAsync(&fm, st->fdiff_max, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      DMTS_HIP(hipStreamSynchronize(s));
+      float fv;
+      std::memcpy(&fv, &fm, sizeof(fv));
+      st->last_fdiff = fv;
+    }
     DMTS_HIP(hipStreamSynchronize(s));
-    if (f & dmts::kFlagStale) {
-      // an atom moved beyond the shared list's skin: restore and redo with exact lists
+    if (f & (dmts::kFlagStale | dmts::kFlagFdiff)) {
+      // an atom moved beyond the shared list's skin: restore and redo with exact lists;
+      // |F - F_small| above the threshold: restore and redo as single-time-step steps of
+      // the inner length with the reference model (the paper's temporary reversion)
+      const bool sts = (f & dmts::kFlagFdiff) != 0;
       double* b = st->bak;
       dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(b, x, n3);
       dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(b + n3, v, n3);
@@ -530,12 +637,22 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
       }
       DMTS_CHECK_LAUNCH();
       st->first = first0;
-      if ((r = dmts::fill_u32(st->flags, f & ~dmts::kFlagStale, 1, s)) != DMTS_OK) return r;
+      st->o_count = o_count0;   // the same thermostat noise
+      if ((r = dmts::fill_u32(st->flags, f & ~(dmts::kFlagStale | dmts::kFlagFdiff), 1, s)) !=
+          DMTS_OK)
+        return r;
       dmts::Runner E{st, x, v, s};
-      ++st->n_fallbacks;
-      if ((r = dmts::run_steps(st, E, small, large, n_outer)) != DMTS_OK) return r;
-      // the exact lists of this call are not the shared list: the next call starts by
-      // evaluating both models (building a fresh shared list); the forces are the same
+      if (sts) {
+        ++st->n_sts_redos;
+        if ((r = dmts::run_steps(st, E, nullptr, large, n_outer * st->n_inner,
+                                 st->dt / st->n_inner)) != DMTS_OK)
+          return r;
+      } else {
+        ++st->n_fallbacks;
+        if ((r = dmts::run_steps(st, E, small, large, n_outer)) != DMTS_OK) return r;
+      }
+      // the exact lists of this call are not the shared list (and a single-time-step redo
+      // leaves F_small behind): the next call starts by evaluating both models
       st->first = true;
     }
   }

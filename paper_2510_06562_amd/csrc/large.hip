@@ -360,7 +360,6 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const int i = ag * kWaves + w;
   if (i >= n) continue;
   float* sd = sD[w];
-  float* vh = v + (size_t)half * 3 * cap;   // this half's share of v_ij
   const int zi_s = species[i];
   // D[y][c]: dE/dq folded with dq/dM, off-diagonal M2 components doubled, so that
   // dm = sum_y Y[y] D[y]
@@ -542,14 +541,16 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       const float vx = rho * gv.x * ir + irc * ax;
       const float vy = rho * gv.y * ir + irc * ay;
       const float vz = rho * gv.z * ir + irc * az;
+      // this half's share of v_ij: slot [p][half] of the [cap][2] float4 array
+      float4* vh = reinterpret_cast<float4*>(v) + 2 * (size_t)p + half;
       if (LAYER == 2) {
-        vh[p] = vx;
-        vh[cap + p] = vy;
-        vh[2 * cap + p] = vz;
+        *vh = make_float4(vx, vy, vz, 0.f);
       } else {
-        vh[p] += vx;
-        vh[cap + p] += vy;
-        vh[2 * cap + p] += vz;
+        float4 t = *vh;
+        t.x += vx;
+        t.y += vy;
+        t.z += vz;
+        *vh = t;
       }
     }
   }
@@ -622,14 +623,17 @@ k_force_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr
   if (has_ep && lane < 3) ein = prefetch_coord(E, i, n, lane, fresh_small);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   const int row0 = offs[i], row1 = offs[i + 1];
+  const float4* v4 = reinterpret_cast<const float4*>(v);   // [cap][2 halves]
   for (int p = row0 + lane; p < row1; p += 64) {
     if (nbr[p] < 0) continue;
     const int q = rev[p];
     if (q < 0) continue;
-    const float* v1 = v + 3 * cap;
-    fx += (v[p] + v1[p]) - (v[q] + v1[q]);
-    fy += (v[cap + p] + v1[cap + p]) - (v[cap + q] + v1[cap + q]);
-    fz += (v[2 * cap + p] + v1[2 * cap + p]) - (v[2 * cap + q] + v1[2 * cap + q]);
+    // both halves of a slot share one 32-byte sector: one random access per pair
+    const float4 a0 = v4[2 * (size_t)p], a1 = v4[2 * (size_t)p + 1];
+    const float4 b0 = v4[2 * (size_t)q], b1 = v4[2 * (size_t)q + 1];
+    fx += (a0.x + a1.x) - (b0.x + b1.x);
+    fy += (a0.y + a1.y) - (b0.y + b1.y);
+    fz += (a0.z + a1.z) - (b0.z + b1.z);
   }
   fx = wave_sum(fx);
   fy = wave_sum(fy);
@@ -666,7 +670,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                "large model: atom workspace");
   const int64_t cap = nl->max_pairs;
   if (forces) {
-    DMTS_REQUIRE(m->pair_ws.reserve(sizeof(float) * (size_t)cap * (F + 6), s) == DMTS_OK,
+    DMTS_REQUIRE(m->pair_ws.reserve(sizeof(float) * (size_t)cap * (F + 8), s) == DMTS_OK,
                  DMTS_E_OOM, "large model: pair workspace");
   }
   float* W = m->atom_ws.as<float>();
@@ -716,7 +720,8 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
                             forces != nullptr, s)) != DMTS_OK) return st;
       if (forces) {
-        // pair workspace: dA [cap][F] (FP32 or bfloat16), then v [2][3][cap] FP32
+        // pair workspace: dA [cap][F] (FP32 or bfloat16), then v [cap][2] float4 (the
+        // two channel halves' partial dE/dd_ij of a slot side by side)
         DAType<NP>* dA = m->pair_ws.as<DAType<NP>>();
         float* v = m->pair_ws.as<float>() + (size_t)cap * F;
         {
@@ -741,14 +746,18 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                        static_cast<DAType<NP>*>(nullptr), nullptr, v, cap);
         }
         DMTS_CHECK_LAUNCH();
+        // the integrator program runs in the force gather's epilogue, or (with an O-step)
+        // as a launch of its own right after it
+        const bool fuse = ep && !has_thermo(ep->prog);
         if (ep && ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
         {
           ProfScope ps(DMTS_K_GATHER, s);
           k_force_gather<<<blocks, 256, 0, s>>>(nl->offs, nl->nbr, nl->rev, n, v, cap, forces,
-                                                ep ? *ep : Epilogue{}, ep != nullptr,
-                                                ep && forces == ep->Fs);
+                                                fuse ? *ep : Epilogue{}, fuse,
+                                                fuse && forces == ep->Fs);
         }
         DMTS_CHECK_LAUNCH();
+        if (ep && !fuse && (st = apply_program(*ep, n, s)) != DMTS_OK) return st;
       }
     }
 
