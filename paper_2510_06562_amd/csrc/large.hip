@@ -565,15 +565,17 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
 }
 
 // S_j = sum over the rows of j of dA at the reverse positions (the sender sums), in FP32.
-// One wave per atom, lane l owns channels 2l and 2l+1.  The row's reverse positions are
-// read 64 at a time (one per lane) and broadcast, so the dA rows of eight pairs are in
-// flight at once; they are added in row order.
-__device__ __forceinline__ float2 load_da2(const float* dA, size_t k) {
-  return reinterpret_cast<const float2*>(dA)[k];
+// One wave per atom; each load instruction fetches two dA rows, lanes 0-31 the first and
+// lanes 32-63 the second, four channels per lane (16 or 8 bytes).  The row's reverse
+// positions are read 64 at a time (one per lane) and broadcast; eight row pairs are in
+// flight at once.  Each half adds its rows (even, odd positions) in row order, then the
+// two halves are added.
+__device__ __forceinline__ float4 load_da4(const float* dA, size_t k) {
+  return *reinterpret_cast<const float4*>(dA + k);
 }
-__device__ __forceinline__ float2 load_da2(const __bf16* dA, size_t k) {
-  const bf16x2 t = reinterpret_cast<const bf16x2*>(dA)[k];
-  return make_float2((float)t[0], (float)t[1]);
+__device__ __forceinline__ float4 load_da4(const __bf16* dA, size_t k) {
+  const bf16x4 t = *reinterpret_cast<const bf16x4*>(dA + k);
+  return make_float4((float)t[0], (float)t[1], (float)t[2], (float)t[3]);
 }
 
 template <typename T>
@@ -583,29 +585,39 @@ k_sender_gather(const int32_t* __restrict__ offs, const int32_t* __restrict__ nb
                 float* __restrict__ RS) {
   constexpr int kU = 8;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = lane >> 5, c0 = 4 * (lane & 31);
   const int i = blockIdx.x * kWaves + w;
   if (i >= n) return;
-  float2 s = make_float2(0.f, 0.f);
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int base = row0; base < row1; base += 64) {
     const int p = base + lane;
     const int q = (p < row1 && nbr[p] >= 0) ? rev[p] : -1;
     const int m = min(64, row1 - base);
-    for (int k = 0; k < m; k += kU) {
-      float2 t[kU];
+    // k < m <= 64 steps by 16, so k + 2 u + 1 <= 63
+    for (int k = 0; k < m; k += 2 * kU) {
+      float4 t[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int qq = __builtin_amdgcn_readlane(q, k + u);
-        t[u] = qq >= 0 ? load_da2(dA, (size_t)qq * (F_L / 2) + lane) : make_float2(0.f, 0.f);
+        const int qa = __builtin_amdgcn_readlane(q, k + 2 * u);
+        const int qb = __builtin_amdgcn_readlane(q, k + 2 * u + 1);
+        const int qq = h ? qb : qa;
+        t[u] = qq >= 0 ? load_da4(dA, (size_t)qq * F_L + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         s.x += t[u].x;
         s.y += t[u].y;
+        s.z += t[u].z;
+        s.w += t[u].w;
       }
     }
   }
-  reinterpret_cast<float2*>(RS + (size_t)i * 2 * F_L + F_L)[lane] = s;
+  s.x += __shfl_xor(s.x, 32, 64);
+  s.y += __shfl_xor(s.y, 32, 64);
+  s.z += __shfl_xor(s.z, 32, 64);
+  s.w += __shfl_xor(s.w, 32, 64);
+  if (h == 0) *reinterpret_cast<float4*>(RS + (size_t)i * 2 * F_L + F_L + c0) = s;
 }
 
 }  // namespace
