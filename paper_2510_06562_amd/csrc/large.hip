@@ -215,10 +215,12 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
 }
 
 // Both pair kernels are latency bound at low occupancy: the registers of the forward kernel
-// are capped so that four waves share a SIMD, those of the reverse kernel for three (as
-// many work-groups per CU as their LDS allows).
+// are capped so that four waves share a SIMD (five in the BF16 form, at the cost of a few
+// spilled registers outside the tile loop, measured faster), those of the reverse kernel
+// for three (four for the BF16 form of interaction 1, which fits 128 registers).
 template <int LAYER, int NP>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kWaves * 64)
+__attribute__((amdgpu_waves_per_eu(NP == 1 ? 5 : 4)))
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
@@ -337,7 +339,8 @@ constexpr int kLdR = 68;
 constexpr bool kAhead = true;
 
 template <int LAYER, int NP>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kWaves * 64)
+__attribute__((amdgpu_waves_per_eu(NP == 1 && LAYER == 1 ? 4 : 3)))
 k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, const float* __restrict__ Mall,
