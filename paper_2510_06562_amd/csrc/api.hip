@@ -67,14 +67,22 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
-ProfScope::ProfScope(int kernel_class, hipStream_t stream) : kid(kernel_class), s(stream) {
+ProfScope::ProfScope(int kernel_class, hipStream_t stream, bool packet_launch)
+    : kid(kernel_class), s(stream) {
   if (!((g_prof_mask >> kid) & 1u)) return;
   a = get_event();
-  if (a) (void)hipEventRecord(a, s);
+  if (a && !packet_launch) {
+    (void)hipEventRecord(a, s);
+    started = true;
+  }
 }
 
 ProfScope::~ProfScope() {
   if (!a) return;
+  if (!started) {   // a packet launch that could not take the events: nothing timed
+    g_event_pool.push_back(a);
+    return;
+  }
   if (!b) {
     b = get_event();
     if (!b) return;
@@ -89,6 +97,7 @@ bool ProfScope::packet(hipEvent_t& start, hipEvent_t& stop) {
   if (!b) return false;
   start = a;
   stop = b;
+  started = true;
   return true;
 }
 

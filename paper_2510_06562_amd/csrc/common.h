@@ -407,7 +407,10 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr;
   hipEvent_t b = nullptr;   // set when the launch itself records the stop event
-  ProfScope(int kernel_class, hipStream_t stream);
+  bool started = false;     // a is (or will be, by the dispatch) recorded
+  // packet_launch: the scope holds one launch_timed launch, whose dispatch records both
+  // events (no marker of its own on the stream, which would stall the queue)
+  ProfScope(int kernel_class, hipStream_t stream, bool packet_launch = false);
   ~ProfScope();
   // When this class is timed: start and stop events for a launch that records them in its
   // own dispatch (the kernel's start and end), instead of around it.

@@ -720,14 +720,14 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       auto grid_of = [&](auto kernel) { return dim3(pgrid(reinterpret_cast<const void*>(kernel))); };
       const dim3 wg(kWaves * 64);
       {
-        ProfScope ps(DMTS_K_PAIR1_FORWARD, s);
+        ProfScope ps(DMTS_K_PAIR1_FORWARD, s, true);
         launch_timed(ps, &k_pair_fwd_mfma<1, NP>, grid_of(&k_pair_fwd_mfma<1, NP>), wg, s, P1,
                      nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_q1);
       }
       DMTS_CHECK_LAUNCH();
       if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
       {
-        ProfScope ps(DMTS_K_PAIR2_FORWARD, s);
+        ProfScope ps(DMTS_K_PAIR2_FORWARD, s, true);
         launch_timed(ps, &k_pair_fwd_mfma<2, NP>, grid_of(&k_pair_fwd_mfma<2, NP>), wg, s, P2,
                      nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_q2);
       }
@@ -740,7 +740,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         DAType<NP>* dA = m->pair_ws.as<DAType<NP>>();
         float* v = m->pair_ws.as<float>() + (size_t)cap * F;
         {
-          ProfScope ps(DMTS_K_PAIR2_BACKWARD, s);
+          ProfScope ps(DMTS_K_PAIR2_BACKWARD, s, true);
           launch_timed(ps, &k_pair_bwd_mfma<2, NP>, grid_of(&k_pair_bwd_mfma<2, NP>), wg, s, P2,
                        nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_dq2, dA,
                        W + o_RS, v, cap);
@@ -755,7 +755,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
           return st;
         {
-          ProfScope ps(DMTS_K_PAIR1_BACKWARD, s);
+          ProfScope ps(DMTS_K_PAIR1_BACKWARD, s, true);
           launch_timed(ps, &k_pair_bwd_mfma<1, NP>, grid_of(&k_pair_bwd_mfma<1, NP>), wg, s, P1,
                        nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_dq1,
                        static_cast<DAType<NP>*>(nullptr), nullptr, v, cap);

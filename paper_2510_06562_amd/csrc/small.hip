@@ -397,14 +397,14 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
     auto run = [&](auto bf_tag) {
       constexpr bool BF = decltype(bf_tag)::value;
       {
-        ProfScope ps(DMTS_K_SMALL_FORWARD, s);
+        ProfScope ps(DMTS_K_SMALL_FORWARD, s, true);
         const int blocks = m->launch_grid(
             natural, resident_groups(reinterpret_cast<const void*>(&k_small_fwd<BF>), kWaves * 64));
         launch_timed(ps, &k_small_fwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, nl->offs,
                      nl->nbr, pos, species, n, box, e_atom, g, ell_j, ell_g, ell_n, nl->flags);
       }
       if (hipPeekAtLastError() != hipSuccess || !forces) return;
-      ProfScope ps(DMTS_K_SMALL_BACKWARD, s);
+      ProfScope ps(DMTS_K_SMALL_BACKWARD, s, true);
       const int blocks = m->launch_grid(
           natural, resident_groups(reinterpret_cast<const void*>(&k_small_bwd<BF>), kWaves * 64));
       launch_timed(ps, &k_small_bwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, species, n, g,
