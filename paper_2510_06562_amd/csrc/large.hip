@@ -133,8 +133,9 @@ __device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float 
                                              float inv_s2, float (&bk)[8]) {
   if (NP == 1) {
     const float x0 = r - sigma * k0;
-    float b = valid ? __expf(-0.5f * x0 * x0 * inv_s2) : 0.f;
-    float rho = valid ? __expf(x0 * (sigma * inv_s2) - 0.5f) : 0.f;
+    // invalid pairs: exponent -1e30 gives 0 without a branch around the exponential
+    float b = __expf(valid ? -0.5f * x0 * x0 * inv_s2 : -1e30f);
+    float rho = __expf(valid ? x0 * (sigma * inv_s2) - 0.5f : -1e30f);
     bk[0] = b;
 #pragma unroll
     for (int e = 1; e < 8; ++e) {
@@ -147,7 +148,7 @@ __device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float 
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const float x = r - sigma * (k0 + e);
-    bk[e] = valid ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+    bk[e] = __expf(valid ? -0.5f * x * x * inv_s2 : -1e30f);
   }
 }
 
@@ -220,13 +221,13 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
 // for three (four for the BF16 form of interaction 1, which fits 128 registers).
 template <int LAYER, int NP>
 __global__ void __launch_bounds__(kWaves * 64)
-__attribute__((amdgpu_waves_per_eu(NP == 1 ? 5 : 4)))
+__attribute__((amdgpu_waves_per_eu(NP == 1 && LAYER == 1 ? 5 : 4)))
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
   __shared__ __bf16 sW[NP * (F_L / 2) * K_L];   // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
-  __shared__ float sM[kWaves][NMOM * kLdM];
+  __shared__ float sM[kWaves][16 * kLdM];   // rows 10..15 (zero moments) unused
   const int half = blockIdx.x & 1, hb = 4 * half;   // hb: first channel block of the half
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
@@ -263,6 +264,8 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     int jj[4], zz[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      // everything computed unconditionally and selected, so that the four geometry
+      // loads are issued together (a branch per pair would serialize them)
       const int p = t0 + 4 * g + r;
       const float4 gv = geo[p];
       const int j = nbr[p];
@@ -271,7 +274,10 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       cutoff_fn(gv.w, pi_rc, v, fc[r], dfc);
       jj[r] = v ? j : -1;
       zz[r] = LAYER == 1 ? species[v ? j : i] : 0;
-      yop[r] = v ? ycomp(cl, gv.x * irc, gv.y * irc, gv.z * irc) : (cl == 0 ? 1.f : 0.f);
+      // an invalid pair has u = 0, whose components are Y = (1, 0, ..., 0)
+      const float ux = v ? gv.x * irc : 0.f, uy = v ? gv.y * irc : 0.f;
+      const float uz = v ? gv.z * irc : 0.f;
+      yop[r] = ycomp(cl, ux, uy, uz);
     }
     // sender terms of the lane's sixteen (pair, channel) values, all requested before the
     // products so that their latencies overlap
@@ -305,15 +311,13 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         Mt[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(yop[s], mv[s], Mt[b], 0, 0, 0);
     }
   }
-  // M^T rows y = 4 g + r (y < 10) -> LDS, then moments and invariants per channel
+  // M^T rows y = 4 g + r -> LDS (all sixteen, without a branch; rows 10..15 are not
+  // read), then moments and invariants per channel
   float* sm = sM[w];
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int y = 4 * g + r;
-      if (y < NMOM) sm[y * kLdM + 16 * b + cl] = Mt[b][r];
-    }
+    for (int r = 0; r < 4; ++r) sm[(4 * g + r) * kLdM + 16 * b + cl] = Mt[b][r];
   wave_sync();
   float* Mi = Mout + (size_t)i * NMOM * F_L;
   float* qi = q + (size_t)i * 3 * F_L;
