@@ -158,17 +158,15 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
     for (int base = row0; base < row1; base += 64) {
       const int p = base + lane;
       const int j = p < row1 ? nbr[p] : -1;
-      float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
-      bool ok = false;
-      int zj = 0;
-      if (j >= 0) {
-        zj = species[j];
-        dx = static_cast<float>(minimage(pos[j] - xi, box, inv_box));
-        dy = static_cast<float>(minimage(pos[n + j] - yi, box, inv_box));
-        dz = static_cast<float>(minimage(pos[2 * n + j] - zi, box, inv_box));
-        r = sqrtf(dx * dx + dy * dy + dz * dz);
-        ok = r < P.rc;
-      }
+      // loads from the receiver itself where there is no pair: no branch, all loads of a
+      // lane issue together
+      const int jc = j >= 0 ? j : i;
+      const int zj = species[jc];
+      const float dx = static_cast<float>(minimage(pos[jc] - xi, box, inv_box));
+      const float dy = static_cast<float>(minimage(pos[n + jc] - yi, box, inv_box));
+      const float dz = static_cast<float>(minimage(pos[2 * n + jc] - zi, box, inv_box));
+      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+      const bool ok = j >= 0 && r < P.rc;
       const uint64_t mask = __ballot(ok);
       const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
       if (ok && k < kCap) {
@@ -199,11 +197,12 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
     for (int t0 = 0; t0 < cnt; t0 += kTile) {
       const int pc = t0 + cl;                       // pair of the A operand
       const bool vp = pc < cnt;
-      const float rp = vp ? sG[w][pc].w : 0.f;
+      // slots past the row read slot 0 and are masked after: no branches
+      const float rp = vp ? sG[w][vp ? pc : 0].w : 0.f;
       auto bk = [&](int e) {
         const int kk = BF16 ? 4 * g + e : 4 * e + g;
         const float x = rp - P.sigma * kk;
-        return vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+        return __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);
       };
       float fc[4];
       int zz[4];
@@ -211,9 +210,12 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
       for (int r = 0; r < 4; ++r) {
         const int q = t0 + 4 * g + r;
         const bool v = q < cnt;
-        const float rq = v ? sG[w][q].w : 0.f;
-        fc[r] = v ? 0.5f * (__cosf(pi_rc * rq) + 1.0f) : 0.f;
-        zz[r] = v ? sZ[w][q] : zi_s;
+        const int qc = v ? q : 0;
+        const float rq = sG[w][qc].w;
+        const float cq = 0.5f * (__cosf(pi_rc * rq) + 1.0f);
+        fc[r] = v ? cq : 0.f;
+        const int zq = sZ[w][qc];
+        zz[r] = v ? zq : zi_s;
       }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -285,8 +287,12 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
     if (act) {
       cnt = ell_n[i];
       zi_s = species[i];
-      jl = lane < cnt ? ell_j[(size_t)i * kCap + lane] : i;
-      gl = lane < cnt ? ell_g[(size_t)i * kCap + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+      // every lane loads its slot of the table (within the allocation) and entries past
+      // the row are replaced after: no branch around the loads
+      const int jraw = ell_j[(size_t)i * kCap + lane];
+      const float4 graw = ell_g[(size_t)i * kCap + lane];
+      jl = lane < cnt ? jraw : i;
+      gl = lane < cnt ? graw : make_float4(0.f, 0.f, 0.f, 0.f);
       zl = species[jl];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -319,12 +325,12 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
       auto bk = [&](int e) {
         const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
         const float x = rp - P.sigma * kk;
-        return vp ? __expf(-0.5f * x * x * inv_s2) : 0.f;
+        return __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);   // 0 past the row, no branch
       };
       auto dbk = [&](int e) {
         const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
         const float x = rp - P.sigma * kk;
-        return vp ? -x * inv_s2 * __expf(-0.5f * x * x * inv_s2) : 0.f;
+        return -x * inv_s2 * __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);
       };
       float S = 0.f;
 #pragma unroll
