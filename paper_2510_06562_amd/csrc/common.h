@@ -77,9 +77,10 @@ struct NList {
   int32_t n_cells_cap = 0;
 };
 
+// pos_copy (optional, float64 [3][n]): receives the positions the list is built from.
 dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
                             const int32_t* sys_offsets, int32_t n_sys, double cutoff,
-                            hipStream_t s);
+                            hipStream_t s, double* pos_copy = nullptr);
 
 // ------------------------------------------------------------------ models
 struct Model {

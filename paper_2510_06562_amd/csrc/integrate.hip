@@ -230,14 +230,10 @@ struct Runner {
     // for the fast model's displacement check, after which it becomes the current one)
     NList* nl = shared ? shared_list(st->shared_cur ^ 1) : st->nl_large;
     r = build_neighbors(nl, x, st->n, st->box, nullptr, 1,
-                        shared ? list_cut : (double)large->desc.cutoff, q);
+                        shared ? list_cut : (double)large->desc.cutoff, q,
+                        shared ? st->x_ref : nullptr);
     if (r != DMTS_OK) return r;
-    if (shared) {
-      const int64_t n3 = 3 * (int64_t)st->n;
-      k_copy_f64<<<ceil_div(n3, 256), 256, 0, q>>>(x, st->x_ref, n3);
-      DMTS_CHECK_LAUNCH();
-      st->shared_cur ^= 1;
-    }
+    if (shared) st->shared_cur ^= 1;
     return energy_forces(large, nl, x, st->species, st->n, st->box, nullptr, 1,
                          it.want_e ? st->e_models : nullptr, st->FL, nullptr, q, ep);
   }

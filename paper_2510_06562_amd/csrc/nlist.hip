@@ -124,9 +124,65 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int32_t* __restrict
 
 int scan_tiles(int64_t n) { return n <= 0 ? 1 : (int)((n + kScanTile - 1) / kScanTile); }
 
-// The two scan launches; `part` holds at least scan_tiles(n) values.
+// Up to kScanOne elements: one work-group of 1,024 threads, eight consecutive elements per
+// lane (one launch instead of two), the same exclusive scan, cap and flag as above.
+constexpr int kScanOneThreads = 1024, kScanOnePer = 8;
+constexpr int kScanOne = kScanOneThreads * kScanOnePer;
+
+__global__ void __launch_bounds__(kScanOneThreads) k_scan_one(int32_t* __restrict__ in,
+                                                             int32_t* __restrict__ out,
+                                                             int32_t* __restrict__ copy_to,
+                                                             int32_t n, int64_t cap,
+                                                             uint32_t* __restrict__ flags,
+                                                             bool zero_in) {
+  __shared__ int64_t wsum[kScanOneThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int k0 = t * kScanOnePer;
+  int32_t v[kScanOnePer];
+  int64_t run = 0;
+#pragma unroll
+  for (int e = 0; e < kScanOnePer; ++e) {
+    v[e] = k0 + e < n ? in[k0 + e] : 0;
+    run += v[e];
+  }
+  int64_t incl = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int64_t wbase = 0, total = 0;
+  for (int k = 0; k < kScanOneThreads / 64; ++k) {
+    wbase += k < w ? wsum[k] : 0;
+    total += wsum[k];
+  }
+  const bool overflow = total > cap;
+  int64_t o = wbase + incl - run;
+#pragma unroll
+  for (int e = 0; e < kScanOnePer; ++e) {
+    if (k0 + e < n) {
+      const int32_t r = overflow ? 0 : static_cast<int32_t>(o);
+      out[k0 + e] = r;
+      if (copy_to) copy_to[k0 + e] = r;
+      if (zero_in) in[k0 + e] = 0;
+    }
+    o += v[e];
+  }
+  if (t == 0) {
+    out[n] = overflow ? 0 : static_cast<int32_t>(total);
+    if (overflow && flags) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+  }
+}
+
+// The scan: one launch up to kScanOne elements, else the two tile launches (`part` holds at
+// least scan_tiles(n) values).
 void scan(int32_t* in, int32_t* out, int32_t* copy_to, int32_t n, int64_t cap, uint32_t* flags,
           bool zero_in, int64_t* part, hipStream_t s) {
+  if (n <= kScanOne) {
+    k_scan_one<<<1, kScanOneThreads, 0, s>>>(in, out, copy_to, n, cap, flags, zero_in);
+    return;
+  }
   const int tiles = scan_tiles(n);
   k_scan_sums<<<tiles, kScanThreads, 0, s>>>(in, n, part);
   k_scan_tiles<<<tiles, kScanThreads, 0, s>>>(in, out, copy_to, n, cap, flags, zero_in, part,
@@ -318,13 +374,14 @@ template <bool kCells>
 __global__ void __launch_bounds__(kNbWaves * 64)
 k_rows(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys,
        int32_t align, int32_t* __restrict__ ell, int32_t* __restrict__ len,
-       int32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
+       int32_t* __restrict__ cnt, uint32_t* __restrict__ flags, double* __restrict__ pos_copy) {
   __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
   __shared__ int32_t s_row[kNbWaves][kRowCap];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNbWaves + w;
   if (i >= g.n) return;
   const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
+  if (pos_copy && lane < 3) pos_copy[(size_t)lane * g.n + i] = lane == 0 ? xi : lane == 1 ? yi : zi;
   int lo = 0, hi = 0;
   if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
   int run = 0;
@@ -416,7 +473,7 @@ dmts_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 
 dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
                             const int32_t* sys_offsets, int32_t n_sys, double cutoff,
-                            hipStream_t s) {
+                            hipStream_t s, double* pos_copy) {
   DMTS_REQUIRE(nl && pos, DMTS_E_ARG, "build_neighbors: null argument");
   DMTS_REQUIRE(n >= 0 && n <= nl->max_atoms, DMTS_E_ARG,
                "build_neighbors: n_atoms %d outside [0, %d]", n, nl->max_atoms);
@@ -472,10 +529,12 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
   const int blocks = ceil_div(n, kNbWaves);
   if (cells)
     k_rows<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align,
-                                                   nl->ell, nl->len, nl->cnt, nl->flags);
+                                                   nl->ell, nl->len, nl->cnt, nl->flags,
+                                                   pos_copy);
   else
     k_rows<false><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align,
-                                                    nl->ell, nl->len, nl->cnt, nl->flags);
+                                                    nl->ell, nl->len, nl->cnt, nl->flags,
+                                                    pos_copy);
   DMTS_CHECK_LAUNCH();
   scan(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags, false, nl->scan_part, s);
   DMTS_CHECK_LAUNCH();
