@@ -285,3 +285,32 @@ def test_periodic_self_image_consistency():
     E2, F2, _ = P.energy_forces(SMALL, pos2, sp2, 2 * L)
     assert E2[0] == pytest.approx(8 * E1[0], rel=1e-12)
     np.testing.assert_allclose(F2[:192], F1, atol=1e-14)
+
+
+def test_solvated100k_fixture_matches_the_oracle():
+    """The stored full-size samples (tests/golden/solvated100k_samples.json) are the
+    oracle's: the fast model's per-atom energies and forces are recomputed here on their
+    receptive-field clusters (the reference model's take minutes and are left to the
+    generating script)."""
+    import json
+    import os
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import make_solvated100k_samples as gen
+    from paper_2510_06562_amd import synth
+    with open(os.path.join(here, "golden", "solvated100k_samples.json")) as f:
+        ref = json.load(f)
+    sy = synth.solvated_chain()
+    assert ref["atoms"] == gen.samples(sy.n_atoms)
+    spec, seed = gen.SPECS["small"]
+    m = P.make_model(spec.kind, spec.cutoff, spec.n_rbf, spec.width,
+                      synth.model_weights(spec, seed), energy_scale=spec.energy_scale)
+    for k, i in enumerate(ref["atoms"]):
+        p, s = gen.cluster(sy, i, 3.5 + 0.5)
+        _, _, Ea = P.energy_forces(m, p, s, 0.0)
+        assert Ea[0] == pytest.approx(ref["energy"]["small"][k], rel=1e-12, abs=1e-15)
+        p, s = gen.cluster(sy, i, 7.0 + 0.5)
+        _, F, Ea2 = P.energy_forces(m, p, s, 0.0)
+        np.testing.assert_allclose(F[0], ref["force"]["small"][k], rtol=1e-12, atol=1e-15)
+        assert Ea2[0] == pytest.approx(Ea[0], rel=1e-12)   # the larger cluster agrees
