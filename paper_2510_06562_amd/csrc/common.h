@@ -228,25 +228,32 @@ __device__ inline void fdiff_check(const Epilogue& E, double df2) {
   }
 }
 
+// Every input is loaded before the program runs (one memory round trip instead of one
+// per op that needs a new array); x and x_ref are written or checked only if it drifts.
 __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
-  const double im = inv_mass_of(E, E.species[i]);
-  double vv[3], xx[3];
-  bool moved = false;
+  const int z = E.species[i];
+  double vv[3], xx[3], xr[3];
+  float fl[3], fs[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) vv[d] = E.v[(size_t)d * n + i];
+  for (int d = 0; d < 3; ++d) {
+    const size_t o = (size_t)d * n + i;
+    vv[d] = E.v[o];
+    xx[d] = E.x[o];
+    xr[d] = E.x_ref ? E.x_ref[o] : 0.0;
+    fl[d] = E.FL[o];
+    fs[d] = E.Fs[o];
+  }
+  const double im = inv_mass_of(E, z);
+  bool moved = false;
   for (int k = 0; k < E.prog.nops; ++k) {
     const int op = E.prog.op[k];
     const double c = E.prog.c[k];
     if (op == kDrift) {
-      if (!moved) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xx[d] = E.x[(size_t)d * n + i];
-        moved = true;
-      }
+      moved = true;
 #pragma unroll
       for (int d = 0; d < 3; ++d) xx[d] = xx[d] + c * vv[d];
     } else if (op == kThermo) {
-      const double sd = o_sd_of(E, E.species[i]);
+      const double sd = o_sd_of(E, z);
       for (int d = 0; d < 3; ++d)
         vv[d] = E.o_decay * vv[d] + sd * o_normal(i, E.prog.ctr[k], E.o_key, d);
     } else {
@@ -255,9 +262,9 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double f;
-        if (op == kKickSlow) f = (double)E.FL[(size_t)d * n + i] - (double)E.Fs[(size_t)d * n + i];
-        else if (op == kKickFast) f = (double)E.Fs[(size_t)d * n + i];
-        else f = (double)E.FL[(size_t)d * n + i];
+        if (op == kKickSlow) f = (double)fl[d] - (double)fs[d];
+        else if (op == kKickFast) f = (double)fs[d];
+        else f = (double)fl[d];
         vv[d] = vv[d] + ci * f;
         df2 += f * f;
       }
@@ -277,10 +284,8 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
     for (int d = 0; d < 3; ++d) {
       E.x[(size_t)d * n + i] = xx[d];
       bad |= !isfinite(xx[d]);
-      if (E.x_ref) {
-        const double u = xx[d] - E.x_ref[(size_t)d * n + i];
-        d2 += u * u;
-      }
+      const double u = xx[d] - xr[d];
+      d2 += u * u;
     }
     if (E.x_ref && !(d2 <= E.max_disp2)) f |= kFlagStale;
   }

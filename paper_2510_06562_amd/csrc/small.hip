@@ -14,6 +14,8 @@
 //     W_r b'^T) puts one pair on each lane and 16 channels in its registers; both messages
 //     of the pair (j -> i and i -> j differ only by the swapped species tables) give
 //     s_ij + s_ji = dE/dr_ij as an in-lane channel sum, and F_i = sum_j (s_ij + s_ji) d/r.
+//     Once F_i is final the integrator's kicks and drifts of atom i can run in the same
+//     wave (the program that follows the evaluation, when it has no O-step).
 // Rows are sorted by sender, so the sums do not depend on the list's cutoff or padding.
 //
 // MFMA 16x16x4 f32:  A operand lane l: A[l%16][k0 + l/16]; B: B[k0 + l/16][l%16];
@@ -263,12 +265,14 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
   }
 }
 
+// Three waves per SIMD (registers capped at 168): left free, the compiler takes ~250 for
+// the FP32 form with the integrator epilogue, which leaves two.
 template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64)
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
             const float* __restrict__ g, const int32_t* __restrict__ ell_j,
             const float4* __restrict__ ell_g, const int32_t* __restrict__ ell_n,
-            float* __restrict__ forces) {
+            float* __restrict__ forces, Epilogue E, bool has_ep, bool fresh_small) {
   __shared__ SmallLds<false> L;
   Stager<false> stage;
   stage.fetch(P);
@@ -361,6 +365,8 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
       fy = fmaf(S * ir, gv.y, fy);
       fz = fmaf(S * ir, gv.z, fz);
     }
+    CoordIn ein{};   // the atom's integrator inputs, coordinate d = lane (lanes 0..2)
+    if (has_ep && lane < 3) ein = prefetch_coord(E, i, n, lane, fresh_small);
     // sum over the 16 pair columns (every group holds the same values)
     fx = row16_sum(fx);
     fy = row16_sum(fy);
@@ -370,6 +376,9 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
       forces[n + i] = fy;
       forces[2 * n + i] = fz;
     }
+    // F_i is final (every lane holds the sums): the integrator step of atom i
+    if (has_ep)
+      apply_coords(E, i, n, lane, ein, lane == 0 ? fx : lane == 1 ? fy : fz, fresh_small);
   }
 }
 
@@ -400,6 +409,13 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
                 m->p(m->o_w2), m->rc, m->sigma, m->escale, m->Z};
   if (n > 0) {
     const int natural = ceil_div(n, kWaves);
+    // The integrator program (kicks and drifts) runs in the reverse kernel, per atom once
+    // its force is final: the kernel reads no positions, so a drift cannot race with it.
+    // The forces computed here are the program's F_small or, when this model stands in for
+    // the reference one (single-time-step runs), its F_large.  A program with an O-step
+    // runs as a launch of its own.
+    const bool fuse = ep && forces && (forces == ep->Fs || forces == ep->FL) &&
+                      !has_thermo(ep->prog);
     auto run = [&](auto bf_tag) {
       constexpr bool BF = decltype(bf_tag)::value;
       {
@@ -414,14 +430,14 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
       const int blocks = m->launch_grid(
           natural, resident_groups(reinterpret_cast<const void*>(&k_small_bwd<BF>), kWaves * 64));
       launch_timed(ps, &k_small_bwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, species, n, g,
-                   ell_j, ell_g, ell_n, forces);
+                   ell_j, ell_g, ell_n, forces, fuse ? *ep : Epilogue{}, fuse,
+                   fuse && forces == ep->Fs);
     };
+    if (fuse && ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
     if (m->bf16) run(std::true_type{});
     else run(std::false_type{});
     DMTS_CHECK_LAUNCH();
-    // the integrator program runs as a launch of its own here: in the reverse kernel's
-    // epilogue it would lengthen every wave by more than the launch costs
-    if (ep) {
+    if (ep && !fuse) {
       if (ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
       const dmts_status st = apply_program(*ep, n, s);
       if (st != DMTS_OK) return st;
