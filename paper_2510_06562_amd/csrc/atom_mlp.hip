@@ -1,10 +1,11 @@
 // Per-atom dense layers of the reference potential as fused MFMA chains.
 //
 // Every per-atom layer is a row-local contraction [rows x K] * [K x N], so the whole chain
-// of layers between two pair kernels runs in one launch: a work-group owns RT tiles of 16
-// atoms (RT = 1 in the FP32 form, 2 in the BF16 form, where each weight load then feeds
-// both tiles), keeps the activations of its atoms in LDS between layers and streams the
-// weights (at most 384 x 384, L2-resident) from global memory.  Contractions use
+// of layers between two pair kernels runs in one launch: a work-group owns RT = 2 tiles of
+// 16 atoms (each weight load feeds both tiles), keeps the activations of its atoms in LDS
+// between layers and streams the weights (at most 384 x 384, L2-resident) from global
+// memory.  The weight stream, not the products, bounds a 16-atom work-group in the FP32
+// form, so both forms take 32 atoms.  Contractions use
 // v_mfma_f32_16x16x4_f32; the eight waves of the work-group split the output columns in
 // blocks of 16.  A row's result does not depend on its tile or work-group.
 //
@@ -31,6 +32,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512;   // eight waves: one or more 16-column blocks each
+constexpr int kRT = 2;       // 16-atom tiles per work-group
 constexpr int kLd = 388;     // LDS row stride (floats) for activations up to 384 wide
 
 template <int RT>
@@ -270,8 +272,7 @@ dmts_status atom_chain1(const AtomMlpParams& P, int M, const float* q1, float* z
                         float* P2, hipStream_t s) {
   if (M <= 0) return DMTS_OK;
   ProfScope ps(DMTS_K_ATOM_GEMM, s);
-  if (P.h_U1) k_chain1<2><<<ceil_div(M, 32), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
-  else k_chain1<1><<<ceil_div(M, 16), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
+  k_chain1<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
@@ -281,12 +282,8 @@ dmts_status atom_chain2(const AtomMlpParams& P, int M, const float* q2, const fl
                         hipStream_t s) {
   if (M <= 0) return DMTS_OK;
   ProfScope ps(DMTS_K_ATOM_GEMM, s);
-  if (P.h_U2)
-    k_chain2<2><<<ceil_div(M, 32), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2, dq2,
-                                                     backward);
-  else
-    k_chain2<1><<<ceil_div(M, 16), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2, dq2,
-                                                     backward);
+  k_chain2<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2,
+                                                           dq2, backward);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
@@ -295,8 +292,7 @@ dmts_status atom_chain3(const AtomMlpParams& P, int M, const float* RS, const fl
                         const float* z1, float* dq1, hipStream_t s) {
   if (M <= 0) return DMTS_OK;
   ProfScope ps(DMTS_K_ATOM_GEMM, s);
-  if (P.h_U1T) k_chain3<2><<<ceil_div(M, 32), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
-  else k_chain3<1><<<ceil_div(M, 16), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
+  k_chain3<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
