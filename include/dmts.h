@@ -219,6 +219,17 @@ dmts_status dmts_step(dmts_state* st, double* x, double* v, nnp_model* small,
 dmts_status dmts_state_reset(dmts_state* st);
 dmts_status dmts_state_fallbacks(dmts_state* st, int64_t* n_calls);
 
+/* Per-atom masses (amu, host array of n_atoms values, each finite and > 0), used instead of
+ * the species table by every kick, O-step and kinetic energy of the state: hydrogen mass
+ * repartitioning (heavier hydrogens for longer outer steps: the bulk-water stability
+ * tests and their table) needs masses that depend on the bonding, not only on the
+ * species.  NULL returns to the species table.  Copies the values to device memory the state owns (blocking; call it
+ * between steps, not while a dmts_step of this state is in flight).  DMTS_E_ARG for a
+ * count other than the state's or a mass that is not finite and positive.
+ */
+dmts_status dmts_state_set_atom_masses(dmts_state* st, const double* host_masses,
+                                       int32_t n_atoms);
+
 /* Langevin thermostat of Algorithm 1 (the O-step; the paper's production runs use
  * gamma = 1 ps^-1 = 0.001 fs^-1).  gamma_per_fs >= 0 (0 turns it off), temperature_K >= 0,
  * seed: the key of the noise.  Resets the O-step counter to 0; DMTS_E_ARG for a negative

@@ -78,6 +78,7 @@ _SIGS = {
     "dmts_state_set_thermostat": ([_P, _D, _D, ctypes.c_uint64], _I32),
     "dmts_state_o_steps": ([_P, ctypes.POINTER(ctypes.c_uint64)], _I32),
     "dmts_state_set_fdiff_threshold": ([_P, _D], _I32),
+    "dmts_state_set_atom_masses": ([_P, _P, _I32], _I32),
     "dmts_state_fdiff": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_D)], _I32),
     "dmts_state_forces": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I32),
     "dmts_state_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
@@ -351,6 +352,18 @@ class DMTS:
         """Langevin O-step of Algorithm 1 (gamma 0 = off); resets the O-step counter."""
         _check(lib().dmts_state_set_thermostat(self._h, float(gamma_per_fs),
                                                float(temperature_K), int(seed)))
+
+    def set_atom_masses(self, masses):
+        """Per-atom masses (amu; e.g. hydrogen mass repartitioning) instead of the species
+        table for the kicks, O-steps and kinetic energy; None returns to the table."""
+        if masses is None:
+            _check(lib().dmts_state_set_atom_masses(self._h, None, 0))
+            return
+        m = np.ascontiguousarray(np.asarray(masses, dtype=np.float64))
+        if m.ndim != 1:
+            raise DmtsError(E_ARG, "set_atom_masses: expected a 1-d array of masses")
+        _check(lib().dmts_state_set_atom_masses(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                                int(m.shape[0])))
 
     def set_fdiff_threshold(self, eV_per_A: float):
         """Redo a call as single-time-step steps when |F - F_small| of an atom exceeds

@@ -149,6 +149,7 @@ struct Epilogue {
   const float* Fs;           // [3][n] fast-model forces
   const int32_t* species;
   double inv_mass[8];        // per species (kernel argument: no memory round trip)
+  const double* inv_mass_atom;   // [n] per-atom 1/m (repartitioned masses) or null
   const double* x_ref;       // positions of the shared list's build (displacement check) or null
   double max_disp2;
   uint32_t* flags;
@@ -156,6 +157,7 @@ struct Epilogue {
   // sqrt((1 - decay^2) k_B T KAPPA / m), Philox key words
   double o_decay;
   double o_sd[8];
+  double o_var;              // (1 - decay^2) k_B T KAPPA: the noise scale is sqrt(o_var / m)
   uint32_t o_key[2];
   // force-difference monitor of the slow kicks: squared threshold (0: off) and the word
   // that keeps the largest breaching |F - F_small| (float bits, eV/A)
@@ -212,6 +214,10 @@ __device__ inline double inv_mass_of(const Epilogue& E, int z) {
   for (int k = 1; k < 8; ++k) im = z == k ? E.inv_mass[k] : im;
   return im;
 }
+// 1 / m of atom i (species z): the per-atom table when one is set, else the species table.
+__device__ inline double inv_mass_at(const Epilogue& E, int i, int z) {
+  return E.inv_mass_atom ? E.inv_mass_atom[i] : inv_mass_of(E, z);
+}
 __device__ inline double o_sd_of(const Epilogue& E, int z) {
   double sd = E.o_sd[0];
 #pragma unroll
@@ -232,6 +238,7 @@ __device__ inline void fdiff_check(const Epilogue& E, double df2) {
 // per op that needs a new array); x and x_ref are written or checked only if it drifts.
 __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
   const int z = E.species[i];
+  const double im_atom = E.inv_mass_atom ? E.inv_mass_atom[i] : 0.0;
   double vv[3], xx[3], xr[3];
   float fl[3], fs[3];
 #pragma unroll
@@ -243,7 +250,7 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
     fl[d] = E.FL[o];
     fs[d] = E.Fs[o];
   }
-  const double im = inv_mass_of(E, z);
+  const double im = E.inv_mass_atom ? im_atom : inv_mass_of(E, z);
   bool moved = false;
   for (int k = 0; k < E.prog.nops; ++k) {
     const int op = E.prog.op[k];
@@ -253,7 +260,7 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) xx[d] = xx[d] + c * vv[d];
     } else if (op == kThermo) {
-      const double sd = o_sd_of(E, z);
+      const double sd = E.inv_mass_atom ? sqrt(E.o_var * im) : o_sd_of(E, z);
       for (int d = 0; d < 3; ++d)
         vv[d] = E.o_decay * vv[d] + sd * o_normal(i, E.prog.ctr[k], E.o_key, d);
     } else {
@@ -298,8 +305,7 @@ __device__ inline void apply_atom(const Epilogue& E, int i, int n) {
 // computed as `fresh`; fresh_small tells whether that is the program's F_small (else
 // F_large), whichever model produced it.
 struct CoordIn {
-  double x, v, xr, fother;
-  int z;
+  double x, v, xr, fother, im;
 };
 
 __device__ inline CoordIn prefetch_coord(const Epilogue& E, int i, int n, int d, bool fresh_small) {
@@ -309,7 +315,7 @@ __device__ inline CoordIn prefetch_coord(const Epilogue& E, int i, int n, int d,
   c.v = E.v[o];
   c.xr = E.x_ref ? E.x_ref[o] : 0.0;
   c.fother = fresh_small ? (double)E.FL[o] : (double)E.Fs[o];
-  c.z = E.species[i];
+  c.im = inv_mass_at(E, i, E.species[i]);
   return c;
 }
 
@@ -321,7 +327,7 @@ __device__ inline void apply_coords(const Epilogue& E, int i, int n, int lane, c
                                     float fresh, bool fresh_small) {
   double vv = c.v, xx = c.x;
   bool moved = false;
-  const double im = inv_mass_of(E, c.z);
+  const double im = c.im;
   const double fl = fresh_small ? c.fother : (double)fresh;
   const double fs = fresh_small ? (double)fresh : c.fother;
   for (int k = 0; k < E.prog.nops; ++k) {

@@ -58,7 +58,8 @@ constexpr int kKeChunk = kKeThreads * 8;
 
 __global__ void __launch_bounds__(kKeThreads)
 k_ke_chunks(int n, const double* __restrict__ v, const int32_t* __restrict__ species,
-            const double* __restrict__ mass, double* __restrict__ partial) {
+            const double* __restrict__ mass, const double* __restrict__ atom_mass,
+            double* __restrict__ partial) {
   __shared__ double wsum[kKeThreads / 64];
   const int base = blockIdx.x * kKeChunk;
   double a[8];
@@ -67,7 +68,7 @@ k_ke_chunks(int n, const double* __restrict__ v, const int32_t* __restrict__ spe
     const int i = base + (int)threadIdx.x + j * kKeThreads;
     a[j] = 0.0;
     if (i < n) {
-      const double m = mass[species[i]];
+      const double m = atom_mass ? atom_mass[i] : mass[species[i]];
       const double x = v[i], y = v[(size_t)n + i], z = v[2 * (size_t)n + i];
       a[j] = m * (x * x + y * y + z * z);
     }
@@ -130,6 +131,9 @@ struct State {
   double* inv_mass = nullptr;
   double host_inv_mass[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the same, for kernel arguments
   double host_mass[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // per-atom masses and their inverses (hydrogen mass repartitioning); null: species table
+  double* atom_mass = nullptr;       // [n]
+  double* atom_inv_mass = nullptr;   // [n]
   // Langevin O-step (gamma = 0: off, NVE); o_count numbers the state's O-steps
   double gamma = 0.0, temperature = 0.0;
   uint64_t seed = 0, o_count = 0;
@@ -179,6 +183,7 @@ struct Runner {
   // O-step constants of this call
   double o_decay = 1.0;
   double o_sd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double o_var = 0.0;
 
   void op(int o, double c, uint64_t ctr = 0) { sched.push_back(Item{false, o, c, false, ctr}); }
   void eval(int kind, bool want_e) { sched.push_back(Item{true, kind, 0.0, want_e, 0}); }
@@ -192,11 +197,13 @@ struct Runner {
     e.Fs = st->Fs;
     e.species = st->species;
     for (int z = 0; z < 8; ++z) e.inv_mass[z] = st->host_inv_mass[z];
+    e.inv_mass_atom = st->atom_inv_mass;
     e.x_ref = shared ? st->x_ref : nullptr;
     e.max_disp2 = max_disp2;
     e.flags = st->flags;
     e.o_decay = o_decay;
     for (int z = 0; z < 8; ++z) e.o_sd[z] = o_sd[z];
+    e.o_var = o_var;
     e.o_key[0] = (uint32_t)st->seed;
     e.o_key[1] = (uint32_t)(st->seed >> 32);
     e.fdiff_thr2 = st->fdiff_thr * st->fdiff_thr;
@@ -305,6 +312,7 @@ struct Runner {
 // sqrt((1 - decay^2) k_B T KAPPA / m) (Algorithm 1's thermostat, exact Ornstein-Uhlenbeck).
 void o_constants(const State* st, Runner& R, double h) {
   R.o_decay = std::exp(-st->gamma * h);
+  R.o_var = (1.0 - R.o_decay * R.o_decay) * kBoltzmann * st->temperature * kKappa;
   for (int z = 0; z < 8; ++z)
     R.o_sd[z] = st->host_mass[z] > 0.0
                     ? std::sqrt((1.0 - R.o_decay * R.o_decay) * kBoltzmann * st->temperature *
@@ -469,6 +477,8 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   (void)hipFree(st->bak);
   (void)hipFree(st->mass);
   (void)hipFree(st->inv_mass);
+  (void)hipFree(st->atom_mass);
+  (void)hipFree(st->atom_inv_mass);
   (void)hipFree(st->e_models);
   (void)hipFree(st->ke_part);
   (void)hipFree(st->fdiff_max);
@@ -496,6 +506,40 @@ extern "C" dmts_status dmts_state_set_thermostat(dmts_state* h, double gamma_per
   st->temperature = temperature_K;
   st->seed = seed;
   st->o_count = 0;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_set_atom_masses(dmts_state* h, const double* host_masses,
+                                                  int32_t n_atoms) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_set_atom_masses: null state");
+  if (!host_masses) {   // back to the species table
+    (void)hipFree(st->atom_mass);
+    (void)hipFree(st->atom_inv_mass);
+    st->atom_mass = st->atom_inv_mass = nullptr;
+    return DMTS_OK;
+  }
+  DMTS_REQUIRE(n_atoms == st->n, DMTS_E_ARG,
+               "dmts_state_set_atom_masses: %d masses for a state of %d atoms", n_atoms, st->n);
+  std::vector<double> m(2 * (size_t)n_atoms);
+  for (int32_t i = 0; i < n_atoms; ++i) {
+    DMTS_REQUIRE(std::isfinite(host_masses[i]) && host_masses[i] > 0.0, DMTS_E_ARG,
+                 "dmts_state_set_atom_masses: mass %d is %g (must be finite and > 0)", i,
+                 host_masses[i]);
+    m[i] = host_masses[i];
+    m[(size_t)n_atoms + i] = 1.0 / host_masses[i];
+  }
+  const size_t bytes = sizeof(double) * (size_t)n_atoms;
+  if (!st->atom_mass) {
+    DMTS_HIP(hipMalloc(&st->atom_mass, bytes));
+    if (hipMalloc(&st->atom_inv_mass, bytes) != hipSuccess) {
+      (void)hipFree(st->atom_mass);
+      st->atom_mass = nullptr;
+      DMTS_REQUIRE(false, DMTS_E_OOM, "dmts_state_set_atom_masses: out of device memory");
+    }
+  }
+  DMTS_HIP(hipMemcpy(st->atom_mass, m.data(), bytes, hipMemcpyHostToDevice));
+  DMTS_HIP(hipMemcpy(st->atom_inv_mass, m.data() + n_atoms, bytes, hipMemcpyHostToDevice));
   return DMTS_OK;
 }
 
@@ -656,7 +700,7 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
     const int nc = (st->n + dmts::kKeChunk - 1) / dmts::kKeChunk;
     if (nc > 0)
       dmts::k_ke_chunks<<<nc, dmts::kKeThreads, 0, s>>>(st->n, v, st->species, st->mass,
-                                                         st->ke_part);
+                                                         st->atom_mass, st->ke_part);
     dmts::k_energies<<<1, 64, 0, s>>>(st->ke_part, nc, st->e_models, energies_out, st->flags);
   }
   DMTS_CHECK_LAUNCH();

@@ -66,6 +66,34 @@ class System:
     def masses(self) -> np.ndarray:
         return MASSES[self.species]
 
+    def hmr_masses(self, h_mass: float = 3.024) -> np.ndarray:
+        """Hydrogen mass repartitioning: every hydrogen gets h_mass (default three times
+        its mass) and the difference is taken from its nearest heavy atom (minimum image;
+        in a batch, within its molecule), so each molecule keeps its total mass.  A heavy
+        atom gives at most what keeps it at h_mass (random synthetic molecules can put many
+        hydrogens next to one atom); its hydrogens then share that amount equally."""
+        from scipy.spatial import cKDTree
+        m = self.masses().copy()
+        offs = self.sys_offsets if self.sys_offsets is not None else np.array([0, self.n_atoms])
+        for a, b in zip(offs[:-1], offs[1:]):
+            sp = self.species[a:b]
+            hyd = np.nonzero(sp == H)[0]
+            heavy = np.nonzero(sp != H)[0]
+            if len(hyd) == 0 or len(heavy) == 0:
+                continue
+            pos = self.pos[a:b]
+            if self.box > 0.0:
+                tree = cKDTree(np.mod(pos[heavy], self.box), boxsize=self.box)
+                _, k = tree.query(np.mod(pos[hyd], self.box))
+            else:
+                _, k = cKDTree(pos[heavy]).query(pos[hyd])
+            cnt = np.bincount(k, minlength=len(heavy))
+            room = np.maximum(m[a + heavy] - h_mass, 0.0)
+            dm = np.minimum(h_mass - MASSES[H], room / np.maximum(cnt, 1))
+            m[a + hyd] = MASSES[H] + dm[k]
+            m[a + heavy] -= cnt * dm
+        return m
+
 
 # --------------------------------------------------------------------------- rotations
 def _haar_rotations(rng: np.random.Generator, n: int) -> np.ndarray:

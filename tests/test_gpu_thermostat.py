@@ -123,7 +123,8 @@ def test_langevin_resume_and_seed(models):
 def test_thermostat_reaches_bath_temperature_water4500(models):
     """From rest, strong friction brings the 4,500-atom box to the bath temperature: the
     mean kinetic temperature (3N degrees of freedom, all thermostatted) over the second
-    half of 60 outer steps is within 3% of 300 K."""
+    half of 60 outer steps is within 3% of 300 K, and the velocities of the last step
+    follow the Maxwell-Boltzmann distribution of each species (Kolmogorov-Smirnov)."""
     say("Langevin water4500 bath temperature")
     sy = system("water4500")
     st = _state(sy, 4.0, 4, thermo=False)
@@ -137,6 +138,18 @@ def test_thermostat_reaches_bath_temperature_water4500(models):
             temps.append(2.0 * e[2].item() / (3 * sy.n_atoms * OI.K_BOLTZMANN))
     say(f"mean T {np.mean(temps):.1f} K")
     assert abs(np.mean(temps) / TEMP - 1.0) < 0.03
+    # Maxwell-Boltzmann: each velocity component, scaled by sqrt(m / (k_B T KAPPA)), is a
+    # standard normal; Kolmogorov-Smirnov over the 13,500 components of the last step,
+    # hydrogen and oxygen separately (the scale depends on the mass)
+    from scipy import stats
+    vv = v.cpu().numpy()
+    m = synth.MASSES[sy.species]
+    z = vv * np.sqrt(m / (OI.K_BOLTZMANN * TEMP * OI.KAPPA))[None, :]
+    for sp_id in np.unique(sy.species):
+        sample = z[:, sy.species == sp_id].ravel()
+        ks = stats.kstest(sample, "norm")
+        say(f"species {sp_id}: {sample.size} components, KS D {ks.statistic:.4f}, p {ks.pvalue:.3f}")
+        assert ks.pvalue > 1e-3
 
 
 def test_thermostat_rejects_bad_arguments():

@@ -49,3 +49,22 @@ def test_weight_blob_sizes_and_scale():
     assert wl.size == 80 + 128 * 64 + 128 * 384 + 128 * 288 + 128 * 384 + 128 * 128 + 128
     u = synth.unpack_weights(synth.LARGE, wl)
     assert abs(u["U1"].std() * np.sqrt(384) - 1.0) < 0.02
+
+
+def test_hmr_masses():
+    """Hydrogen mass repartitioning keeps every molecule's mass: in water each H gets
+    3.024 amu and its oxygen 15.999 - 2 (3.024 - 1.008); in the random batch molecules
+    no heavy atom ends lighter than the repartitioned hydrogens."""
+    w = synth.water_192()
+    m = w.hmr_masses()
+    assert np.allclose(m[w.species == synth.H], 3.024)
+    assert np.allclose(m[w.species == synth.O], 15.999 - 2 * (3.024 - 1.008))
+    assert abs(m.sum() - w.masses().sum()) < 1e-9
+    b = synth.molecule_batch(16, seed=3)
+    mb = b.hmr_masses()
+    for a, c in zip(b.sys_offsets[:-1], b.sys_offsets[1:]):
+        assert abs(mb[a:c].sum() - b.masses()[a:c].sum()) < 1e-9
+    heavy = b.species != synth.H
+    assert mb[heavy].min() >= 3.024 - 1e-12
+    assert mb[~heavy].min() >= synth.MASSES[synth.H] - 1e-12
+    assert mb[~heavy].max() <= 3.024 + 1e-12
