@@ -117,6 +117,10 @@ def parse():
                     help="Langevin friction per fs for both timed runs (0: NVE; the paper's "
                          "production value is 0.001)")
     ap.add_argument("--temperature", type=float, default=300.0)
+    ap.add_argument("--fast-model", default="one", choices=["one", "mp"],
+                    help="fast model: one interaction (rc 3.5 A, F 64; default) or the "
+                         "message-passing variant (two interactions as the reference model, "
+                         "rc 3.5 A), which runs on the shared list filtered to 3.5 A")
     ap.add_argument("--n-inner", type=int, default=4)
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -126,7 +130,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_oracle(sy, ws, wl, n_inner, dt_inner):
+def cpu_oracle(sy, ws, wl, n_inner, dt_inner, spec_s, spec_l):
     """Time the FP64 oracle on this host: one fast-model and one reference-model
     evaluation of the workload (the bounded sample), extrapolated to DMTS ns/day."""
     from oracle import potentials as OP
@@ -136,8 +140,10 @@ def cpu_oracle(sy, ws, wl, n_inner, dt_inner):
         cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
-    ms = OP.make_model(0, 3.5, 16, 64, ws)
-    ml = OP.make_model(1, 5.2, 32, 128, wl)
+    ms = OP.make_model(spec_s.kind, spec_s.cutoff, spec_s.n_rbf, spec_s.width, ws,
+                       energy_scale=spec_s.energy_scale)
+    ml = OP.make_model(spec_l.kind, spec_l.cutoff, spec_l.n_rbf, spec_l.width, wl,
+                       energy_scale=spec_l.energy_scale)
     t0 = time.perf_counter()
     Es, Fs, _ = OP.energy_forces(ms, sy.pos, sy.species, sy.box)
     t1 = time.perf_counter()
@@ -267,10 +273,12 @@ def main():
         return
     sy = {"water4500": synth.water_4500, "water192": synth.water_192,
           "solvated100k": synth.solvated_chain}[args.workload]()
-    ws = synth.model_weights(synth.SMALL, synth.SMALL_SEED)
+    spec_s, seed_s = ((synth.SMALL, synth.SMALL_SEED) if args.fast_model == "one" else
+                      (synth.SMALL_MP, synth.SMALL_MP_SEED))
+    ws = synth.model_weights(spec_s, seed_s)
     wl = synth.model_weights(synth.LARGE, synth.LARGE_SEED)
     prec = api.PREC_BF16 if args.precision == "bf16" else api.PREC_FP32
-    small = api.Model.from_spec(synth.SMALL, ws, precision=prec)
+    small = api.Model.from_spec(spec_s, ws, precision=prec)
     large = api.Model.from_spec(synth.LARGE, wl, precision=prec)
     sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
     v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201)
@@ -354,7 +362,9 @@ def main():
 
     # ---------------------------------------------------------------- dominant kernel roofline
     roofline = None
-    if dom and prof[dom][1] > 0:
+    # (with the message-passing fast model both models launch the pair kernels, whose
+    # timing classes then mix two pair counts: no roofline line)
+    if dom and prof[dom][1] > 0 and args.fast_model == "one":
         tot_ms, launches = prof[dom]
         avg_s = tot_ms / launches * 1e-3
         pairs = pairs_small if dom.startswith("small") else pairs_large
@@ -372,7 +382,7 @@ def main():
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
-        c = cpu_oracle(sy, ws, wl, n_inner, dt_in)
+        c = cpu_oracle(sy, ws, wl, n_inner, dt_in, spec_s, synth.LARGE)
         cpu = {"value": round(c["ns_per_day"], 6), "unit": "ns/day", "cores": c["cores"],
                "kind": "oracle",
                "sample": (f"one fast-model ({c['t_small']:.2f} s) and one reference-model "
@@ -404,7 +414,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": sy.n_atoms, "box_A": sy.box,
                    "dt_inner_fs": dt_in, "dt_outer_fs": dt_out,
-                   "fast_model": "1 interaction, rc 3.5 A, K 16, F 64",
+                   "fast_model": ("1 interaction, rc 3.5 A, K 16, F 64" if args.fast_model == "one"
+                                  else "2 interactions, rc 3.5 A, K 32, F 128, l<=2"),
                    "reference_model": "2 interactions, rc 5.2 A, K 32, F 128, l<=2",
                    "integration": "f64",
                    "ensemble": ("NVE" if args.gamma <= 0.0 else

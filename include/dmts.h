@@ -140,6 +140,14 @@ dmts_status nnp_autotune(nnp_model* model, nnp_nlist* nl, const double* pos,
  * nnp_build_neighbors: rebuilds the list for pos ([3][n_atoms] float64).  A periodic box
  *   needs cutoff < box/2 (else DMTS_E_BOX).  A list that would exceed max_pairs sets
  *   DMTS_FLAG_NBR_OVERFLOW on the device and is then incomplete.  Asynchronous.
+ * nnp_filter_neighbors: rebuilds child as the list at cutoff (<= the parent's) for pos,
+ *   from the rows of parent (built for the same atoms, at a longer cutoff, from positions
+ *   none of which has since moved more than half the cutoff difference): each parent row
+ *   filtered to |d_ij| < cutoff at pos, which keeps it sorted, so the child equals a list
+ *   built at cutoff with nnp_build_neighbors (a fast model of the reference kind reuses
+ *   the reference model's list this way).  child and parent must differ; the child's
+ *   row_align and capacity apply; DMTS_E_ARG for a cutoff outside (0, parent cutoff] or a
+ *   child with room for fewer atoms.  Asynchronous.
  * nnp_nlist_flags: synchronizes the stream, returns the flag word in *host_flags and
  *   clears it.
  * nnp_nlist_download: synchronizes, copies offs [n_atoms+1], nbr and rev [offs[n]] to
@@ -152,6 +160,8 @@ void nnp_nlist_destroy(nnp_nlist* nl);
 dmts_status nnp_build_neighbors(nnp_nlist* nl, const double* pos, int32_t n_atoms,
                                 double box, const int32_t* sys_offsets, int32_t n_sys,
                                 double cutoff, void* stream);
+dmts_status nnp_filter_neighbors(nnp_nlist* child, const nnp_nlist* parent, const double* pos,
+                                 double cutoff, void* stream);
 dmts_status nnp_nlist_flags(nnp_nlist* nl, void* stream, uint32_t* host_flags);
 dmts_status nnp_nlist_download(nnp_nlist* nl, void* stream, int32_t* host_offs,
                                int32_t* host_nbr, int32_t* host_rev, int64_t host_cap,

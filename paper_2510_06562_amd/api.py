@@ -67,6 +67,7 @@ _SIGS = {
     "nnp_nlist_create": ([_I32, _I64, _I32, ctypes.POINTER(_P)], _I32),
     "nnp_nlist_destroy": ([_P], None),
     "nnp_build_neighbors": ([_P, _P, _I32, _D, _P, _I32, _D, _P], _I32),
+    "nnp_filter_neighbors": ([_P, _P, _P, _D, _P], _I32),
     "nnp_nlist_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
     "nnp_nlist_download": ([_P, _P, _P, _P, _P, _I64, ctypes.POINTER(_I64)], _I32),
     "nnp_energy_forces": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _P, _P, _P, _P], _I32),
@@ -225,6 +226,13 @@ class NeighborList:
             n_sys = sys_offsets.numel() - 1
         _check(lib().nnp_build_neighbors(self._h, _ptr(pos_soa), n, float(box), _ptr(sys_offsets),
                                          n_sys, float(cutoff), _stream(stream)))
+
+    def filter_from(self, parent: "NeighborList", pos_soa: torch.Tensor, cutoff: float,
+                    stream=None):
+        """This list at `cutoff` (<= the parent's) from the parent's rows at pos_soa."""
+        _dev_check(pos_soa, torch.float64, (3, pos_soa.shape[1]), "pos")
+        _check(lib().nnp_filter_neighbors(self._h, parent.handle, _ptr(pos_soa), float(cutoff),
+                                          _stream(stream)))
 
     def flags(self, stream=None) -> int:
         f = ctypes.c_uint32()

@@ -81,6 +81,9 @@ struct NList {
 dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
                             const int32_t* sys_offsets, int32_t n_sys, double cutoff,
                             hipStream_t s, double* pos_copy = nullptr);
+// The list at a cutoff <= the parent's, from the parent's rows at the current positions.
+dmts_status filter_neighbors(NList* child, const NList* parent, const double* pos,
+                             double cutoff, hipStream_t s);
 
 // ------------------------------------------------------------------ models
 struct Model {

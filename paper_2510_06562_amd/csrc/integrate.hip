@@ -223,13 +223,20 @@ struct Runner {
     const Epilogue* ep = after.nops > 0 ? &E : nullptr;
     dmts_status r;
     if (it.op_or_kind == kEvalSmall) {
+      NList* nl = shared ? shared_list(st->shared_cur) : st->nl_small;
       if (!shared) {
         r = build_neighbors(st->nl_small, x, st->n, st->box, nullptr, 1,
                             (double)small->desc.cutoff, q);
         if (r != DMTS_OK) return r;
+      } else if (small->desc.kind == NNP_KIND_TWO_INTERACTION) {
+        // a fast model of the reference kind sums over exact rows: the shared list's rows
+        // filtered to its cutoff at the current positions (the one-interaction kernels
+        // compact the rows themselves)
+        r = filter_neighbors(st->nl_small, nl, x, (double)small->desc.cutoff, q);
+        if (r != DMTS_OK) return r;
+        nl = st->nl_small;
       }
-      return energy_forces(small, shared ? shared_list(st->shared_cur) : st->nl_small, x,
-                           st->species, st->n, st->box, nullptr, 1,
+      return energy_forces(small, nl, x, st->species, st->n, st->box, nullptr, 1,
                            it.want_e ? st->e_models + 1 : nullptr, st->Fs, nullptr, q, ep);
     }
     // reference model (Algorithm 1) or the plain single-time-step model: builds its list
@@ -410,7 +417,7 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
   st->species = species;
   st->dt = dt_outer_fs;
   st->n_inner = n_inner;
-  dmts_status r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_small + 4), 4,
+  dmts_status r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_small + 16), 16,
                                    reinterpret_cast<nnp_nlist**>(&st->nl_small));
   if (r == DMTS_OK)
     r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 16), 16,

@@ -412,6 +412,41 @@ k_rows(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys
   }
 }
 
+// Rows of a list at a shorter cutoff from a parent list: the parent row of i (ascending
+// senders, -1 padding) filtered to |d_ij| < r_c at the current positions.  Kept entries
+// stay in the parent's order, so the rows are sorted, and they are those of a list built
+// at r_c whenever the parent holds every such pair.  Same outputs and overflow rule as
+// k_rows.
+__global__ void __launch_bounds__(kNbWaves * 64)
+k_sub_rows(Geo g, const int32_t* __restrict__ p_offs, const int32_t* __restrict__ p_nbr,
+           int32_t align, int32_t* __restrict__ ell, int32_t* __restrict__ len,
+           int32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNbWaves + w;
+  if (i >= g.n) return;
+  const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
+  const int r0 = p_offs[i], r1 = p_offs[i + 1];
+  int32_t* out = ell + (size_t)i * kRowCap;
+  int run = 0;
+  for (int base = r0; base < r1; base += 64) {   // wave-uniform trip count
+    const int q = base + lane;
+    const int j = q < r1 ? p_nbr[q] : -1;
+    const bool acc = j >= 0 && within(g, xi, yi, zi, j);
+    const uint64_t mask = __ballot(acc);
+    const int slot = run + __popcll(mask & ((1ull << lane) - 1ull));
+    if (acc && slot < kRowCap) out[slot] = j;
+    run += __popcll(mask);
+  }
+  if (run > kRowCap) {
+    if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+    run = kRowCap;
+  }
+  if (lane == 0) {
+    len[i] = run;
+    cnt[i] = (run + align - 1) / align * align;
+  }
+}
+
 // CSR rows (padded with -1) from the staging table, the reverse index
 // rev[p] = offs[j] + (position of i in the sorted row of j), and the pair geometry at the
 // build positions: geo[p] = (d_ij as float, |d_ij|), zero for padding.
@@ -544,6 +579,37 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
   return DMTS_OK;
 }
 
+dmts_status filter_neighbors(NList* child, const NList* parent, const double* pos,
+                             double cutoff, hipStream_t s) {
+  DMTS_REQUIRE(child && parent && pos && child != parent, DMTS_E_ARG,
+               "filter_neighbors: null or aliased argument");
+  DMTS_REQUIRE(cutoff > 0.0 && cutoff <= parent->cutoff, DMTS_E_ARG,
+               "filter_neighbors: cutoff %g outside (0, %g] (the parent's)", cutoff,
+               parent->cutoff);
+  const int32_t n = parent->n_atoms;
+  DMTS_REQUIRE(n <= child->max_atoms, DMTS_E_ARG,
+               "filter_neighbors: the parent holds %d atoms, the child room for %d", n,
+               child->max_atoms);
+  child->n_atoms = n;
+  child->box = parent->box;
+  child->cutoff = cutoff;
+  ProfScope ps(DMTS_K_NEIGHBORS, s);
+  if (n == 0) return fill_u32(reinterpret_cast<uint32_t*>(child->offs), 0u, 1, s);
+  const double box = parent->box;
+  Geo g{pos, n, box, box > 0.0 ? 1.0 / box : 0.0, cutoff * cutoff};
+  const int blocks = ceil_div(n, kNbWaves);
+  k_sub_rows<<<blocks, kNbWaves * 64, 0, s>>>(g, parent->offs, parent->nbr, child->row_align,
+                                              child->ell, child->len, child->cnt, child->flags);
+  DMTS_CHECK_LAUNCH();
+  scan(child->cnt, child->offs, nullptr, n, child->max_pairs, child->flags, false,
+       child->scan_part, s);
+  DMTS_CHECK_LAUNCH();
+  k_compact<<<blocks, kNbWaves * 64, 0, s>>>(g, child->ell, child->len, child->offs, child->nbr,
+                                             child->rev, child->geo);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
 }  // namespace dmts
 
 // ------------------------------------------------------------------ C ABI
@@ -607,6 +673,13 @@ extern "C" void nnp_nlist_destroy(nnp_nlist* h) {
   (void)hipFree(nl->scan_part);
   nl->cell_buf.release();
   delete nl;
+}
+
+extern "C" dmts_status nnp_filter_neighbors(nnp_nlist* child, const nnp_nlist* parent,
+                                            const double* pos, double cutoff, void* stream) {
+  return dmts::filter_neighbors(reinterpret_cast<NList*>(child),
+                                reinterpret_cast<const NList*>(parent), pos, cutoff,
+                                static_cast<hipStream_t>(stream));
 }
 
 extern "C" dmts_status nnp_build_neighbors(nnp_nlist* h, const double* pos, int32_t n_atoms,

@@ -331,8 +331,12 @@ class ModelSpec:
 
 SMALL = ModelSpec(kind=0, cutoff=3.5, n_rbf=16, width=64)
 LARGE = ModelSpec(kind=1, cutoff=5.2, n_rbf=32, width=128)
+# the message-passing fast model (two interactions, as the reference model) at the fast
+# model's cutoff
+SMALL_MP = ModelSpec(kind=1, cutoff=3.5, n_rbf=32, width=128)
 SMALL_SEED = 101
 LARGE_SEED = 102
+SMALL_MP_SEED = 103
 
 
 def model_weights(spec: ModelSpec, seed: int) -> np.ndarray:

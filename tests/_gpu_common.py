@@ -43,8 +43,8 @@ def system(name):
     raise KeyError(name)
 
 
-SPECS = {"small": synth.SMALL, "large": synth.LARGE}
-SEEDS = {"small": synth.SMALL_SEED, "large": synth.LARGE_SEED}
+SPECS = {"small": synth.SMALL, "large": synth.LARGE, "small_mp": synth.SMALL_MP}
+SEEDS = {"small": synth.SMALL_SEED, "large": synth.LARGE_SEED, "small_mp": synth.SMALL_MP_SEED}
 
 
 @functools.lru_cache(maxsize=None)

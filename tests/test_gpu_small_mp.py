@@ -1,0 +1,86 @@
+"""The message-passing fast model (two interactions at the fast model's 3.5 A cutoff, the
+paper's more expressive small-model variant): the list filtered from the reference
+model's 5.2 A list equals the list built at 3.5 A; the model's energies and forces match
+the oracle; and Algorithm 1 with it as the fast model (on the filtered shared list)
+follows the oracle's trajectory."""
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu_common import OI, OP, oracle_ef, oracle_model, rel_rmse, say, system, weights, SPECS
+from paper_2510_06562_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def models():
+    return {k: api.Model.from_spec(SPECS[k], weights(k)) for k in ("small_mp", "large")}
+
+
+@pytest.mark.parametrize("sysname", ["water192", "water4500"])
+def test_filtered_list_equals_built_list(sysname):
+    say(f"list filter 5.2 -> 3.5 A, {sysname}")
+    sy = system(sysname)
+    pos = api.to_soa(sy.pos)
+    parent = api.NeighborList(sy.n_atoms, sy.n_atoms * 96, 16)
+    parent.build(pos, sy.box, 5.2)
+    a = api.NeighborList(sy.n_atoms, sy.n_atoms * 64, 16)
+    b = api.NeighborList(sy.n_atoms, sy.n_atoms * 64, 16)
+    a.filter_from(parent, pos, 3.5)
+    b.build(pos, sy.box, 3.5)
+    assert parent.flags() == 0 and a.flags() == 0 and b.flags() == 0
+    oa, na, ra = a.download(sy.n_atoms)
+    ob, nb, rb = b.download(sy.n_atoms)
+    assert np.array_equal(oa, ob) and np.array_equal(na, nb) and np.array_equal(ra, rb)
+
+
+def test_filter_rejects_a_longer_cutoff():
+    sy = system("water192")
+    pos = api.to_soa(sy.pos)
+    parent = api.NeighborList(sy.n_atoms, sy.n_atoms * 64, 16)
+    parent.build(pos, sy.box, 3.5)
+    child = api.NeighborList(sy.n_atoms, sy.n_atoms * 64, 16)
+    with pytest.raises(api.DmtsError) as e:
+        child.filter_from(parent, pos, 4.0)
+    assert e.value.status == api.E_ARG
+
+
+def test_small_mp_matches_oracle_water192(models):
+    say("message-passing fast model vs oracle, water192")
+    sy = system("water192")
+    E, F = api.Potential(models["small_mp"], sy.n_atoms, sy.box, 160)(api.to_soa(sy.pos),
+        torch.as_tensor(sy.species, dtype=torch.int32, device="cuda"))[:2]
+    Eo, Fo, _ = oracle_ef("water192", "small_mp")
+    e = float(E if not torch.is_tensor(E) else E.reshape(-1)[0])
+    ferr = rel_rmse(api.from_soa(F.double()), Fo)
+    say(f"  E {e:.6f} vs {Eo[0]:.6f}, force rel RMSE {ferr:.2e}")
+    assert abs(e - Eo[0]) <= 1e-5 * max(1.0, abs(Eo[0]))
+    assert ferr <= 1e-5
+
+
+def test_dmts_with_small_mp_matches_oracle_water192(models):
+    say("DMTS with the message-passing fast model, water192 3 outer x (4 inner), dt 2 fs")
+    sy = system("water192")
+    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 200)
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, 2.0, 4, 48, 128)
+    x, v = api.to_soa(sy.pos), api.to_soa(v0)
+    st.step(x, v, models["small_mp"], models["large"], 3)
+    assert st.fallbacks == 0
+    o = OI.MTSState(x=sy.pos.copy(), v=v0.copy(), m=sy.masses())
+
+    def force(which):
+        m = oracle_model(which)
+
+        def f(xx):
+            E, F, _ = OP.energy_forces(m, xx, sy.species, sy.box)
+            return E[0], F
+        return f
+    for _ in range(3):
+        OI.mts_step(o, 2.0, 4, force("small_mp"), force("large"))
+    dx = np.max(np.abs(api.from_soa(x) - o.x))
+    dv = np.max(np.abs(api.from_soa(v) - o.v))
+    say(f"  max |dx| {dx:.2e}, max |dv| {dv:.2e}")
+    assert dx < 1e-7 and dv < 1e-8
