@@ -214,7 +214,11 @@ dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos
  * is exact while every atom stays within half the gap to the fast cutoff of where the
  * list was built.  The device checks that bound at every drift; when it fails, the call
  * restores its starting x, v and carried forces and repeats with fresh lists for every
- * evaluation (same results, slower).
+ * evaluation (same results, slower).  The fast model may be of either kind: a
+ * one-interaction model compacts the shared rows to its cutoff inside its own kernels; a
+ * two-interaction one (the message-passing fast model) gets the shared list filtered to
+ * its cutoff (nnp_filter_neighbors) before each evaluation, so max_nbrs_small must hold
+ * its rows padded to 16.
  * dmts_state_forces: device pointers to the carried F_large and F_small (float32
  *   [3][n_atoms]) for inspection.
  */
