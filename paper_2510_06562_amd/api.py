@@ -211,6 +211,7 @@ class NeighborList:
         self._h = h
         self.max_atoms = max_atoms
         self.max_pairs = max_pairs
+        self.n_atoms = 0   # atoms of the last build
 
     @property
     def handle(self):
@@ -226,13 +227,16 @@ class NeighborList:
             n_sys = sys_offsets.numel() - 1
         _check(lib().nnp_build_neighbors(self._h, _ptr(pos_soa), n, float(box), _ptr(sys_offsets),
                                          n_sys, float(cutoff), _stream(stream)))
+        self.n_atoms = n
 
     def filter_from(self, parent: "NeighborList", pos_soa: torch.Tensor, cutoff: float,
                     stream=None):
-        """This list at `cutoff` (<= the parent's) from the parent's rows at pos_soa."""
-        _dev_check(pos_soa, torch.float64, (3, pos_soa.shape[1]), "pos")
+        """This list at `cutoff` (<= the parent's) from the parent's rows at pos_soa, which
+        holds the parent's atoms."""
+        _dev_check(pos_soa, torch.float64, (3, parent.n_atoms), "pos")
         _check(lib().nnp_filter_neighbors(self._h, parent.handle, _ptr(pos_soa), float(cutoff),
                                           _stream(stream)))
+        self.n_atoms = parent.n_atoms
 
     def flags(self, stream=None) -> int:
         f = ctypes.c_uint32()

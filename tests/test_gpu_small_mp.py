@@ -36,7 +36,7 @@ def test_filtered_list_equals_built_list(sysname):
     assert np.array_equal(oa, ob) and np.array_equal(na, nb) and np.array_equal(ra, rb)
 
 
-def test_filter_rejects_a_longer_cutoff():
+def test_filter_rejects_bad_arguments():
     sy = system("water192")
     pos = api.to_soa(sy.pos)
     parent = api.NeighborList(sy.n_atoms, sy.n_atoms * 64, 16)
@@ -45,6 +45,8 @@ def test_filter_rejects_a_longer_cutoff():
     with pytest.raises(api.DmtsError) as e:
         child.filter_from(parent, pos, 4.0)
     assert e.value.status == api.E_ARG
+    with pytest.raises(ValueError):   # positions of another atom count
+        child.filter_from(parent, pos[:, :10].contiguous(), 3.0)
 
 
 def test_small_mp_matches_oracle_water192(models):
