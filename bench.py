@@ -121,6 +121,9 @@ def parse():
                     help="fast model: one interaction (rc 3.5 A, F 64; default) or the "
                          "message-passing variant (two interactions as the reference model, "
                          "rc 3.5 A), which runs on the shared list filtered to 3.5 A")
+    ap.add_argument("--hmr", action="store_true",
+                    help="hydrogen mass repartitioning (3.024 amu hydrogens, mass taken from "
+                         "the nearest heavy atom) for every dynamics run")
     ap.add_argument("--n-inner", type=int, default=4)
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -164,10 +167,13 @@ def nve_drift(args, api, synth, sy, sp, v0, small, large):
     import torch
 
     out = {"mode": "nve-drift", "workload": args.workload, "n_atoms": sy.n_atoms,
-           "precision": args.precision, "ps": args.nve_ps}
+           "precision": args.precision, "ps": args.nve_ps, "hmr": args.hmr,
+           "fast_model": args.fast_model}
     for name, small_m, dt, n_in in (("dmts", small, args.dt_inner * args.n_inner, args.n_inner),
                                     ("verlet", None, args.dt_inner, 1)):
         st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt, n_in, 64, 128)
+        if args.hmr:
+            st.set_atom_masses(sy.hmr_masses())
         x, v = api.to_soa(sy.pos), api.to_soa(v0)
         n_steps = int(round(args.nve_ps * 1000.0 / dt))
         chunk = max(1, int(round(20.0 / dt)))   # sample every ~20 fs
@@ -281,7 +287,8 @@ def main():
     small = api.Model.from_spec(spec_s, ws, precision=prec)
     large = api.Model.from_spec(synth.LARGE, wl, precision=prec)
     sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
-    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201)
+    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201,
+                                 masses=sy.hmr_masses() if args.hmr else None)
     n_inner, dt_in = args.n_inner, args.dt_inner
     dt_out = n_inner * dt_in
     stream = torch.cuda.current_stream()
@@ -303,6 +310,8 @@ def main():
 
     # ---------------------------------------------------------------- DMTS timed region
     st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_out, n_inner, 64, 128)
+    if args.hmr:
+        st.set_atom_masses(sy.hmr_masses())
     if args.gamma > 0.0:
         st.set_thermostat(args.gamma, args.temperature, 2025)
     x, v = api.to_soa(sy.pos), api.to_soa(v0)
@@ -345,6 +354,8 @@ def main():
     vv = None
     if not args.no_verlet:
         st_v = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_in, 1, 64, 128)
+        if args.hmr:
+            st_v.set_atom_masses(sy.hmr_masses())
         if args.gamma > 0.0:
             st_v.set_thermostat(args.gamma, args.temperature, 2026)
         xv, vvel = api.to_soa(sy.pos), api.to_soa(v0)
@@ -418,6 +429,7 @@ def main():
                                   else "2 interactions, rc 3.5 A, K 32, F 128, l<=2"),
                    "reference_model": "2 interactions, rc 5.2 A, K 32, F 128, l<=2",
                    "integration": "f64",
+                   "masses": "repartitioned (HMR)" if args.hmr else "species",
                    "ensemble": ("NVE" if args.gamma <= 0.0 else
                                 f"Langevin gamma {args.gamma} /fs, {args.temperature} K"),
                    "mlp_operands": args.precision},

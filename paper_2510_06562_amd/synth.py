@@ -363,11 +363,13 @@ def unpack_weights(spec: ModelSpec, flat: np.ndarray) -> dict:
 
 # --------------------------------------------------------------------------- velocities
 def maxwell_boltzmann(species: np.ndarray, T: float, seed: int,
-                      sys_offsets: np.ndarray | None = None) -> np.ndarray:
+                      sys_offsets: np.ndarray | None = None,
+                      masses: np.ndarray | None = None) -> np.ndarray:
     """v ~ N(0, k_B T / m) per component in A/fs, centre-of-mass velocity removed (per
-    molecule when sys_offsets is given), not rescaled."""
+    molecule when sys_offsets is given), not rescaled.  m: the species masses, or the
+    per-atom `masses` when given (e.g. repartitioned)."""
     rng = _rng(seed)
-    m = MASSES[species]
+    m = MASSES[species] if masses is None else np.asarray(masses, dtype=np.float64)
     sd = np.sqrt(_EV_PER_K * T * _ANG_FS2_PER_EV_AMU / m)
     v = rng.standard_normal((len(species), 3)) * sd[:, None]
     offs = np.array([0, len(species)]) if sys_offsets is None else sys_offsets
