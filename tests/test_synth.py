@@ -68,3 +68,19 @@ def test_hmr_masses():
     assert mb[heavy].min() >= 3.024 - 1e-12
     assert mb[~heavy].min() >= synth.MASSES[synth.H] - 1e-12
     assert mb[~heavy].max() <= 3.024 + 1e-12
+
+
+def test_maxwell_boltzmann_with_atom_masses():
+    """Velocities drawn for per-atom masses have k_B T / m_i variance per component (the
+    same normals scaled by sqrt(m_species / m_i)) and zero total momentum."""
+    w = synth.water_4500()
+    m = w.hmr_masses()
+    v = synth.maxwell_boltzmann(w.species, 300.0, 5, masses=m)
+    v0 = synth.maxwell_boltzmann(w.species, 300.0, 5)
+    assert np.allclose((m[:, None] * v).sum(0), 0.0, atol=1e-9)
+    # before the centre-of-mass shift the two draws differ by the per-atom scale only
+    ratio = (v - v.mean(0)) / (v0 - v0.mean(0))
+    h = w.species == synth.H
+    assert abs(np.median(ratio[h]) - np.sqrt(1.008 / 3.024)) < 1e-3
+    kT_over_m = (8.617333262e-5 * 300.0) * (1.602176634e-19 / 1.66053906660e-27 * 1e-10) / m
+    assert abs(np.mean(v[h] ** 2 / kT_over_m[h, None]) - 1.0) < 0.05
