@@ -73,8 +73,9 @@ struct SmallLds {
 };
 
 // Staging of the LDS weights in two halves: fetch() issues the thread's global loads into
-// registers, store() writes them to LDS, so that independent work (the first receiver's
-// neighbor loads) can overlap the loads.
+// registers, store() writes them to LDS, so that independent work (the reverse kernel's
+// first receiver loads) can overlap the loads.  The forward kernel stores them at once:
+// holding them across its first receiver would raise its register peak.
 template <bool kReadout>
 struct Stager {
   static constexpr int kW = K_S * F_S, kT = Z_MAX * F_S, kR = kReadout ? F_S * F_S : 0;
@@ -129,9 +130,11 @@ __device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
   return acc;
 }
 
-// Four waves per SIMD: the registers are capped at 128.
+// Five waves per SIMD (registers capped at 102; the kernel needs 76-90 once the weights
+// are in LDS before the first receiver): five work-groups per CU by LDS as well, so the
+// 4,500-atom box runs in one round.
 template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
 k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
             const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
             double box, float* __restrict__ atom_e, float* __restrict__ g_out,
@@ -141,9 +144,12 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
   __shared__ int sZ[kWaves][kCap];
   __shared__ float4 sG[kWaves][kCap];
   __shared__ float sVec[kWaves][F_S];
-  Stager<true> stage;
-  stage.fetch(P);
-  bool staged = false;
+  {
+    Stager<true> stage;
+    stage.fetch(P);
+    stage.store(L);
+  }
+  __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const double inv_box = box > 0.0 ? 1.0 / box : 0.0;
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
@@ -185,11 +191,6 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
       cnt = kCap;
     }
     if (lane == 0) ell_n[i] = cnt;
-    }
-    if (!staged) {   // the weights, once per work-group, after the first receivers' loads
-      stage.store(L);
-      __syncthreads();
-      staged = true;
     }
     if (!act) continue;
     wave_sync();
