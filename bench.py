@@ -255,7 +255,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
-              "single-GPU in this build (see DESIGN.md for how it would shard).", file=sys.stderr)
+              "single-GPU: one process drives one device.", file=sys.stderr)
         sys.exit(2)
 
     import torch
