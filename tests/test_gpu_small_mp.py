@@ -86,3 +86,31 @@ def test_dmts_with_small_mp_matches_oracle_water192(models):
     dv = np.max(np.abs(api.from_soa(v) - o.v))
     say(f"  max |dx| {dx:.2e}, max |dv| {dv:.2e}")
     assert dx < 1e-7 and dv < 1e-8
+
+
+def test_small_mp_exact_fallback(models):
+    """An atom that leaves the shared list's skin within one call: the call is redone with
+    exact lists (the fast list then built at 3.5 A, 16-padded as the reference kernels
+    need) and still follows the oracle's Algorithm 1."""
+    say("message-passing fast model, shared-list fallback")
+    sy = system("water192")
+    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 200)
+    v0[7] = [0.35, 0.0, 0.0]          # 1.4 A per 4 fs outer step (skin half-width 0.85 A)
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, 4.0, 4, 48, 128)
+    x, v = api.to_soa(sy.pos), api.to_soa(v0)
+    st.step(x, v, models["small_mp"], models["large"], 1)
+    assert st.fallbacks == 1
+    o = OI.MTSState(x=sy.pos.copy(), v=v0.copy(), m=sy.masses())
+
+    def force(which):
+        m = oracle_model(which)
+
+        def f(xx):
+            E, F, _ = OP.energy_forces(m, xx, sy.species, sy.box)
+            return E[0], F
+        return f
+    OI.mts_step(o, 4.0, 4, force("small_mp"), force("large"))
+    dx = np.max(np.abs(api.from_soa(x) - o.x))
+    say(f"  max |dx| {dx:.2e}")
+    assert dx < 1e-7
