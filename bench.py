@@ -124,6 +124,9 @@ def parse():
     ap.add_argument("--hmr", action="store_true",
                     help="hydrogen mass repartitioning (3.024 amu hydrogens, mass taken from "
                          "the nearest heavy atom) for every dynamics run")
+    ap.add_argument("--distill", action="store_true",
+                    help="fit the fast model's readout vector to the reference forces on "
+                         "four snapshots of a 100 fs reference-model run before timing")
     ap.add_argument("--n-inner", type=int, default=4)
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -168,7 +171,7 @@ def nve_drift(args, api, synth, sy, sp, v0, small, large):
 
     out = {"mode": "nve-drift", "workload": args.workload, "n_atoms": sy.n_atoms,
            "precision": args.precision, "ps": args.nve_ps, "hmr": args.hmr,
-           "fast_model": args.fast_model}
+           "fast_model": args.fast_model, "distilled": args.distill}
     for name, small_m, dt, n_in in (("dmts", small, args.dt_inner * args.n_inner, args.n_inner),
                                     ("verlet", None, args.dt_inner, 1)):
         st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt, n_in, 64, 128)
@@ -284,11 +287,19 @@ def main():
     ws = synth.model_weights(spec_s, seed_s)
     wl = synth.model_weights(synth.LARGE, synth.LARGE_SEED)
     prec = api.PREC_BF16 if args.precision == "bf16" else api.PREC_FP32
-    small = api.Model.from_spec(spec_s, ws, precision=prec)
     large = api.Model.from_spec(synth.LARGE, wl, precision=prec)
     sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
     v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201,
                                  masses=sy.hmr_masses() if args.hmr else None)
+    distilled = None
+    if args.distill:
+        from paper_2510_06562_amd import distill
+        snaps = distill.reference_snapshots(large, sp, sy.box, synth.MASSES, sy.pos, v0, 4, 25)
+        ws, distilled = distill.fit_readout(spec_s, ws, large, sp, sy.box, snaps,
+                                            precision=prec)
+        print(f"distilled readout: rms |F_L - F_S| {distilled['rms_before']:.5f} -> "
+              f"{distilled['rms_after']:.5f} eV/A", file=sys.stderr, flush=True)
+    small = api.Model.from_spec(spec_s, ws, precision=prec)
     n_inner, dt_in = args.n_inner, args.dt_inner
     dt_out = n_inner * dt_in
     stream = torch.cuda.current_stream()
@@ -442,6 +453,7 @@ def main():
         "pairs": {"fast": pairs_small, "reference": pairs_large},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "distilled_readout": distilled,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
