@@ -40,14 +40,20 @@ def readout_design(spec, weights: np.ndarray, species: torch.Tensor, box: float,
     readout vector replaced by the unit vector e_c."""
     F = spec.width
     n = snapshots[0].shape[1]
+    # one list per snapshot, shared by the unit-readout models
+    lists = []
+    for x in snapshots:
+        nl = api.NeighborList(n, n * (128 + 16), 16)
+        nl.build(x, box, spec.cutoff)
+        lists.append(nl)
     cols = np.empty((len(snapshots) * 3 * n, F), dtype=np.float64)
     for c in range(F):
         w = np.array(weights, dtype=np.float32, copy=True)
         w[-F:] = 0.0
         w[-F + c] = 1.0
-        pot = api.Potential(api.Model.from_spec(spec, w, precision=precision), n, box, 128)
-        for s, x in enumerate(snapshots):
-            f = pot(x, species)[1]
+        model = api.Model.from_spec(spec, w, precision=precision)
+        for s, (x, nl) in enumerate(zip(snapshots, lists)):
+            f = api.energy_forces(model, nl, x, species, box)[1]
             cols[s * 3 * n:(s + 1) * 3 * n, c] = f.double().cpu().numpy().ravel()
     return cols
 
