@@ -105,6 +105,103 @@ def test_small_dimer_closed_form_width_one():
     assert E[0] == pytest.approx(E_ref, rel=1e-13)
 
 
+def _trimer_closed_form(w, pos, z, rc=5.2, K=4, scale=0.7, residual=True, swap=False):
+    """Per-atom energies of a one-channel two-interaction model, written out with math.*
+    scalars from the model's definition (Methods: neural network architectures, as read
+    here): layer 1 on [b; e_i; e_j], q = [M0; |M1|^2; |M2|_F^2], h1 = SiLU(U1 q1), layer 2
+    on [b; h1_i; h1_j], h2 = h1 + SiLU(U2 q2), E_i = s_E w_o SiLU(W_o h2).  `residual` and
+    `swap` plant the two mistakes the pin must catch (no residual; receiver and sender
+    blocks of layer 2 exchanged)."""
+    silu = lambda t: t / (1 + math.exp(-t))  # noqa: E731
+    sig = rc / (K - 1)
+    n = len(pos)
+
+    def pair(i, j):
+        d = [pos[j][a] - pos[i][a] for a in range(3)]
+        r = math.sqrt(sum(x * x for x in d))
+        b = [math.exp(-(r - k * sig) ** 2 / (2 * sig * sig)) for k in range(K)]
+        fc = 0.5 * (math.cos(math.pi * r / rc) + 1)
+        return [x / rc for x in d], b, fc
+
+    def layer(Wp, feat_i, feat_j):
+        """q of every atom for messages m_ij = fc SiLU(Wp [b; s_i; s_j])."""
+        q = []
+        for i in range(n):
+            M0, M1, M2 = 0.0, [0.0] * 3, [[0.0] * 3 for _ in range(3)]
+            for j in range(n):
+                if j == i:
+                    continue
+                u, b, fc = pair(i, j)
+                a = sum(Wp[k] * b[k] for k in range(K))
+                a += sum(Wp[K + e] * x for e, x in enumerate(feat_i(i)))
+                a += sum(Wp[K + len(feat_i(i)) + e] * x for e, x in enumerate(feat_j(j)))
+                m = fc * silu(a)
+                u2 = sum(x * x for x in u)
+                M0 += m
+                for p in range(3):
+                    M1[p] += m * u[p]
+                    for s in range(3):
+                        M2[p][s] += m * (u[p] * u[s] - (u2 / 3.0 if p == s else 0.0))
+            q.append([M0, sum(x * x for x in M1), sum(x * x for row in M2 for x in row)])
+        return q
+
+    emb = w["emb"]
+    q1 = layer(w["W_pair1"][0], lambda i: list(emb[z[i]]), lambda j: list(emb[z[j]]))
+    h1 = [silu(sum(w["U1"][0][c] * q1[i][c] for c in range(3))) for i in range(n)]
+    W2 = list(w["W_pair2"][0])
+    if swap:
+        W2[K], W2[K + 1] = W2[K + 1], W2[K]
+    q2 = layer(W2, lambda i: [h1[i]], lambda j: [h1[j]])
+    E = []
+    for i in range(n):
+        t = silu(sum(w["U2"][0][c] * q2[i][c] for c in range(3)))
+        h2 = h1[i] + t if residual else t
+        E.append(scale * w["w_out2"][0] * silu(w["W_out1"][0][0] * h2))
+    return E
+
+
+TRIMER = np.array([[0.0, 0.0, 0.0], [1.9, 0.3, -0.2], [0.4, 2.6, 0.9]])   # all pairs < 5.2 A
+TRIMER_Z = np.array([0, 3, 1])                                            # H, O, C
+
+
+def test_large_trimer_closed_form_width_one():
+    """The two-interaction model with one channel on an open trimer of three species: the
+    oracle's per-atom energies equal the scalar expression above, and its forces equal
+    central differences of that expression (independent of the oracle's reverse pass)."""
+    m = _model(1, cutoff=5.2, K=4, F=1, D=2, seed=11, scale=0.7)
+    E_ref = _trimer_closed_form(m.w, TRIMER.tolist(), TRIMER_Z)
+    _, F, Ea = P.energy_forces(m, TRIMER, TRIMER_Z, 0.0)
+    np.testing.assert_allclose(Ea, E_ref, rtol=1e-13, atol=0)
+    h = 1e-5
+    fd = np.zeros((3, 3))
+    for a in range(3):
+        for c in range(3):
+            xp, xm = TRIMER.copy(), TRIMER.copy()
+            xp[a, c] += h
+            xm[a, c] -= h
+            fd[a, c] = -(sum(_trimer_closed_form(m.w, xp.tolist(), TRIMER_Z))
+                         - sum(_trimer_closed_form(m.w, xm.tolist(), TRIMER_Z))) / (2 * h)
+    np.testing.assert_allclose(F, fd, rtol=0, atol=1e-9 * np.abs(F).max())
+
+
+def test_large_trimer_pin_catches_planted_mistakes():
+    """Each planted mistake moves the energies far outside the pin's 1e-13: a layer 2 that
+    reads [b; h1_j; h1_i] (planted in the oracle by exchanging the receiver and sender
+    columns of W_pair2), and an update without the residual h1 (planted in the scalar
+    expression, which the oracle's value must then miss)."""
+    m = _model(1, cutoff=5.2, K=4, F=1, D=2, seed=11, scale=0.7)
+    E_ref = np.array(_trimer_closed_form(m.w, TRIMER.tolist(), TRIMER_Z))
+    bad = P.Model(**{**m.__dict__, "w": dict(m.w)})
+    bad.w["W_pair2"] = m.w["W_pair2"][:, [0, 1, 2, 3, 5, 4]]
+    Ea_bad = P.energy_forces(bad, TRIMER, TRIMER_Z, 0.0)[2]
+    assert np.max(np.abs(Ea_bad - E_ref) / np.abs(E_ref)) > 1e-6
+    E_swap = np.array(_trimer_closed_form(m.w, TRIMER.tolist(), TRIMER_Z, swap=True))
+    np.testing.assert_allclose(Ea_bad, E_swap, rtol=1e-13)   # the planted oracle = the mutant
+    E_nores = np.array(_trimer_closed_form(m.w, TRIMER.tolist(), TRIMER_Z, residual=False))
+    Ea = P.energy_forces(m, TRIMER, TRIMER_Z, 0.0)[2]
+    assert np.max(np.abs(E_nores - Ea) / np.abs(Ea)) > 1e-6
+
+
 def test_large_angular_invariants_follow_legendre_addition():
     """For a centre with two neighbours u, w at angle theta:
        |m1 u + m2 w|^2 = m1^2|u|^2 + m2^2|w|^2 + 2 m1 m2 |u||w| P1(cos theta)
