@@ -191,7 +191,8 @@ dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos
  * v <- c v + sqrt((1 - c^2) k_B T KAPPA / m) xi with c = exp(-gamma h), off (the
  * identity: NVE) unless dmts_state_set_thermostat gave gamma > 0.
  * Both forces are evaluated on the first step only and carried between calls
- * afterwards.  With small == NULL the call runs the single-time-step baseline instead:
+ * afterwards (for the same two models: a call with another model, or with a model created
+ * since, evaluates both afresh).  With small == NULL the call runs the single-time-step baseline instead:
  * BAOAB with the large model at dt_outer (velocity Verlet when gamma = 0; n_inner is
  * ignored).
  *
@@ -261,17 +262,20 @@ dmts_status dmts_state_o_steps(dmts_state* st, uint64_t* n_o_steps);
 
 /* Force-difference monitor (the paper's guard against holes in the fast model: where
  * |F - F_small| of an atom exceeds an unphysical threshold, 150 kcal/mol/A = 6.505 eV/A in
- * the paper, the integrator temporarily reverts to single-time-step integration).
+ * the paper, the integrator temporarily reverts to single-time-step integration; Results,
+ * protein-ligand complexes).
  * dmts_state_set_fdiff_threshold: eV_per_A > 0 turns the check on (0, the default, off;
- *   DMTS_E_ARG for a negative or non-finite value).  Every slow kick of dmts_step tests
- *   |F_i - F_small,i| of each atom; when any atom exceeds the threshold, the call restores
- *   its starting x, v and carried forces and redoes its n_outer outer steps as
- *   n_outer * n_inner single-time-step steps of length dt_outer / n_inner with the
- *   reference model (same O-step numbers; E_small is not refreshed by such a call), and the
- *   next call evaluates both models afresh.  With the monitor on, every call backs up its
- *   starting state and reads the device flags once more.
- * dmts_state_fdiff: the number of calls redone that way, and the largest breaching
- *   |F - F_small| (eV/A) of the last call that checked (0 if none breached).
+ *   DMTS_E_ARG for a negative or non-finite value).  With the check on, dmts_step takes its
+ *   n_outer outer steps one at a time: both slow kicks of a step test |F_i - F_small,i| of
+ *   every atom, and when any atom exceeds the threshold the step is rolled back to its
+ *   starting x, v and carried forces and redone as n_inner single-time-step steps of length
+ *   dt_outer / n_inner with the reference model (same O-step numbers); the next step then
+ *   evaluates both models afresh.  A breach seen while a step is redone with exact lists
+ *   (neighbor-list note) is acted on the same way.  Each step backs up its starting state
+ *   and reads the device flags once (one host synchronization per outer step).
+ * dmts_state_fdiff: the number of outer steps redone that way since the state was created,
+ *   and the largest breaching |F - F_small| (eV/A) seen by the last dmts_step call (0 if
+ *   none breached).
  */
 dmts_status dmts_state_set_fdiff_threshold(dmts_state* st, double eV_per_A);
 dmts_status dmts_state_fdiff(dmts_state* st, int64_t* n_sts_redos, double* last_breach);

@@ -125,6 +125,44 @@ def sts_step(st: MTSState, dt: float, force: ForceFn,
     return st
 
 
+def _max_force_difference(st: MTSState) -> float:
+    """max_i |F_i - F_small,i| (eV/A) at the state's positions."""
+    return float(np.max(np.linalg.norm(st.F - st.F_small, axis=1)))
+
+
+def mts_step_monitored(st: MTSState, dt: float, n_slow: int, small: ForceFn, large: ForceFn,
+                       threshold: float) -> tuple:
+    """One outer step of Algorithm 1 guarded by the force-difference check of the paper's
+    protein-ligand runs (Results: frames whose per-atom |F - F_small| exceeds an
+    unphysical threshold, 150 kcal/mol/A, are integrated with single time steps instead).
+    Reading used here: the outer step is taken as usual; if either of its two slow kicks
+    sees an atom with |F - F_small| > threshold, the step is discarded and redone from its
+    starting state as n_slow single-time-step steps of dt/n_slow with the reference model,
+    after which both forces are evaluated afresh.  NVE only (no thermostat).
+    Returns (state, worst, redone): worst is the largest |F - F_small| of the RESPA step's
+    two kicks (kept or discarded), redone whether it was replaced."""
+    start = MTSState(x=st.x.copy(), v=st.v.copy(), m=st.m,
+                     F=None if st.F is None else st.F.copy(),
+                     F_small=None if st.F_small is None else st.F_small.copy(),
+                     E=st.E, E_small=st.E_small, first_step=st.first_step)
+    trial = MTSState(x=st.x.copy(), v=st.v.copy(), m=st.m, F=start.F, F_small=start.F_small,
+                     E=st.E, E_small=st.E_small, first_step=st.first_step)
+    if trial.first_step:
+        trial.E_small, trial.F_small = small(trial.x)
+        trial.E, trial.F = large(trial.x)
+        trial.first_step = False
+    worst = _max_force_difference(trial)                      # the opening slow kick
+    mts_step(trial, dt, n_slow, small, large)
+    worst = max(worst, _max_force_difference(trial))          # the closing slow kick
+    if worst <= threshold:
+        return trial, worst, False
+    redo = MTSState(x=start.x, v=start.v, m=st.m, first_step=True)
+    for _ in range(n_slow):
+        sts_step(redo, dt / n_slow, large)
+    redo.first_step = True   # the next outer step evaluates both models afresh
+    return redo, worst, True
+
+
 def conserved_energy(st: MTSState) -> float:
     """H = KE + E_reference (the quantity NVE dynamics conserves)."""
     return kinetic_energy(st.v, st.m) + st.E

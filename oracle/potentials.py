@@ -300,6 +300,32 @@ def energy_forces(model: Model, pos, species, box: float, sys_offsets=None, pair
     return _system_sums(E_atom, pos.shape[0], sys_offsets), F, E_atom
 
 
+def readout_magnitude(model: Model, pos, species, box: float, sys_offsets=None) -> np.ndarray:
+    """Per-atom s_E sum_c |w_c SiLU(z_c)|: the size of the terms the readout adds up to
+    E_i = s_E sum_c w_c SiLU(z_c) (z = W_atom1 h for the fast model, W_out1 h^2 for the
+    reference model).  Rounding the readout's operands to a precision u moves E_i by a
+    multiple of u times this, whatever the cancellation in E_i itself."""
+    pos = np.asarray(pos, dtype=np.float64)
+    species = np.asarray(species, dtype=np.int64)
+    i, j, d = _pairs(pos, box, model.cutoff, sys_offsets)
+    w = model.w
+    n = pos.shape[0]
+    if model.kind == 0:
+        h = np.zeros((n, model.width))
+        for s in range(0, len(i), _CHUNK):
+            sl = slice(s, s + _CHUNK)
+            _, b, _, fc, _ = _pair_geometry(model, d[sl])
+            feat = np.concatenate([b, w["emb"][species[i[sl]]], w["emb"][species[j[sl]]]], axis=1)
+            np.add.at(h, i[sl], fc[:, None] * silu(feat @ w["W_pair"].T))
+        z, wo = h @ w["W_atom1"].T, w["w_atom2"]
+    else:
+        s1 = w["emb"][species]
+        h1 = silu(invariants(*_moments_layer(model, w["W_pair1"], s1, i, j, d, n)) @ w["U1"].T)
+        q2 = invariants(*_moments_layer(model, w["W_pair2"], h1, i, j, d, n))
+        z, wo = (h1 + silu(q2 @ w["U2"].T)) @ w["W_out1"].T, w["w_out2"]
+    return model.energy_scale * (np.abs(silu(z)) @ np.abs(wo))
+
+
 def large_layer1_invariants(model: Model, pos, species, box: float, sys_offsets=None):
     """q^1 of the two-interaction model (exposed for the closed-form angular checks)."""
     pos = np.asarray(pos, dtype=np.float64)

@@ -280,20 +280,35 @@ def energy_forces(model: Model, nlist: NeighborList, pos_soa: torch.Tensor,
 
 
 class Potential:
-    """A model with its own neighbor list: ``pot(pos_soa) -> (E, F)``."""
+    """A model with its own neighbor list: ``pot(pos_soa) -> (E, F)``.
+
+    With ``check`` (the default) every call reads the list's device flag word afterwards
+    (one synchronization) and raises DmtsError(E_CAPACITY) when a row or the list
+    overflowed, so that truncated sums never pass silently; ``check=False`` leaves that to
+    the caller (``nlist.flags()``)."""
 
     def __init__(self, model: Model, max_atoms: int, box: float, max_nbrs: int = 128,
-                 sys_offsets: Optional[torch.Tensor] = None):
+                 sys_offsets: Optional[torch.Tensor] = None, check: bool = True):
         self.model = model
         self.box = box
         self.sys_offsets = sys_offsets
+        self.check = check
         self.nlist = NeighborList(max_atoms, max_atoms * (max_nbrs + 16), 16)
 
     def __call__(self, pos_soa: torch.Tensor, species: torch.Tensor, want_forces=True,
                  atom_energy=False, stream=None):
         self.nlist.build(pos_soa, self.box, self.model.desc.cutoff, self.sys_offsets, stream)
-        return energy_forces(self.model, self.nlist, pos_soa, species, self.box,
-                             self.sys_offsets, want_forces, atom_energy, stream)
+        out = energy_forces(self.model, self.nlist, pos_soa, species, self.box,
+                            self.sys_offsets, want_forces, atom_energy, stream)
+        if self.check:
+            f = self.nlist.flags(stream)
+            if f & FLAG_NBR_OVERFLOW:
+                raise DmtsError(E_CAPACITY, "neighbor list overflow: a row held more "
+                                "neighbors than the kernels take (or the list its capacity); "
+                                "the forces would be truncated")
+            if f & FLAG_NONFINITE:
+                raise DmtsError(E_NONFINITE, "non-finite value met in the evaluation")
+        return out
 
 
 def autotune(potential: "Potential", pos_soa: torch.Tensor, species: torch.Tensor,
@@ -314,19 +329,30 @@ def autotune(potential: "Potential", pos_soa: torch.Tensor, species: torch.Tenso
 
 class NNPEnergy(torch.autograd.Function):
     """E = NNPEnergy.apply(pos_soa, potential, species): forward returns the energy per
-    system; backward returns -F * grad_E (the library's analytic forces)."""
+    system ([n_sys], float64); backward returns dL/dx = -F_i * dL/dE_s(i) for every atom i
+    of system s(i) (the library's analytic forces; atoms outside every system get zero)."""
 
     @staticmethod
     def forward(ctx, pos_soa, potential: Potential, species):
         E, F = potential(pos_soa.detach(), species, want_forces=True)
         ctx.save_for_backward(F)
+        ctx.sys_offsets = potential.sys_offsets
         return E
 
     @staticmethod
     def backward(ctx, grad_E):
         (F,) = ctx.saved_tensors
-        g = grad_E.sum().to(torch.float64) if grad_E.numel() > 1 else grad_E.reshape(()).to(torch.float64)
-        return -(F.to(torch.float64) * g), None, None
+        n = F.shape[1]
+        g = grad_E.reshape(-1).to(torch.float64)
+        offs = ctx.sys_offsets
+        if offs is None:
+            g_atom = g.expand(n)
+        else:
+            o = offs.to(device=F.device, dtype=torch.int64)
+            g_atom = torch.zeros(n, dtype=torch.float64, device=F.device)
+            lo, hi = int(o[0]), int(o[-1])
+            g_atom[lo:hi] = torch.repeat_interleave(g, o[1:] - o[:-1], output_size=hi - lo)
+        return -(F.to(torch.float64) * g_atom[None, :]), None, None
 
 
 # ------------------------------------------------------------------ dynamics

@@ -1,6 +1,7 @@
 // Library glue: error reporting, device buffers, model creation (weight re-layout) and the
 // energy/force entry point.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstring>
 #include <map>
@@ -322,6 +323,8 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
                "nnp_model_create: %lld weights given, %zu expected", (long long)n_weights, expect);
 
   Model* m = new Model();
+  static std::atomic<uint64_t> next_generation{1};
+  m->generation = next_generation.fetch_add(1);
   m->desc = d;
   m->K = K;
   m->F = F;

@@ -109,6 +109,9 @@ struct Model {
   // launch: work-groups of the pair kernels (0 = one per group of receivers); the pair
   // kernels loop over receivers in a grid-stride order, so any count gives the same bits
   int32_t grid = 0;
+  // distinct for every model created in the process (never 0): a RESPA state compares it to
+  // know whether its carried forces belong to this model
+  uint64_t generation = 0;
   // workspace
   DevBuf atom_ws, pair_ws, sys_ws;
   // natural: work-groups for one pass over the receivers; resident: how many the GPU holds

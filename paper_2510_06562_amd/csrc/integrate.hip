@@ -145,9 +145,9 @@ struct State {
   double* e_models = nullptr;   // {E_large, E_small}
   double* ke_part = nullptr;    // per-chunk kinetic energy sums
   uint32_t* flags = nullptr;
-  // models the carried forces belong to
-  Model* last_small = nullptr;
-  Model* last_large = nullptr;
+  // generations of the models the carried forces belong to (0: none)
+  uint64_t last_small = 0;
+  uint64_t last_large = 0;
   int64_t n_fallbacks = 0;   // calls redone with exact lists
 };
 
@@ -610,6 +610,104 @@ extern "C" dmts_status dmts_state_flags(dmts_state* h, void* stream, uint32_t* h
   return DMTS_OK;
 }
 
+namespace dmts {
+namespace {
+
+// Host copy of the state a roll-back returns to: x, v (and the carried forces unless the
+// next run evaluates both models afresh) go to the state's backup buffer.
+dmts_status backup(State* st, const double* x, const double* v, bool forces, hipStream_t s) {
+  const int64_t n3 = 3 * (int64_t)st->n;
+  double* b = st->bak;
+  k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(x, b, n3);
+  k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(v, b + n3, n3);
+  if (forces) {   // carried forces: 2 x 3n floats = 3n doubles
+    DMTS_HIP(hipMemcpyAsync(b + 2 * n3, st->FL, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+    DMTS_HIP(hipMemcpyAsync(reinterpret_cast<float*>(b + 2 * n3) + n3, st->Fs,
+                            sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+  }
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+dmts_status restore(State* st, double* x, double* v, bool forces, hipStream_t s) {
+  const int64_t n3 = 3 * (int64_t)st->n;
+  double* b = st->bak;
+  k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(b, x, n3);
+  k_copy_f64<<<ceil_div(n3, 256), 256, 0, s>>>(b + n3, v, n3);
+  if (forces) {
+    DMTS_HIP(hipMemcpyAsync(st->FL, b + 2 * n3, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+    DMTS_HIP(hipMemcpyAsync(st->Fs, reinterpret_cast<float*>(b + 2 * n3) + n3,
+                            sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+  }
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+// The state's flag word and largest recorded force difference (synchronizes the stream).
+dmts_status read_flags(State* st, bool monitor, hipStream_t s, uint32_t& f, float& fdiff) {
+  DMTS_HIP(hipMemcpyAsync(&f, st->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  uint32_t fm = 0;
+  if (monitor)
+    DMTS_HIP(hipMemcpyAsync(&fm, st->fdiff_max, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  DMTS_HIP(hipStreamSynchronize(s));
+  std::memcpy(&fdiff, &fm, sizeof(fdiff));
+  return DMTS_OK;
+}
+
+// n_outer outer steps of Algorithm 1 taken as one attempt that may be rolled back:
+//  * an atom moved beyond the shared list's skin (shared mode): restore the starting state
+//    and redo with exact lists for every evaluation;
+//  * a slow kick saw |F - F_small| above the monitor's threshold (in the first attempt or
+//    in the redo with exact lists): restore and redo as n_outer * n_inner single-time-step
+//    steps of the inner length with the reference model (the paper's reversion).
+// Either redo leaves lists or forces that are not the carried ones, so the next attempt
+// evaluates both models afresh.
+dmts_status checked_steps(State* st, double* x, double* v, Model* small, Model* large,
+                          int n_outer, const Runner& proto, bool monitor, hipStream_t s) {
+  const bool first0 = st->first;
+  const uint64_t o_count0 = st->o_count;
+  dmts_status r;
+  if (monitor && (r = fill_u32(st->fdiff_max, 0u, 1, s)) != DMTS_OK) return r;
+  if ((r = backup(st, x, v, !first0, s)) != DMTS_OK) return r;
+  Runner R = proto;
+  if ((r = run_steps(st, R, small, large, n_outer)) != DMTS_OK) return r;
+  uint32_t f = 0;
+  float fd = 0.f;
+  if ((r = read_flags(st, monitor, s, f, fd)) != DMTS_OK) return r;
+  constexpr uint32_t kRedo = kFlagStale | kFlagFdiff;
+  if ((f & kFlagStale) && !(f & kFlagFdiff)) {
+    if ((r = restore(st, x, v, !first0, s)) != DMTS_OK) return r;
+    st->first = first0;
+    st->o_count = o_count0;   // the same thermostat noise
+    if ((r = fill_u32(st->flags, f & ~kRedo, 1, s)) != DMTS_OK) return r;
+    ++st->n_fallbacks;
+    Runner E{st, x, v, s};    // exact lists for every evaluation
+    if ((r = run_steps(st, E, small, large, n_outer)) != DMTS_OK) return r;
+    st->first = true;
+    uint32_t f2 = 0;
+    if ((r = read_flags(st, monitor, s, f2, fd)) != DMTS_OK) return r;
+    f = (f & ~kRedo) | f2;    // a breach seen by the redo is acted on below
+  }
+  if (f & kFlagFdiff) {
+    st->last_fdiff = std::max(st->last_fdiff, fd);
+    if ((r = restore(st, x, v, !first0, s)) != DMTS_OK) return r;
+    st->first = first0;
+    st->o_count = o_count0;
+    if ((r = fill_u32(st->flags, f & ~kRedo, 1, s)) != DMTS_OK) return r;
+    ++st->n_sts_redos;
+    Runner E{st, x, v, s};
+    if ((r = run_steps(st, E, nullptr, large, n_outer * st->n_inner, st->dt / st->n_inner)) !=
+        DMTS_OK)
+      return r;
+    // the single-time-step steps leave F_small behind: the next attempt evaluates both
+    st->first = true;
+  }
+  return DMTS_OK;
+}
+
+}  // namespace
+}  // namespace dmts
+
 extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model* small_h,
                                  nnp_model* large_h, int32_t n_outer, double* energies_out,
                                  void* stream) {
@@ -621,12 +719,13 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
   DMTS_REQUIRE(large->desc.cutoff < 0.5 * st->box || st->box == 0.0, DMTS_E_BOX,
                "dmts_step: cutoff %g must be below half the box edge", large->desc.cutoff);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (small != st->last_small || large != st->last_large) st->first = true;
-  st->last_small = small;
-  st->last_large = large;
+  // carried forces belong to the models (by identity, not address) they were computed with
+  const uint64_t gs = small ? small->generation : 0, gl = large->generation;
+  if (gs != st->last_small || gl != st->last_large) st->first = true;
+  st->last_small = gs;
+  st->last_large = gl;
   dmts::Runner R{st, x, v, s};
   dmts_status r;
-  const int64_t n3 = 3 * (int64_t)st->n;
   if (small) {
     const double want = std::max((double)large->desc.cutoff,
                                  (double)small->desc.cutoff + dmts::kMinSkin);
@@ -637,71 +736,18 @@ extern "C" dmts_status dmts_step(dmts_state* h, double* x, double* v, nnp_model*
       R.max_disp2 = half_skin * half_skin;
     }
   }
-  // starting state, for the rare roll-back of a shared-list call or of a call whose
-  // force difference breached the monitor's threshold
-  const bool first0 = st->first;
-  const uint64_t o_count0 = st->o_count;
   const bool monitor = small && st->fdiff_thr > 0.0;
+  if (monitor) st->last_fdiff = 0.f;
   if (monitor) {
-    if ((r = dmts::fill_u32(st->fdiff_max, 0u, 1, s)) != DMTS_OK) return r;
-  }
-  if (R.shared || monitor) {
-    double* b = st->bak;
-    dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(x, b, n3);
-    dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(v, b + n3, n3);
-    if (!first0) {   // carried forces: 2 x 3n floats = 3n doubles
-      DMTS_HIP(hipMemcpyAsync(b + 2 * n3, st->FL, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
-      DMTS_HIP(hipMemcpyAsync(reinterpret_cast<float*>(b + 2 * n3) + n3, st->Fs,
-                              sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
-    }
-    DMTS_CHECK_LAUNCH();
-  }
-  if ((r = dmts::run_steps(st, R, small, large, n_outer)) != DMTS_OK) return r;
-  if (R.shared || monitor) {
-    uint32_t f = 0;
-    DMTS_HIP(hipMemcpyAsync(&f, st->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    if (monitor) {
-      uint32_t fm = 0;
-      DMTS_HIP(hipMemcpyAsync(&fm, st->fdiff_max, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      DMTS_HIP(hipStreamSynchronize(s));
-      float fv;
-      std::memcpy(&fv, &fm, sizeof(fv));
-      st->last_fdiff = fv;
-    }
-    DMTS_HIP(hipStreamSynchronize(s));
-    if (f & (dmts::kFlagStale | dmts::kFlagFdiff)) {
-      // an atom moved beyond the shared list's skin: restore and redo with exact lists;
-      // |F - F_small| above the threshold: restore and redo as single-time-step steps of
-      // the inner length with the reference model (the paper's temporary reversion)
-      const bool sts = (f & dmts::kFlagFdiff) != 0;
-      double* b = st->bak;
-      dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(b, x, n3);
-      dmts::k_copy_f64<<<dmts::ceil_div(n3, 256), 256, 0, s>>>(b + n3, v, n3);
-      if (!first0) {
-        DMTS_HIP(hipMemcpyAsync(st->FL, b + 2 * n3, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
-        DMTS_HIP(hipMemcpyAsync(st->Fs, reinterpret_cast<float*>(b + 2 * n3) + n3,
-                                sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
-      }
-      DMTS_CHECK_LAUNCH();
-      st->first = first0;
-      st->o_count = o_count0;   // the same thermostat noise
-      if ((r = dmts::fill_u32(st->flags, f & ~(dmts::kFlagStale | dmts::kFlagFdiff), 1, s)) !=
-          DMTS_OK)
-        return r;
-      dmts::Runner E{st, x, v, s};
-      if (sts) {
-        ++st->n_sts_redos;
-        if ((r = dmts::run_steps(st, E, nullptr, large, n_outer * st->n_inner,
-                                 st->dt / st->n_inner)) != DMTS_OK)
-          return r;
-      } else {
-        ++st->n_fallbacks;
-        if ((r = dmts::run_steps(st, E, small, large, n_outer)) != DMTS_OK) return r;
-      }
-      // the exact lists of this call are not the shared list (and a single-time-step redo
-      // leaves F_small behind): the next call starts by evaluating both models
-      st->first = true;
-    }
+    // the monitor decides per outer step: one checked attempt per step
+    for (int o = 0; o < n_outer; ++o)
+      if ((r = dmts::checked_steps(st, x, v, small, large, 1, R, true, s)) != DMTS_OK) return r;
+    if (n_outer == 0 && (r = dmts::run_steps(st, R, small, large, 0)) != DMTS_OK) return r;
+  } else if (R.shared) {
+    if ((r = dmts::checked_steps(st, x, v, small, large, n_outer, R, false, s)) != DMTS_OK)
+      return r;
+  } else if ((r = dmts::run_steps(st, R, small, large, n_outer)) != DMTS_OK) {
+    return r;
   }
   {
     const int nc = (st->n + dmts::kKeChunk - 1) / dmts::kKeChunk;

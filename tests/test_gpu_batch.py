@@ -94,7 +94,11 @@ def test_single_system_sum_matches_one_system_batch(which):
     forces do not depend on the offsets either."""
     say(f"energy reduction forms {which}")
     sy = system("batch256")   # all ~18,000 atoms as one open system (several chunks)
-    pos = api.to_soa(sy.pos)
+    # the molecules are centred at the origin: spread them 30 A apart on a grid, so that the
+    # single system has no pairs across molecules (and no row beyond the kernels' caps)
+    mol = np.repeat(np.arange(256), np.diff(sy.sys_offsets))
+    grid = np.stack([mol % 7, (mol // 7) % 7, mol // 49], axis=1) * 30.0
+    pos = api.to_soa(sy.pos + grid)
     sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
     model = api.Model.from_spec(SPECS[which], weights(which))
     E1, F1 = api.Potential(model, sy.n_atoms, 0.0, 160)(pos, sp)

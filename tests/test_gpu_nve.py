@@ -1,0 +1,63 @@
+"""Energy conservation of the 4,500-atom water box over 10 ps of NVE dynamics (FP32 model
+arithmetic, float64 integration), DMTS at 1 fs / 4 fs against 1 fs velocity Verlet with the
+reference model.  H = KE + E_reference is sampled every 20 fs and fitted with a straight
+line; the drift is slope x 10 ps per atom."""
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu_common import say, system, weights, SPECS
+from paper_2510_06562_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def drift_fit(t_ps, H, n_atoms, span_ps):
+    """Least-squares line through H(t): drift over span_ps per atom, its standard error
+    and the largest deviation from H(0) per atom."""
+    A = np.vstack([t_ps, np.ones_like(t_ps)]).T
+    coef, res, _, _ = np.linalg.lstsq(A, H, rcond=None)
+    resid = H - A @ coef
+    s2 = resid @ resid / max(len(H) - 2, 1)
+    se = np.sqrt(s2 / np.sum((t_ps - t_ps.mean()) ** 2))
+    return (coef[0] * span_ps / n_atoms, se * span_ps / n_atoms,
+            float(np.max(np.abs(H - H[0]))) / n_atoms)
+
+
+def run_nve(sy, small, large, dt_outer, n_inner, ps, sample_fs=20.0):
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_outer, n_inner, 64, 128)
+    v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201)
+    x, v = api.to_soa(sy.pos), api.to_soa(v0)
+    n_steps = int(round(ps * 1000.0 / dt_outer))
+    chunk = max(1, int(round(sample_fs / dt_outer)))
+    t, H = [0.0], [st.step(x, v, small, large, 0)[3].item()]
+    done = 0
+    while done < n_steps:
+        k = min(chunk, n_steps - done)
+        H.append(st.step(x, v, small, large, k)[3].item())
+        done += k
+        t.append(done * dt_outer / 1000.0)
+    return np.array(t), np.array(H), st.fallbacks
+
+
+def test_water4500_fp32_10ps_conserves_energy():
+    say("NVE 10 ps water4500 FP32: DMTS 1/4 fs, DMTS 1/2 fs, Verlet 1 fs")
+    sy = system("water4500")
+    small = api.Model.from_spec(SPECS["small"], weights("small"))
+    large = api.Model.from_spec(SPECS["large"], weights("large"))
+    out = {}
+    for name, sm, dt, n in (("dmts_4fs", small, 4.0, 4), ("dmts_2fs", small, 2.0, 2),
+                            ("verlet_1fs", None, 1.0, 1)):
+        t, H, fb = run_nve(sy, sm, large, dt, n, 10.0)
+        out[name] = drift_fit(t, H, sy.n_atoms, 10.0) + (fb,)
+        say(f"  {name}: drift {out[name][0]:+.2e} eV/atom (se {out[name][1]:.1e}), "
+            f"max dev {out[name][2]:.2e}, fallbacks {fb}")
+    drift, se, dev, _ = out["dmts_4fs"]
+    # reading 20, first clause: no visible drift over 10 ps
+    assert abs(drift) <= 1e-5 and dev <= 2e-5
+    # the FP32 kernels themselves add no drift: the same kernels at 1 fs conserve H to
+    # well below the DMTS splitting's own drift
+    assert abs(out["verlet_1fs"][0]) <= 1e-7
+    assert all(v[3] == 0 for v in out.values())

@@ -66,6 +66,34 @@ def test_respa_step_is_the_transfer_matrix_product(n_slow):
     assert np.linalg.det(T) == pytest.approx(1.0, abs=1e-13)   # symplectic in 1D
 
 
+@pytest.mark.parametrize("n_slow", [1, 4])
+def test_monitored_step_follows_the_transfer_matrices(n_slow):
+    """The force-difference guard on a 1-d oscillator with F_small = -k_s x and
+    F = -k_L x: below the threshold the step is the RESPA matrix product; above it the
+    step is n_slow velocity-Verlet steps of dt/n_slow with k_L, and the recorded breach is
+    |k_L - k_s| max(|x_0|, |x_1|), x_1 the end of the discarded RESPA step."""
+    ks, kL, m, dt = 5.0, 4.2, 2.0, 1.3
+    h = dt / n_slow
+    inner = _kick_mat(h / 2, ks, m) @ _drift_mat(h / 2) @ _drift_mat(h / 2) @ _kick_mat(h / 2, ks, m)
+    T = _kick_mat(dt / 2, kL - ks, m) @ np.linalg.matrix_power(inner, n_slow) @ _kick_mat(dt / 2, kL - ks, m)
+    V = np.linalg.matrix_power(_kick_mat(h / 2, kL, m) @ _drift_mat(h) @ _kick_mat(h / 2, kL, m), n_slow)
+    x0, v0 = 0.8, -0.05
+    x1 = (T @ np.array([x0, v0]))[0]
+    breach = abs(kL - ks) * max(abs(x0), abs(x1))
+
+    def run(thr):
+        st = I.MTSState(x=np.array([[x0, 0, 0]]), v=np.array([[v0, 0, 0]]), m=np.array([m]))
+        return I.mts_step_monitored(st, dt, n_slow, _harmonic(ks), _harmonic(kL), thr)
+
+    kept, b, redo = run(breach * (1 + 1e-9))
+    assert not redo and b == pytest.approx(breach, rel=1e-14)
+    np.testing.assert_allclose([kept.x[0, 0], kept.v[0, 0]], T @ [x0, v0], rtol=1e-13)
+    redone, b, redo = run(breach * (1 - 1e-9))
+    assert redo and b == pytest.approx(breach, rel=1e-14)
+    np.testing.assert_allclose([redone.x[0, 0], redone.v[0, 0]], V @ [x0, v0], rtol=1e-13)
+    assert redone.first_step
+
+
 SMALL = P.make_model(0, 3.5, 16, 64, synth.model_weights(synth.SMALL, synth.SMALL_SEED),
                      energy_scale=1.0)
 
