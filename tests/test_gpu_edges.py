@@ -100,8 +100,10 @@ def test_bf16_per_atom_energies_within_rounding_bound(which):
     product is rounded to 8 significant bits (relative error <= 2^-9); through the pair
     contraction, the message sums and the readout chain the error of E_i stays a small
     multiple of 2^-9 times the size of the readout terms, s_E sum_c |w_c SiLU(z_c)| (from
-    the oracle), which does not shrink when the terms cancel.  Bound: 2^-4 of that size,
-    i.e. 32 units of 2^-9."""
+    the oracle), which does not shrink when the terms cancel.  Bound: 8 units of 2^-9 of
+    that size (four chained roundings: radial operands, message sums into the readout,
+    readout operands, and for the reference model the update chains; twice that for
+    margin).  Measured on the 4,500-atom box: at most 1.0 (fast) and 1.8 (reference)."""
     say(f"bf16 per-atom energies {which}")
     sy = system("water4500")
     model = api.Model.from_spec(SPECS[which], weights(which), precision=api.PREC_BF16)
@@ -111,7 +113,7 @@ def test_bf16_per_atom_energies_within_rounding_bound(which):
     size = OP.readout_magnitude(oracle_model(which), sy.pos, sy.species, sy.box)
     ratio = np.abs(Ea.cpu().numpy().astype(np.float64) - Ea0) / (2.0 ** -9 * size)
     say(f"  max |dE_i| / (2^-9 size_i) = {ratio.max():.2f}, median {np.median(ratio):.3f}")
-    assert ratio.max() <= 32.0
+    assert ratio.max() <= 8.0
 
 
 @pytest.mark.parametrize("which", ["small", "large"])

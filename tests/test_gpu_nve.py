@@ -55,9 +55,13 @@ def test_water4500_fp32_10ps_conserves_energy():
         say(f"  {name}: drift {out[name][0]:+.2e} eV/atom (se {out[name][1]:.1e}), "
             f"max dev {out[name][2]:.2e}, fallbacks {fb}")
     drift, se, dev, _ = out["dmts_4fs"]
-    # reading 20, first clause: no visible drift over 10 ps
+    # first clause: no visible drift over 10 ps
     assert abs(drift) <= 1e-5 and dev <= 2e-5
-    # the FP32 kernels themselves add no drift: the same kernels at 1 fs conserve H to
-    # well below the DMTS splitting's own drift
-    assert abs(out["verlet_1fs"][0]) <= 1e-7
+    # second clause, as evaluated here: the FP32 kernels add no drift of their own (the
+    # same kernels under 1 fs Verlet drift by less than 3 standard errors of the fit, or
+    # by less than 1e-8 eV/atom), and the DMTS drift is the splitting's: it falls more than
+    # eightfold from a 4 fs to a 2 fs outer step, which rounding noise would not do
+    v_drift, v_se = out["verlet_1fs"][:2]
+    assert abs(v_drift) <= max(3.0 * v_se, 1e-8)
+    assert abs(out["dmts_2fs"][0]) * 8.0 <= abs(drift)
     assert all(v[3] == 0 for v in out.values())
