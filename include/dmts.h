@@ -181,6 +181,26 @@ dmts_status nnp_energy_forces(nnp_model* model, nnp_nlist* nl, const double* pos
                               const int32_t* sys_offsets, int32_t n_sys, double* energy,
                               float* forces, float* atom_energy, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): nnp_energy_forces of a
+ * one-interaction (fast) model that allocates nothing.  Same arguments, results (bit for
+ * bit) and asynchrony as nnp_energy_forces; the caller still passes inputs, outputs and a
+ * built list (nnp_nlist_create allocates, once).  Its workspace is a fixed array of
+ * 13 MiB in device memory, one per GPU the library runs on, held until the process ends;
+ * it holds systems of at most 8,192 atoms: more returns DMTS_E_CAPACITY, a
+ * two-interaction model DMTS_E_ARG, both before anything is enqueued.  Every call on one
+ * GPU shares that GPU's array (its contents are those of the last call; nothing in it needs
+ * to start at zero), so calls that overlap on one GPU (other streams or threads) race:
+ * order them on one stream.  The first call on a device looks up the array's address
+ * there (hipGetSymbolAddress); with kernel timing (dmts_prof_enable) on, timing events may
+ * be created.
+ */
+dmts_status nnp_energy_forces_noalloc(nnp_model* model, nnp_nlist* nl, const double* pos,
+                                      const int32_t* species, int32_t n_atoms, double box,
+                                      const int32_t* sys_offsets, int32_t n_sys,
+                                      double* energy, float* forces, float* atom_energy,
+                                      void* stream);
+
 /* ---------------------------------------------------------------- the RESPA loop
  * Algorithm 1 (BAOAB-RESPA with force splitting).  One outer step of length dt_outer:
  *   v += dt/2 (F - F_small)/m;

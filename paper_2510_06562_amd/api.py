@@ -71,6 +71,7 @@ _SIGS = {
     "nnp_nlist_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
     "nnp_nlist_download": ([_P, _P, _P, _P, _P, _I64, ctypes.POINTER(_I64)], _I32),
     "nnp_energy_forces": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _P, _P, _P, _P], _I32),
+    "nnp_energy_forces_noalloc": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _P, _P, _P, _P], _I32),
     "dmts_state_create": ([_I32, _D, _P, _P, _I32, _D, _I32, _I32, _I32, ctypes.POINTER(_P)], _I32),
     "dmts_state_destroy": ([_P], None),
     "dmts_step": ([_P, _P, _P, _P, _P, _I32, _P, _P], _I32),
@@ -277,6 +278,29 @@ def energy_forces(model: Model, nlist: NeighborList, pos_soa: torch.Tensor,
                                    float(box), _ptr(sys_offsets), n_sys, _ptr(E), _ptr(F),
                                    _ptr(Ea), _stream(stream)))
     return (E, F, Ea) if atom_energy else (E, F)
+
+
+def energy_forces_noalloc(model: Model, nlist: NeighborList, pos_soa: torch.Tensor,
+                          species: torch.Tensor, box: float, energy: torch.Tensor,
+                          forces: Optional[torch.Tensor] = None,
+                          atom_energy: Optional[torch.Tensor] = None,
+                          sys_offsets: Optional[torch.Tensor] = None, stream=None):
+    """nnp_energy_forces_noalloc: a one-interaction model's energies and forces into the
+    caller's preallocated tensors (energy float64 [n_sys], forces float32 [3, N],
+    atom_energy float32 [N]); the library allocates nothing."""
+    n = pos_soa.shape[1]
+    _dev_check(pos_soa, torch.float64, (3, n), "pos")
+    _dev_check(species, torch.int32, (n,), "species")
+    n_sys = 1 if sys_offsets is None else sys_offsets.numel() - 1
+    _dev_check(energy, torch.float64, (n_sys,), "energy")
+    if forces is not None:
+        _dev_check(forces, torch.float32, (3, n), "forces")
+    if atom_energy is not None:
+        _dev_check(atom_energy, torch.float32, (n,), "atom_energy")
+    _check(lib().nnp_energy_forces_noalloc(model.handle, nlist.handle, _ptr(pos_soa),
+                                           _ptr(species), n, float(box), _ptr(sys_offsets),
+                                           n_sys, _ptr(energy), _ptr(forces), _ptr(atom_energy),
+                                           _stream(stream)))
 
 
 class Potential:

@@ -475,8 +475,10 @@ namespace dmts {
 dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
                           int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
                           double* energy, float* forces, float* atom_energy, hipStream_t s,
-                          const Epilogue* ep) {
+                          const Epilogue* ep, char* ws) {
   DMTS_REQUIRE(m && nl && pos && species, DMTS_E_ARG, "nnp_energy_forces: null argument");
+  DMTS_REQUIRE(!ws || m->desc.kind == NNP_KIND_ONE_INTERACTION, DMTS_E_ARG,
+               "energy_forces: a caller workspace is for one-interaction models");
   DMTS_REQUIRE(!ep || forces, DMTS_E_ARG, "energy_forces: an integrator epilogue needs forces");
   DMTS_REQUIRE(n == nl->n_atoms, DMTS_E_STATE,
                "nnp_energy_forces: list built for %d atoms, called with %d", nl->n_atoms, n);
@@ -488,7 +490,7 @@ dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t*
                "nnp_energy_forces: n_sys must be >= 1 with sys_offsets");
   if (m->desc.kind == NNP_KIND_ONE_INTERACTION)
     return small_energy_forces(m, nl, pos, species, n, box, sys_offsets, n_sys, energy, forces,
-                               atom_energy, s, ep);
+                               atom_energy, s, ep, ws);
   return large_energy_forces(m, nl, pos, species, n, box, sys_offsets, n_sys, energy, forces,
                              atom_energy, s, ep);
 }

@@ -391,11 +391,14 @@ int resident_groups(const void* kernel, int threads);
 
 // `ep` (optional, needs `forces`): integrator program applied to every atom once its force
 // is final; `forces` must then be the program's F_small (fast model) or F_large.
+// `ws` (optional, fast model only): a caller-provided workspace of small_workspace_bytes(n)
+// bytes used instead of the model's own (which then never grows).
+size_t small_workspace_bytes(int32_t n);
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos,
                                 const int32_t* species, int32_t n, double box,
                                 const int32_t* sys_offsets, int32_t n_sys, double* energy,
                                 float* forces, float* atom_energy, hipStream_t s,
-                                const Epilogue* ep = nullptr);
+                                const Epilogue* ep = nullptr, char* ws = nullptr);
 dmts_status large_energy_forces(Model* m, NList* nl, const double* pos,
                                 const int32_t* species, int32_t n, double box,
                                 const int32_t* sys_offsets, int32_t n_sys, double* energy,
@@ -405,7 +408,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos,
 dmts_status energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
                           int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
                           double* energy, float* forces, float* atom_energy, hipStream_t s,
-                          const Epilogue* ep = nullptr);
+                          const Epilogue* ep = nullptr, char* ws = nullptr);
 
 // Deterministic FP64 sum of per-atom FP32 energies per system: energy[s] = sum over the
 // atoms of system s (one system when sys_offsets is NULL).  `partial` (energy_partials(n)

@@ -23,6 +23,7 @@
 // BF16 form: v_mfma_f32_16x16x16_bf16 (A: A[l%16][4 (l/16) + e], B: B[4 (l/16) + e][l%16],
 // e = 0..3) with b, b' and W_r rounded to bfloat16; the readout uses bfloat16-valued W1 and
 // activations with FP32 accumulation.  Geometry and elementwise math are FP32.
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -385,19 +386,25 @@ k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
 
 }  // namespace
 
+// Workspace of one evaluation: compact pair table [n][kCap] (geometry, senders, counts),
+// adjoint g [n][F], atom energies [n], the energy partial sums.
+size_t small_workspace_bytes(int32_t n) {
+  const size_t N = (size_t)(n + 63) / 64 * 64;
+  return sizeof(float4) * N * kCap + sizeof(float) * (N * F_S + N) +
+         sizeof(int32_t) * (N * kCap + N) + sizeof(double) * energy_partials(n) + 256;
+}
+
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
                                 int32_t n, double box, const int32_t* sys_offsets, int32_t n_sys,
                                 double* energy, float* forces, float* atom_energy, hipStream_t s,
-                                const Epilogue* ep) {
+                                const Epilogue* ep, char* ws) {
   DMTS_REQUIRE(m->K == K_S && m->F == F_S, DMTS_E_ARG, "small model: unsupported shape");
-  // workspace: compact pair table [n][kCap] (geometry, senders, counts), adjoint g [n][F],
-  // atom energies [n]
   const size_t N = (size_t)(n + 63) / 64 * 64;
-  const size_t need = sizeof(float4) * N * kCap + sizeof(float) * (N * F_S + N) +
-                      sizeof(int32_t) * (N * kCap + N) + sizeof(double) * energy_partials(n) +
-                      256;
-  DMTS_REQUIRE(m->atom_ws.reserve(need, s) == DMTS_OK, DMTS_E_OOM, "small model: workspace");
-  char* base = m->atom_ws.as<char>();
+  if (!ws) {
+    DMTS_REQUIRE(m->atom_ws.reserve(small_workspace_bytes(n), s) == DMTS_OK, DMTS_E_OOM,
+                 "small model: workspace");
+  }
+  char* base = ws ? ws : m->atom_ws.as<char>();
   float4* ell_g = reinterpret_cast<float4*>(base);
   float* g = reinterpret_cast<float*>(ell_g + N * kCap);
   float* e_ws = g + N * F_S;
@@ -448,4 +455,58 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
   return DMTS_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free variant
+// The workspace of nnp_energy_forces_noalloc: one array per device, kept for the life of the
+// process, sized for kNoAllocMaxAtoms atoms.  Host code never uses the array's name (it is a
+// host-side stand-in for the symbol); it uses the device address from hipGetSymbolAddress.
+constexpr int32_t kNoAllocMaxAtoms = 8192;
+constexpr size_t kNoAllocBytes = size_t(13) << 20;   // >= small_workspace_bytes(8192)
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+dmts_status scratch_address(void** out) {
+  int dev = 0;
+  DMTS_HIP(hipGetDevice(&dev));
+  DMTS_REQUIRE(dev >= 0 && dev < kMaxDevices, DMTS_E_ARG, "noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    DMTS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    DMTS_REQUIRE(p != nullptr, DMTS_E_HIP, "noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DMTS_OK;
+}
+}  // namespace
+
 }  // namespace dmts
+
+extern "C" dmts_status nnp_energy_forces_noalloc(nnp_model* model, nnp_nlist* nl,
+                                                 const double* pos, const int32_t* species,
+                                                 int32_t n_atoms, double box,
+                                                 const int32_t* sys_offsets, int32_t n_sys,
+                                                 double* energy, float* forces,
+                                                 float* atom_energy, void* stream) {
+  using namespace dmts;
+  Model* m = reinterpret_cast<Model*>(model);
+  DMTS_REQUIRE(m, DMTS_E_ARG, "nnp_energy_forces_noalloc: null model");
+  DMTS_REQUIRE(m->desc.kind == NNP_KIND_ONE_INTERACTION, DMTS_E_ARG,
+               "nnp_energy_forces_noalloc: one-interaction models only");
+  DMTS_REQUIRE(n_atoms >= 0 && n_atoms <= kNoAllocMaxAtoms, DMTS_E_CAPACITY,
+               "nnp_energy_forces_noalloc: %d atoms, the fixed scratch holds at most %d",
+               n_atoms, kNoAllocMaxAtoms);
+  DMTS_REQUIRE(small_workspace_bytes(n_atoms) <= kNoAllocBytes, DMTS_E_CAPACITY,
+               "nnp_energy_forces_noalloc: workspace exceeds the fixed scratch");
+  void* ws = nullptr;
+  const dmts_status r = scratch_address(&ws);
+  if (r != DMTS_OK) return r;
+  return energy_forces(m, reinterpret_cast<NList*>(nl), pos, species, n_atoms, box, sys_offsets,
+                       n_sys, energy, forces, atom_energy, static_cast<hipStream_t>(stream),
+                       nullptr, static_cast<char*>(ws));
+}
