@@ -47,11 +47,15 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 #   per pair: b_k and b'_k (forward 4K: shift, square, scale, exp; backward 6K), f_c and
 #             f_c' (sine/cosine, forward 4, backward 6), Y (15), the force vector (backward
 #             about 30) -> forward 4K + 30, backward 6K + 50.
-# Fast model (F = 64, K = 16), both message directions of a pair in one pass:
-#   forward:  per channel 2K + 8 (radial, two table terms, SiLU, f_c, sum), per pair 4K + 10
-#   backward: per channel 4K + 30 (radial and its derivative, two SiLU-and-derivative
-#             chains of 7, the two directions' radial-force terms of 6 each, two table
-#             sums), per pair 6K + 30.
+# Fast model (F = 64, K = 16), per directed pair inside the cutoff:
+#   evaluation ("small_forward"): per channel 4K + 17 (a = (W_r b)_c and (W_r b')_c 4K,
+#             two table terms 2, sigma 3, SiLU 1, SiLU' 3, m = f_c s 1, the sum into h 1,
+#             dm/dr 3, its product with g_i 2), per pair 6K + 34 (b_k and b'_k 6K, f_c and
+#             f_c' 6, the float geometry and the unit vector about 28); the readout adds
+#             2 x 2 x 64 x 64 flops per atom, not counted here;
+#   force gather ("small_backward"): 7 flops per pair (s_ij + s_ji and three products),
+#             bound by its 28 bytes per list slot (index, reverse index, record, reverse
+#             record's s).
 def _ref_fwd(K=32, F=128):
     return F * (2 * K + 27) + 4 * K + 30         # 11,806
 
@@ -62,8 +66,8 @@ def _ref_bwd(K=32, F=128):
 
 PAIR_FLOPS = {"pair2_backward": _ref_bwd(), "pair1_backward": _ref_bwd(),
               "pair2_forward": _ref_fwd(), "pair1_forward": _ref_fwd(),
-              "small_backward": 64 * (4 * 16 + 30) + 6 * 16 + 30,   # 6,142
-              "small_forward": 64 * (2 * 16 + 8) + 4 * 16 + 10}     # 2,634
+              "small_backward": 7,
+              "small_forward": 64 * (4 * 16 + 17) + 6 * 16 + 34}    # 5,314
 
 
 def measured_traffic(workload, precision, kernel):
@@ -131,6 +135,8 @@ def parse():
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes instead of tuning them for the workload")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="MLP contraction operands (bf16: bfloat16 operands, FP32 accumulate)")
     return ap.parse_args()
@@ -244,8 +250,8 @@ def batch_throughput(args, api, synth, small, large):
     t_b = timed(batched)
     t_l = timed(loop)
     out = {"mode": "batch", "molecules": 256, "n_atoms": sy.n_atoms,
-           "precision": args.precision, "tuned_work_groups": {"fast": tuned[0][0],
-                                                             "reference": tuned[1][0]},
+           "precision": args.precision, "tuned_shapes": {"fast": tuned[0][0],
+                                                        "reference": tuned[1][0]},
            "batched_ms": round(t_b, 4), "per_molecule_loop_ms": round(t_l, 4),
            "batched_molecules_per_s": round(256 / (t_b * 1e-3), 1),
            "loop_molecules_per_s": round(256 / (t_l * 1e-3), 1),
@@ -318,6 +324,17 @@ def main():
     pairs_large = int(np.sum(nbr >= 0))
     offs_s, nbr_s, _ = pot_s.nlist.download(sy.n_atoms)
     pairs_small = int(np.sum(nbr_s >= 0))
+
+    # ---------------------------------------------------------------- tile shapes
+    # each model's shape for this system size, tuned on the list it runs on in the RESPA
+    # loop (the reference model's cutoff, shared by the fast model)
+    shapes = {}
+    if not args.no_autotune:
+        list_cut = max(synth.LARGE.cutoff, spec_s.cutoff + 1.0)
+        for name, mdl in (("fast", small), ("reference", large)):
+            p = api.Potential(mdl, sy.n_atoms, sy.box, 128)
+            sh, t = api.autotune(p, x0, sp, reps=3, cutoff=list_cut)
+            shapes[name] = dict(sh, ms=round(t, 4))
 
     # ---------------------------------------------------------------- DMTS timed region
     st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_out, n_inner, 64, 128)
@@ -454,6 +471,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "distilled_readout": distilled,
+        "tile_shapes": shapes,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)

@@ -109,20 +109,47 @@ dmts_status nnp_model_create(const nnp_model_desc* desc, const float* host_weigh
                              int64_t n_weights, nnp_model** out);
 void nnp_model_destroy(nnp_model* model);
 
-/* Launch shape.  The pair kernels of a model loop over groups of receivers in a
- * grid-stride order with a fixed per-receiver arithmetic, so the number of work-groups
- * changes speed only, never results.  nnp_model_set_grid sets it (0 = one work-group per
- * group of receivers, the default; k > 0 = a persistent grid of at most k work-groups).
- * nnp_autotune times one energy+force evaluation on the given system for each candidate
- * (0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096; median of `reps` after a warm-up, HIP events on
- * `stream`), keeps the fastest in the model and returns it in *chosen (host) with its time
- * in *best_ms (host).  Blocking: synchronizes the stream and allocates scratch. */
+/* Launch shapes (the batching form's tiles, chosen by an autotuner).  Every kernel of a
+ * model computes each receiver and each atom row with a fixed arithmetic whatever
+ * work-group holds it, so a shape changes speed only, never a result bit.
+ *   receivers_per_group  two-interaction pair kernels: receivers per work-group, one
+ *                        wave each, sharing the work-group's staged weights: 2, 4 or 8;
+ *   atom_tiles           two-interaction per-atom MLP chains: 16-atom row tiles per
+ *                        work-group (each weight load feeds them all): 1 or 2;
+ *   keep_derivatives     one-interaction model: 1 keeps the radial derivative factors of a
+ *                        receiver's first 32 pairs in registers across its readout (three
+ *                        waves per SIMD), 0 recomputes them (four waves per SIMD);
+ *   work_groups          grid-stride kernels: 0 = one work-group per group of receivers
+ *                        (one persistent round when that is between one and two rounds of
+ *                        resident work-groups), k > 0 = a persistent grid of at most k.
+ * A model holds a default shape (4, 2, 1, 0 at creation) and one shape per size bucket
+ * (systems with the same number of bits in their atom count).
+ * nnp_model_set_shape: n_atoms <= 0 sets the default and forgets every bucket's shape;
+ *   n_atoms > 0 sets the shape of n_atoms' bucket.  DMTS_E_ARG for a value outside the
+ *   lists above.  nnp_model_get_shape: the shape a system of n_atoms uses (n_atoms <= 0:
+ *   the default).
+ * nnp_model_set_grid / nnp_model_get_grid: work_groups of the default shape (set_grid also
+ *   sets it in every bucket's shape).
+ * nnp_autotune times one energy+force evaluation of the given system (list built from pos)
+ *   for every candidate shape: the values above that the model's kind uses, times
+ *   work_groups in {0, 256, 512, 1024, 2048, 4096} (median of `reps` after a warm-up, HIP
+ *   events on `stream`), keeps the fastest as the shape of n_atoms' bucket and returns it
+ *   in *chosen (host) with its time in *best_ms (host).  Blocking: synchronizes the stream
+ *   and allocates scratch. */
+typedef struct {
+  int32_t receivers_per_group;
+  int32_t atom_tiles;
+  int32_t keep_derivatives;
+  int32_t work_groups;
+} nnp_tile_shape;
+dmts_status nnp_model_set_shape(nnp_model* model, int32_t n_atoms, const nnp_tile_shape* shape);
+dmts_status nnp_model_get_shape(nnp_model* model, int32_t n_atoms, nnp_tile_shape* shape);
 dmts_status nnp_model_set_grid(nnp_model* model, int32_t work_groups);
 dmts_status nnp_model_get_grid(nnp_model* model, int32_t* work_groups);
 dmts_status nnp_autotune(nnp_model* model, nnp_nlist* nl, const double* pos,
                          const int32_t* species, int32_t n_atoms, double box,
                          const int32_t* sys_offsets, int32_t n_sys, int32_t reps, void* stream,
-                         int32_t* chosen, double* best_ms);
+                         nnp_tile_shape* chosen, double* best_ms);
 
 /* ---------------------------------------------------------------- neighbor lists
  * A full (both directions) list of ordered pairs {(i, j): j != i, |d_ij| < cutoff},

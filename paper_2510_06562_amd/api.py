@@ -48,6 +48,14 @@ class _Desc(ctypes.Structure):
                 ("energy_scale", ctypes.c_double)]
 
 
+class _Shape(ctypes.Structure):
+    _fields_ = [("receivers_per_group", ctypes.c_int32), ("atom_tiles", ctypes.c_int32),
+                ("keep_derivatives", ctypes.c_int32), ("work_groups", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -62,7 +70,9 @@ _SIGS = {
     "nnp_model_destroy": ([_P], None),
     "nnp_model_set_grid": ([_P, _I32], _I32),
     "nnp_model_get_grid": ([_P, ctypes.POINTER(_I32)], _I32),
-    "nnp_autotune": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _I32, _P, ctypes.POINTER(_I32),
+    "nnp_model_set_shape": ([_P, _I32, ctypes.POINTER(_Shape)], _I32),
+    "nnp_model_get_shape": ([_P, _I32, ctypes.POINTER(_Shape)], _I32),
+    "nnp_autotune": ([_P, _P, _P, _P, _I32, _D, _P, _I32, _I32, _P, ctypes.POINTER(_Shape),
                       ctypes.POINTER(_D)], _I32),
     "nnp_nlist_create": ([_I32, _I64, _I32, ctypes.POINTER(_P)], _I32),
     "nnp_nlist_destroy": ([_P], None),
@@ -198,6 +208,18 @@ class Model:
     @grid.setter
     def grid(self, work_groups: int):
         _check(lib().nnp_model_set_grid(self._h, int(work_groups)))
+
+    def shape(self, n_atoms: int = 0) -> dict:
+        """The tile shape a system of n_atoms uses (0: the default shape)."""
+        sh = _Shape()
+        _check(lib().nnp_model_get_shape(self._h, int(n_atoms), ctypes.byref(sh)))
+        return sh.as_dict()
+
+    def set_shape(self, n_atoms: int = 0, receivers_per_group: int = 4, atom_tiles: int = 2,
+                  keep_derivatives: int = 1, work_groups: int = 0):
+        """Set the shape of n_atoms' size bucket (0: the default, forgetting every bucket)."""
+        sh = _Shape(receivers_per_group, atom_tiles, keep_derivatives, work_groups)
+        _check(lib().nnp_model_set_shape(self._h, int(n_atoms), ctypes.byref(sh)))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -336,19 +358,21 @@ class Potential:
 
 
 def autotune(potential: "Potential", pos_soa: torch.Tensor, species: torch.Tensor,
-             reps: int = 3, stream=None):
-    """Pick the pair kernels' work-group count for this system (see nnp_autotune); returns
-    (work_groups, best_ms).  Builds the potential's list from pos_soa first."""
-    potential.nlist.build(pos_soa, potential.box, potential.model.desc.cutoff,
+             reps: int = 3, stream=None, cutoff: Optional[float] = None):
+    """Pick the model's tile shape for this system's size bucket (see nnp_autotune); returns
+    (shape dict, best_ms).  Builds the potential's list from pos_soa first, at `cutoff`
+    (default: the model's; a longer one tunes for a list shared with another model)."""
+    potential.nlist.build(pos_soa, potential.box,
+                          potential.model.desc.cutoff if cutoff is None else cutoff,
                           potential.sys_offsets, stream)
     n = pos_soa.shape[1]
     offs = potential.sys_offsets
     n_sys = 1 if offs is None else offs.numel() - 1
-    g, t = ctypes.c_int32(), ctypes.c_double()
+    sh, t = _Shape(), ctypes.c_double()
     _check(lib().nnp_autotune(potential.model.handle, potential.nlist.handle, _ptr(pos_soa),
                               _ptr(species), n, float(potential.box), _ptr(offs), n_sys, reps,
-                              _stream(stream), ctypes.byref(g), ctypes.byref(t)))
-    return g.value, t.value
+                              _stream(stream), ctypes.byref(sh), ctypes.byref(t)))
+    return sh.as_dict(), t.value
 
 
 class NNPEnergy(torch.autograd.Function):

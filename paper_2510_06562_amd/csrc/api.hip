@@ -538,35 +538,108 @@ extern "C" dmts_status dmts_prof_read(int32_t kernel_class, double* total_ms, in
   return DMTS_OK;
 }
 
+namespace {
+
+bool valid_shape(const nnp_tile_shape& t) {
+  return (t.receivers_per_group == 2 || t.receivers_per_group == 4 ||
+          t.receivers_per_group == 8) &&
+         (t.atom_tiles == 1 || t.atom_tiles == 2) &&
+         (t.keep_derivatives == 0 || t.keep_derivatives == 1) && t.work_groups >= 0;
+}
+
+dmts::TileShape to_internal(const nnp_tile_shape& t) {
+  dmts::TileShape s;
+  s.nw = t.receivers_per_group;
+  s.rt = t.atom_tiles;
+  s.keep = t.keep_derivatives;
+  s.grid = t.work_groups;
+  return s;
+}
+
+nnp_tile_shape to_abi(const dmts::TileShape& s) {
+  return nnp_tile_shape{s.nw, s.rt, s.keep, s.grid};
+}
+
+}  // namespace
+
 extern "C" dmts_status nnp_model_set_grid(nnp_model* h, int32_t work_groups) {
   Model* m = reinterpret_cast<Model*>(h);
   DMTS_REQUIRE(m && work_groups >= 0, DMTS_E_ARG, "nnp_model_set_grid: bad argument");
-  m->grid = work_groups;
+  m->shape.grid = work_groups;
+  for (auto& kv : m->tuned) kv.second.grid = work_groups;
   return DMTS_OK;
 }
 
 extern "C" dmts_status nnp_model_get_grid(nnp_model* h, int32_t* work_groups) {
   Model* m = reinterpret_cast<Model*>(h);
   DMTS_REQUIRE(m && work_groups, DMTS_E_ARG, "nnp_model_get_grid: bad argument");
-  *work_groups = m->grid;
+  *work_groups = m->shape.grid;
   return DMTS_OK;
 }
 
-// Times one energy+force evaluation per candidate work-group count (median of `reps`
-// after one warm-up) with HIP events on `stream`, keeps the fastest in the model.
+extern "C" dmts_status nnp_model_set_shape(nnp_model* h, int32_t n_atoms,
+                                           const nnp_tile_shape* shape) {
+  Model* m = reinterpret_cast<Model*>(h);
+  DMTS_REQUIRE(m && shape, DMTS_E_ARG, "nnp_model_set_shape: null argument");
+  DMTS_REQUIRE(valid_shape(*shape), DMTS_E_ARG,
+               "nnp_model_set_shape: receivers_per_group must be 2, 4 or 8, atom_tiles 1 or 2, "
+               "keep_derivatives 0 or 1, work_groups >= 0 (got %d, %d, %d, %d)",
+               shape->receivers_per_group, shape->atom_tiles, shape->keep_derivatives,
+               shape->work_groups);
+  if (n_atoms <= 0) {
+    m->shape = to_internal(*shape);
+    m->tuned.clear();
+  } else {
+    m->tuned[Model::size_bucket(n_atoms)] = to_internal(*shape);
+  }
+  return DMTS_OK;
+}
+
+extern "C" dmts_status nnp_model_get_shape(nnp_model* h, int32_t n_atoms, nnp_tile_shape* shape) {
+  Model* m = reinterpret_cast<Model*>(h);
+  DMTS_REQUIRE(m && shape, DMTS_E_ARG, "nnp_model_get_shape: null argument");
+  *shape = to_abi(n_atoms > 0 ? m->shape_for(n_atoms) : m->shape);
+  return DMTS_OK;
+}
+
+// Times one energy+force evaluation per candidate tile shape (median of `reps` after one
+// warm-up) with HIP events on `stream`, and keeps the fastest as the model's shape for the
+// size bucket of n_atoms.
 extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* pos,
                                     const int32_t* species, int32_t n_atoms, double box,
                                     const int32_t* sys_offsets, int32_t n_sys, int32_t reps,
-                                    void* stream, int32_t* chosen, double* best_ms) {
+                                    void* stream, nnp_tile_shape* chosen, double* best_ms) {
   Model* m = reinterpret_cast<Model*>(h);
   NList* nl = reinterpret_cast<NList*>(nlh);
-  DMTS_REQUIRE(m && nl && reps >= 1 && reps <= 64, DMTS_E_ARG, "nnp_autotune: bad argument");
+  DMTS_REQUIRE(m && nl && reps >= 1 && reps <= 64 && n_atoms >= 1, DMTS_E_ARG,
+               "nnp_autotune: bad argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // candidates: the shapes the model's kernels take, times persistent grids (0 = natural,
+  // then multiples of the 256 compute units)
+  std::vector<dmts::TileShape> cands;
+  const int32_t grids[] = {0, 256, 512, 1024, 2048, 4096};
+  for (int32_t gsz : grids) {
+    dmts::TileShape t;
+    t.grid = gsz;
+    if (m->desc.kind == NNP_KIND_TWO_INTERACTION) {
+      for (int nw : {2, 4, 8})
+        for (int rt : {1, 2}) {
+          t.nw = nw;
+          t.rt = rt;
+          cands.push_back(t);
+        }
+    } else {
+      for (int keep : {0, 1}) {
+        t.keep = keep;
+        cands.push_back(t);
+      }
+    }
+  }
   const int ns = sys_offsets ? n_sys : 1;
   double* energy = nullptr;
   float* forces = nullptr;
   DMTS_HIP(hipMalloc(&energy, sizeof(double) * ns));
-  if (hipMalloc(&forces, sizeof(float) * 3 * (size_t)(n_atoms > 0 ? n_atoms : 1)) != hipSuccess) {
+  if (hipMalloc(&forces, sizeof(float) * 3 * (size_t)n_atoms) != hipSuccess) {
     (void)hipFree(energy);
     dmts::set_error("nnp_autotune: allocation failed");
     return DMTS_E_OOM;
@@ -574,14 +647,13 @@ extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* 
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  // the natural grid, then multiples of the 256 compute units
-  const int32_t cands[] = {0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096};
-  const int32_t saved = m->grid;
-  int32_t best = saved;
+  const int bucket = Model::size_bucket(n_atoms);
+  const std::map<int, dmts::TileShape> saved = m->tuned;
+  dmts::TileShape best = m->shape_for(n_atoms);
   double best_t = 1e300;
   dmts_status st = DMTS_OK;
-  for (int32_t c : cands) {
-    m->grid = c;
+  for (const dmts::TileShape& c : cands) {
+    m->tuned[bucket] = c;
     std::vector<double> t;
     for (int r = 0; r <= reps && st == DMTS_OK; ++r) {
       (void)hipEventRecord(e0, s);
@@ -609,9 +681,10 @@ extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* 
   (void)hipEventDestroy(e1);
   (void)hipFree(energy);
   (void)hipFree(forces);
-  m->grid = st == DMTS_OK ? best : saved;
+  m->tuned = saved;
   if (st != DMTS_OK) return st;
-  if (chosen) *chosen = best;
+  m->tuned[bucket] = best;
+  if (chosen) *chosen = to_abi(best);
   if (best_ms) *best_ms = best_t;
   return DMTS_OK;
 }

@@ -27,12 +27,13 @@ struct AtomMlpParams {
   const __bf16* h_U1T = nullptr;   // [384][128]
 };
 
-dmts_status atom_chain1(const AtomMlpParams& P, int M, const float* q1, float* z1, float* h1,
-                        float* P2, hipStream_t s);
-dmts_status atom_chain2(const AtomMlpParams& P, int M, const float* q2, const float* h1,
+// rt: 16-atom row tiles per work-group (1 or 2), a tile shape the autotuner chooses.
+dmts_status atom_chain1(const AtomMlpParams& P, int M, int rt, const float* q1, float* z1,
+                        float* h1, float* P2, hipStream_t s);
+dmts_status atom_chain2(const AtomMlpParams& P, int M, int rt, const float* q2, const float* h1,
                         float escale, float* atom_e, float* dh2, float* dq2, bool backward,
                         hipStream_t s);
-dmts_status atom_chain3(const AtomMlpParams& P, int M, const float* RS, const float* dh2,
+dmts_status atom_chain3(const AtomMlpParams& P, int M, int rt, const float* RS, const float* dh2,
                         const float* z1, float* dq1, hipStream_t s);
 
 }  // namespace dmts

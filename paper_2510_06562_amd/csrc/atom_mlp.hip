@@ -268,31 +268,39 @@ k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __re
 
 }  // namespace
 
-dmts_status atom_chain1(const AtomMlpParams& P, int M, const float* q1, float* z1, float* h1,
-                        float* P2, hipStream_t s) {
+// rt: 16-atom tiles per work-group (1 or 2; any other value is taken as kRT).  A row's
+// result does not depend on it.
+dmts_status atom_chain1(const AtomMlpParams& P, int M, int rt, const float* q1, float* z1,
+                        float* h1, float* P2, hipStream_t s) {
   if (M <= 0) return DMTS_OK;
   ProfScope ps(DMTS_K_ATOM_GEMM, s);
-  k_chain1<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
+  if (rt == 1) k_chain1<1><<<ceil_div(M, 16), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
+  else k_chain1<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, q1, z1, h1, P2);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
 
-dmts_status atom_chain2(const AtomMlpParams& P, int M, const float* q2, const float* h1,
+dmts_status atom_chain2(const AtomMlpParams& P, int M, int rt, const float* q2, const float* h1,
                         float escale, float* atom_e, float* dh2, float* dq2, bool backward,
                         hipStream_t s) {
   if (M <= 0) return DMTS_OK;
   ProfScope ps(DMTS_K_ATOM_GEMM, s);
-  k_chain2<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2,
-                                                           dq2, backward);
+  if (rt == 1)
+    k_chain2<1><<<ceil_div(M, 16), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2, dq2,
+                                                      backward);
+  else
+    k_chain2<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, q2, h1, escale, atom_e, dh2,
+                                                             dq2, backward);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
 
-dmts_status atom_chain3(const AtomMlpParams& P, int M, const float* RS, const float* dh2,
+dmts_status atom_chain3(const AtomMlpParams& P, int M, int rt, const float* RS, const float* dh2,
                         const float* z1, float* dq1, hipStream_t s) {
   if (M <= 0) return DMTS_OK;
   ProfScope ps(DMTS_K_ATOM_GEMM, s);
-  k_chain3<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
+  if (rt == 1) k_chain3<1><<<ceil_div(M, 16), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
+  else k_chain3<kRT><<<ceil_div(M, 16 * kRT), kThreads, 0, s>>>(P, M, RS, dh2, z1, dq1);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }

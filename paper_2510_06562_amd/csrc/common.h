@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 
 #include "../../include/dmts.h"
@@ -86,6 +87,14 @@ dmts_status filter_neighbors(NList* child, const NList* parent, const double* po
                              double cutoff, hipStream_t s);
 
 // ------------------------------------------------------------------ models
+// Tile shape of one evaluation (see nnp_tile_shape in the ABI header).
+struct TileShape {
+  int32_t nw = 4;     // two-interaction pair kernels: receivers (waves) per work-group, 2/4/8
+  int32_t rt = 2;     // two-interaction atom chains: 16-atom tiles per work-group, 1/2
+  int32_t keep = 1;   // one-interaction model: keep the first tiles' derivatives in registers
+  int32_t grid = 0;   // persistent work-groups of the grid-stride kernels (0 = natural)
+};
+
 struct Model {
   nnp_model_desc desc{};
   int32_t K = 0, F = 0, D = 0, Z = 0;
@@ -106,23 +115,36 @@ struct Model {
   size_t h_WoT = 0, h_U2T = 0, h_W2hs = 0, h_U1T = 0;     // reverse chain layers
   size_t o_WbR = 0, o_W1R = 0, o_W1TR = 0;                // kind 0: bf16-valued floats
   const __bf16* p16(size_t off) const { return params16.as<__bf16>() + off; }
-  // launch: work-groups of the pair kernels (0 = one per group of receivers); the pair
-  // kernels loop over receivers in a grid-stride order, so any count gives the same bits
-  int32_t grid = 0;
+  // Launch shape: the default one and the autotuner's choice per size bucket (number of
+  // bits of the atom count).  No shape changes a result bit: every receiver and every atom
+  // row is computed by the same arithmetic whatever work-group holds it.
+  TileShape shape;
+  std::map<int, TileShape> tuned;
+  static int size_bucket(int32_t n) {
+    int b = 0;
+    while (n > 0) { ++b; n >>= 1; }
+    return b;
+  }
+  TileShape shape_for(int32_t n) const {
+    const auto it = tuned.find(size_bucket(n));
+    return it == tuned.end() ? shape : it->second;
+  }
   // distinct for every model created in the process (never 0): a RESPA state compares it to
   // know whether its carried forces belong to this model
   uint64_t generation = 0;
   // workspace
   DevBuf atom_ws, pair_ws, sys_ws;
-  // natural: work-groups for one pass over the receivers; resident: how many the GPU holds
-  // at once.  With the default grid, a pass that would take between one and two rounds of
-  // work-groups runs as one persistent round instead of a full and a partly filled one.
-  int launch_grid(int natural, int resident = 0) const {
-    if (grid > 0) return grid < natural ? grid : natural;
-    return resident > 0 && natural > resident && natural < 2 * resident ? resident : natural;
-  }
   const float* p(size_t off) const { return params.as<float>() + off; }
 };
+
+// Work-groups of a grid-stride launch: grid > 0 caps it; with 0, natural (one pass over the
+// receivers) unless that takes between one and two rounds of the `resident` work-groups the
+// GPU holds at once, which then run as one persistent round instead of a full and a partly
+// filled one.
+inline int launch_grid(int grid, int natural, int resident = 0) {
+  if (grid > 0) return grid < natural ? grid : natural;
+  return resident > 0 && natural > resident && natural < 2 * resident ? resident : natural;
+}
 
 // ------------------------------------------------------------------ integrator program
 // Kicks and drifts between two force evaluations, applied per atom in the algorithm's
@@ -391,9 +413,10 @@ int resident_groups(const void* kernel, int threads);
 
 // `ep` (optional, needs `forces`): integrator program applied to every atom once its force
 // is final; `forces` must then be the program's F_small (fast model) or F_large.
-// `ws` (optional, fast model only): a caller-provided workspace of small_workspace_bytes(n)
-// bytes used instead of the model's own (which then never grows).
-size_t small_workspace_bytes(int32_t n);
+// `ws` (optional, fast model only): a caller-provided workspace of
+// small_workspace_bytes(n, nl->max_pairs) bytes used instead of the model's own (which then
+// never grows).
+size_t small_workspace_bytes(int32_t n, int64_t max_pairs);
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos,
                                 const int32_t* species, int32_t n, double box,
                                 const int32_t* sys_offsets, int32_t n_sys, double* energy,

@@ -219,24 +219,25 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
 // are capped so that four waves share a SIMD (five in the BF16 form, at the cost of a few
 // spilled registers outside the tile loop, measured faster), those of the reverse kernel
 // for three (four for the BF16 form of interaction 1, which fits 128 registers).
-template <int LAYER, int NP>
-__global__ void __launch_bounds__(kWaves * 64)
+// NW: receivers (one wave each) per work-group, a tile shape the autotuner chooses.
+template <int LAYER, int NP, int NW>
+__global__ void __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(NP == 1 && LAYER == 1 ? 5 : 4)))
 k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
                 const float* __restrict__ P2, float* __restrict__ Mout, float* __restrict__ q) {
   __shared__ __bf16 sW[NP * (F_L / 2) * K_L];   // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
-  __shared__ float sM[kWaves][16 * kLdM];   // rows 10..15 (zero moments) unused
+  __shared__ float sM[NW][16 * kLdM];   // rows 10..15 (zero moments) unused
   const int half = blockIdx.x & 1, hb = 4 * half;   // hb: first channel block of the half
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int n_ag = (n + kWaves - 1) / kWaves;
+  const int n_ag = (n + NW - 1) / NW;
   for (int ag = blockIdx.x >> 1; ag < n_ag; ag += gridDim.x >> 1) {
-  const int i = ag * kWaves + w;
+  const int i = ag * NW + w;
   if (i >= n) continue;
   const int zi_s = species[i];
   float base[4];
@@ -342,8 +343,8 @@ constexpr int kLdR = 68;
 
 constexpr bool kAhead = true;
 
-template <int LAYER, int NP>
-__global__ void __launch_bounds__(kWaves * 64)
+template <int LAYER, int NP, int NW>
+__global__ void __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(NP == 1 && LAYER == 1 ? 4 : 3)))
 k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
                 const float4* __restrict__ geo, const int32_t* __restrict__ species, int n,
@@ -353,18 +354,18 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   __shared__ __bf16 sW[NP * (F_L / 2) * K_L];         // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   // per wave, over its 64 channels (local index cc = c - 64 half)
-  __shared__ float sD[kWaves][NMOM * kLdH];          // D[y][cc] of the receiver (dswz)
-  __shared__ __align__(16) float sB[kWaves][F_L / 2];   // receiver term S_i of a_ij
-  __shared__ float sR[LAYER == 2 ? kWaves : 1][LAYER == 2 ? kTile * kLdR : 1];
+  __shared__ float sD[NW][NMOM * kLdH];          // D[y][cc] of the receiver (dswz)
+  __shared__ __align__(16) float sB[NW][F_L / 2];   // receiver term S_i of a_ij
+  __shared__ float sR[LAYER == 2 ? NW : 1][LAYER == 2 ? kTile * kLdR : 1];
   const int half = blockIdx.x & 1, hb = 4 * half;
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int n_ag = (n + kWaves - 1) / kWaves;
+  const int n_ag = (n + NW - 1) / NW;
   for (int ag = blockIdx.x >> 1; ag < n_ag; ag += gridDim.x >> 1) {
-  const int i = ag * kWaves + w;
+  const int i = ag * NW + w;
   if (i >= n) continue;
   float* sd = sD[w];
   const int zi_s = species[i];
@@ -710,34 +711,38 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
     A.h_U1T = m->p16(m->h_U1T);
   }
   const int blocks = ceil_div(n, kWaves);
-  // two work-groups (channel halves) per kWaves receivers; an even grid of at least two
-  auto pgrid = [&](const void* kernel) {
-    const int b = m->launch_grid(2 * ceil_div(n, kWaves), resident_groups(kernel, kWaves * 64));
-    return b < 2 ? 2 : b + (b & 1);
-  };
+  const TileShape sh = m->shape_for(n);
   // the whole evaluation, instantiated for the FP32 (three-term radial operands) and the
-  // BF16 form (one term)
-  auto run = [&](auto np_tag) -> dmts_status {
+  // BF16 form (one term), and for NW receivers per pair work-group
+  auto run = [&](auto np_tag, auto nw_tag) -> dmts_status {
     constexpr int NP = decltype(np_tag)::value;
+    constexpr int NW = decltype(nw_tag)::value;
     dmts_status st;
     if (n > 0) {
-      auto grid_of = [&](auto kernel) { return dim3(pgrid(reinterpret_cast<const void*>(kernel))); };
-      const dim3 wg(kWaves * 64);
+      // two work-groups (channel halves) per NW receivers; an even grid of at least two
+      auto grid_of = [&](auto kernel) {
+        const int b = launch_grid(sh.grid, 2 * ceil_div(n, NW),
+                                  resident_groups(reinterpret_cast<const void*>(kernel), NW * 64));
+        return dim3(b < 2 ? 2 : b + (b & 1));
+      };
+      const dim3 wg(NW * 64);
       {
         ProfScope ps(DMTS_K_PAIR1_FORWARD, s, true);
-        launch_timed(ps, &k_pair_fwd_mfma<1, NP>, grid_of(&k_pair_fwd_mfma<1, NP>), wg, s, P1,
-                     nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_q1);
+        launch_timed(ps, &k_pair_fwd_mfma<1, NP, NW>, grid_of(&k_pair_fwd_mfma<1, NP, NW>), wg, s,
+                     P1, nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_q1);
       }
       DMTS_CHECK_LAUNCH();
-      if ((st = atom_chain1(A, n, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK) return st;
+      if ((st = atom_chain1(A, n, sh.rt, W + o_q1, W + o_z1, W + o_h1, W + o_P2, s)) != DMTS_OK)
+        return st;
       {
         ProfScope ps(DMTS_K_PAIR2_FORWARD, s, true);
-        launch_timed(ps, &k_pair_fwd_mfma<2, NP>, grid_of(&k_pair_fwd_mfma<2, NP>), wg, s, P2,
-                     nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_q2);
+        launch_timed(ps, &k_pair_fwd_mfma<2, NP, NW>, grid_of(&k_pair_fwd_mfma<2, NP, NW>), wg, s,
+                     P2, nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_q2);
       }
       DMTS_CHECK_LAUNCH();
-      if ((st = atom_chain2(A, n, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2, W + o_dq2,
-                            forces != nullptr, s)) != DMTS_OK) return st;
+      if ((st = atom_chain2(A, n, sh.rt, W + o_q2, W + o_h1, m->escale, e_atom, W + o_dh2,
+                            W + o_dq2, forces != nullptr, s)) != DMTS_OK)
+        return st;
       if (forces) {
         // pair workspace: dA [cap][F] (FP32 or bfloat16), then v [cap][2] float4 (the
         // two channel halves' partial dE/dd_ij of a slot side by side)
@@ -745,9 +750,9 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
         float* v = m->pair_ws.as<float>() + (size_t)cap * F;
         {
           ProfScope ps(DMTS_K_PAIR2_BACKWARD, s, true);
-          launch_timed(ps, &k_pair_bwd_mfma<2, NP>, grid_of(&k_pair_bwd_mfma<2, NP>), wg, s, P2,
-                       nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2, W + o_dq2, dA,
-                       W + o_RS, v, cap);
+          launch_timed(ps, &k_pair_bwd_mfma<2, NP, NW>, grid_of(&k_pair_bwd_mfma<2, NP, NW>), wg,
+                       s, P2, nl->offs, nl->nbr, nl->geo, species, n, W + o_P2, W + o_M2,
+                       W + o_dq2, dA, W + o_RS, v, cap);
         }
         DMTS_CHECK_LAUNCH();
         {
@@ -756,13 +761,14 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
                                                                      n, dA, W + o_RS);
         }
         DMTS_CHECK_LAUNCH();
-        if ((st = atom_chain3(A, n, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) != DMTS_OK)
+        if ((st = atom_chain3(A, n, sh.rt, W + o_RS, W + o_dh2, W + o_z1, W + o_dq1, s)) !=
+            DMTS_OK)
           return st;
         {
           ProfScope ps(DMTS_K_PAIR1_BACKWARD, s, true);
-          launch_timed(ps, &k_pair_bwd_mfma<1, NP>, grid_of(&k_pair_bwd_mfma<1, NP>), wg, s, P1,
-                       nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1, W + o_dq1,
-                       static_cast<DAType<NP>*>(nullptr), nullptr, v, cap);
+          launch_timed(ps, &k_pair_bwd_mfma<1, NP, NW>, grid_of(&k_pair_bwd_mfma<1, NP, NW>), wg,
+                       s, P1, nl->offs, nl->nbr, nl->geo, species, n, nullptr, W + o_M1,
+                       W + o_dq1, static_cast<DAType<NP>*>(nullptr), nullptr, v, cap);
         }
         DMTS_CHECK_LAUNCH();
         // the integrator program runs in the force gather's epilogue, or (with an O-step)
@@ -782,8 +788,15 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
 
     return DMTS_OK;
   };
-  const dmts_status rs = m->bf16 ? run(std::integral_constant<int, 1>{})
-                                 : run(std::integral_constant<int, 3>{});
+  auto run_np = [&](auto np_tag) -> dmts_status {
+    switch (sh.nw) {
+      case 2: return run(np_tag, std::integral_constant<int, 2>{});
+      case 8: return run(np_tag, std::integral_constant<int, 8>{});
+      default: return run(np_tag, std::integral_constant<int, 4>{});
+    }
+  };
+  const dmts_status rs = m->bf16 ? run_np(std::integral_constant<int, 1>{})
+                                 : run_np(std::integral_constant<int, 3>{});
   if (rs != DMTS_OK) return rs;
   if (energy)
     return reduce_energy(e_atom, n, sys_offsets, n_sys, energy,

@@ -131,18 +131,109 @@ __device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
   return acc;
 }
 
-// Five waves per SIMD (registers capped at 102; the kernel needs 76-90 once the weights
-// are in LDS before the first receiver): five work-groups per CU by LDS as well, so the
-// 4,500-atom box runs in one round.
+// One 16-pair tile of the receiver's compact row (pairs t0 .. t0 + 15 of the wave's LDS
+// table), for the lane's channel block b (channel 16 b + cl) and D rows r (pair t0 + 4 g + r):
+//   m[b][r]  = f_c SiLU(a)                                    the message
+//   dm[b][r] = f_c' SiLU(a) + f_c SiLU'(a) (W_r b')_c          its derivative in r
+// with a = (W_r b)_c + T_d[z_i][c] + T_s[z_j][c].  Rows past the row give m = dm = 0 (no
+// branches: they read slot 0 and are masked).
 template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
-k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-            const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
-            double box, float* __restrict__ atom_e, float* __restrict__ g_out,
-            int32_t* __restrict__ ell_j, float4* __restrict__ ell_g, int32_t* __restrict__ ell_n,
-            uint32_t* __restrict__ flags) {
+__device__ __forceinline__ void small_tile(const SmallLds<true>& L, const float4* sG,
+                                           const int* sZ, int t0, int cnt, int zi_s, int g,
+                                           int cl, float sigma, float inv_s2, float pi_rc,
+                                           float (&m)[4][4], float (&dm)[4][4]) {
+  const int pc = t0 + cl;   // pair of the A operand
+  const bool vp = pc < cnt;
+  const float rp = sG[vp ? pc : 0].w;
+  float bv[4], dbv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int kk = BF16 ? 4 * g + e : 4 * e + g;
+    const float x = rp - sigma * kk;
+    const float bb = __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);
+    bv[e] = bb;
+    dbv[e] = -x * inv_s2 * bb;
+  }
+  float fc[4], dfc[4];
+  int zz[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = t0 + 4 * g + r;
+    const bool v = q < cnt;
+    const int qc = v ? q : 0;
+    float sn, cs;
+    __sincosf(pi_rc * sG[qc].w, &sn, &cs);
+    fc[r] = v ? 0.5f * (cs + 1.0f) : 0.f;
+    dfc[r] = v ? -0.5f * pi_rc * sn : 0.f;
+    const int zq = sZ[qc];
+    zz[r] = v ? zq : zi_s;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = 16 * b + cl;
+    auto wk = [&](int e) {
+      const int kk = BF16 ? 4 * g + e : 4 * e + g;
+      return L.W[c * kLdW + kk];
+    };
+    const f32x4 acc = radial_mfma<BF16>([&](int e) { return bv[e]; }, wk, true);
+    const f32x4 accd = radial_mfma<BF16>([&](int e) { return dbv[e]; }, wk, true);
+    const float td = L.Td[zi_s][c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float sv, dsv;
+      silu_and_grad(acc[r] + td + L.Ts[zz[r]][c], sv, dsv);
+      m[b][r] = fc[r] * sv;
+      dm[b][r] = fmaf(dfc[r], sv, fc[r] * dsv * accd[r]);
+    }
+    // one channel block at a time: the products of all four blocks in flight would hold
+    // 32 more registers than the kernel can spare at three waves per SIMD
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// s_ij = dE_i/dr_ij = sum_c g_c dm[c] for the tile's pairs, written with the pair's unit
+// vector to its slot of the list: pw[p] = (d_ij / r_ij, s_ij).  gb[b] = g at channel
+// 16 b + cl.  The channel sum of pair t0 + 4 g + r is in-lane over b, then over the 16
+// lanes of group g; lane cl = r of the group writes it.
+__device__ __forceinline__ void small_tile_store(const float (&dm)[4][4], const float (&gb)[4],
+                                                 const float4* sG, const int* sP, int t0,
+                                                 int cnt, int g, int cl,
+                                                 float4* __restrict__ pw) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float part = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) part = fmaf(gb[b], dm[b][r], part);
+    part = row16_sum(part);
+    const int q = t0 + 4 * g + r;
+    if (cl == r && q < cnt) {
+      const float4 gv = sG[q];
+      const float ir = __builtin_amdgcn_rcpf(gv.w);
+      pw[sP[q]] = make_float4(gv.x * ir, gv.y * ir, gv.z * ir, part);
+    }
+  }
+}
+
+// The evaluation kernel, one wavefront per receiver:
+//   1. the receiver's list row (which may come from a longer cutoff) at the current
+//      positions: the pairs inside the cutoff, in row order, go to an LDS table; every
+//      other real entry of the row gets pw[p] = 0 (no force through it);
+//   2. the messages on MFMA tiles, summed into h_i in registers; with KEEP the derivative
+//      factors dm/dr of the first two tiles stay in registers;
+//   3. the readout: E_i and g_i = dE_i/dh_i;
+//   4. s_ij = g_i . dm_ij/dr for every pair of the row (kept tiles from registers, the
+//      others recomputed with the same arithmetic), written to the pair's slot.
+// KEEP is a tile shape of the autotuner: registers capped at 168 (three waves per SIMD)
+// with it, at 128 (four) without; LDS holds four work-groups per CU.
+template <bool BF16, bool KEEP>
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KEEP ? 3 : 4)))
+k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
+             const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
+             double box, float* __restrict__ atom_e, float4* __restrict__ pw,
+             uint32_t* __restrict__ flags) {
   __shared__ SmallLds<true> L;
   __shared__ int sZ[kWaves][kCap];
+  __shared__ int sP[kWaves][kCap];
   __shared__ float4 sG[kWaves][kCap];
   __shared__ float sVec[kWaves][F_S];
   {
@@ -158,84 +249,66 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
   const int n_wg = (n + kWaves - 1) / kWaves;
   for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {   // uniform over the work-group
     const int i = wg * kWaves + w;
-    const bool act = i < n;
+    if (i >= n) continue;   // no work-group barrier below: waves leave independently
+    // 1. pairs inside the cutoff, in row order
     int cnt = 0;
-    if (act) {
-    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-    // 1. pairs inside the cutoff, in row order, compacted into LDS and the table
-    const int row0 = offs[i], row1 = offs[i + 1];
-    for (int base = row0; base < row1; base += 64) {
-      const int p = base + lane;
-      const int j = p < row1 ? nbr[p] : -1;
-      // loads from the receiver itself where there is no pair: no branch, all loads of a
-      // lane issue together
-      const int jc = j >= 0 ? j : i;
-      const int zj = species[jc];
-      const float dx = static_cast<float>(minimage(pos[jc] - xi, box, inv_box));
-      const float dy = static_cast<float>(minimage(pos[n + jc] - yi, box, inv_box));
-      const float dz = static_cast<float>(minimage(pos[2 * n + jc] - zi, box, inv_box));
-      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      const bool ok = j >= 0 && r < P.rc;
-      const uint64_t mask = __ballot(ok);
-      const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
-      if (ok && k < kCap) {
-        const float4 gv = make_float4(dx, dy, dz, r);
-        sZ[w][k] = zj;
-        sG[w][k] = gv;
-        ell_j[(size_t)i * kCap + k] = j;
-        ell_g[(size_t)i * kCap + k] = gv;
+    {
+      const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+      const int row0 = offs[i], row1 = offs[i + 1];
+      for (int base = row0; base < row1; base += 64) {
+        const int p = base + lane;
+        const int j = p < row1 ? nbr[p] : -1;
+        // loads from the receiver itself where there is no pair: no branch, all loads of a
+        // lane issue together
+        const int jc = j >= 0 ? j : i;
+        const int zj = species[jc];
+        const float dx = static_cast<float>(minimage(pos[jc] - xi, box, inv_box));
+        const float dy = static_cast<float>(minimage(pos[n + jc] - yi, box, inv_box));
+        const float dz = static_cast<float>(minimage(pos[2 * n + jc] - zi, box, inv_box));
+        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+        const bool ok = j >= 0 && r < P.rc;
+        const uint64_t mask = __ballot(ok);
+        const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+        if (ok && k < kCap) {
+          sZ[w][k] = zj;
+          sG[w][k] = make_float4(dx, dy, dz, r);
+          sP[w][k] = p;
+        } else if (j >= 0) {
+          pw[p] = make_float4(0.f, 0.f, 0.f, 0.f);   // outside the cutoff (or past the cap)
+        }
+        cnt += __popcll(mask);
       }
-      cnt += __popcll(mask);
+      if (cnt > kCap) {
+        if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+        cnt = kCap;
+      }
     }
-    if (cnt > kCap) {
-      if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
-      cnt = kCap;
-    }
-    if (lane == 0) ell_n[i] = cnt;
-    }
-    if (!act) continue;
     wave_sync();
     // 2. messages on MFMA tiles, summed over pairs in registers
     const int zi_s = species[i];
+    const float4* sg = sG[w];
+    const int* sz = sZ[w];
     float hacc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int t0 = 0; t0 < cnt; t0 += kTile) {
-      const int pc = t0 + cl;                       // pair of the A operand
-      const bool vp = pc < cnt;
-      // slots past the row read slot 0 and are masked after: no branches
-      const float rp = vp ? sG[w][vp ? pc : 0].w : 0.f;
-      auto bk = [&](int e) {
-        const int kk = BF16 ? 4 * g + e : 4 * e + g;
-        const float x = rp - P.sigma * kk;
-        return __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);
-      };
-      float fc[4];
-      int zz[4];
+    float m[4][4], dm0[4][4], dm1[4][4];
+    auto add_h = [&]() {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = t0 + 4 * g + r;
-        const bool v = q < cnt;
-        const int qc = v ? q : 0;
-        const float rq = sG[w][qc].w;
-        const float cq = 0.5f * (__cosf(pi_rc * rq) + 1.0f);
-        fc[r] = v ? cq : 0.f;
-        const int zq = sZ[w][qc];
-        zz[r] = v ? zq : zi_s;
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) hacc[b] += m[b][r];
+    };
+    constexpr int kKept = KEEP ? 2 : 0;   // tiles whose factors stay in registers
+    if (KEEP) {
+      small_tile<BF16>(L, sg, sz, 0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dm0);
+      add_h();
+      if (cnt > kTile) {
+        small_tile<BF16>(L, sg, sz, kTile, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dm1);
+        add_h();
       }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int c = 16 * b + cl;
-        auto wk = [&](int e) {
-          const int kk = BF16 ? 4 * g + e : 4 * e + g;
-          return L.W[c * kLdW + kk];
-        };
-        const f32x4 acc = radial_mfma<BF16>(bk, wk, true);
-        const float td = L.Td[zi_s][c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float a = acc[r] + td + L.Ts[zz[r]][c];
-          hacc[b] = fmaf(fc[r], silu_f(a), hacc[b]);
-        }
-      }
+    }
+    for (int t0 = kKept * kTile; t0 < cnt; t0 += kTile) {
+      float dmx[4][4];
+      small_tile<BF16>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
+      add_h();
     }
     // h[c] for c = 16 b + cl: add the four pair groups
 #pragma unroll
@@ -251,6 +324,7 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
     // 3. readout, channel c = lane: z = W1 h, E_i = s_E w2 . SiLU(z), g = W1^T (s_E w2 SiLU'(z))
     const int c = lane;
     float z = 0.f;
+#pragma unroll 8
     for (int e = 0; e < F_S; ++e) z = fmaf(L.W1[c][e], sVec[w][e], z);
     float y, dy;
     silu_and_grad(z, y, dy);
@@ -260,138 +334,84 @@ k_small_fwd(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __re
     sVec[w][c] = BF16 ? bf16r(P.escale * w2 * dy) : P.escale * w2 * dy;
     wave_sync();
     float gi = 0.f;
+#pragma unroll 8
     for (int k = 0; k < F_S; ++k) gi = fmaf(L.W1[k][c], sVec[w][k], gi);
-    g_out[(size_t)i * F_S + c] = gi;
     if (lane == 0) atom_e[i] = e_i;
+    // 4. s_ij per pair into the pair's slot
+    float gb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) gb[b] = __shfl(gi, 16 * b + cl, 64);
+    if (KEEP) {
+      small_tile_store(dm0, gb, sg, sP[w], 0, cnt, g, cl, pw);
+      if (cnt > kTile) small_tile_store(dm1, gb, sg, sP[w], kTile, cnt, g, cl, pw);
+    }
+    for (int t0 = kKept * kTile; t0 < cnt; t0 += kTile) {
+      float dmx[4][4];
+      small_tile<BF16>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
+      small_tile_store(dmx, gb, sg, sP[w], t0, cnt, g, cl, pw);
+    }
     wave_sync();
   }
 }
 
-// Three waves per SIMD (registers capped at 168): left free, the compiler takes ~250 for
-// the FP32 form with the integrator epilogue, which leaves two.
-template <bool BF16>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
-k_small_bwd(SmallParams P, const int32_t* __restrict__ species, int n,
-            const float* __restrict__ g, const int32_t* __restrict__ ell_j,
-            const float4* __restrict__ ell_g, const int32_t* __restrict__ ell_n,
-            float* __restrict__ forces, Epilogue E, bool has_ep, bool fresh_small) {
-  __shared__ SmallLds<false> L;
-  Stager<false> stage;
-  stage.fetch(P);
-  bool staged = false;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, cl = lane & 15;
-  const float inv_s2 = 1.0f / (P.sigma * P.sigma);
-  const float pi_rc = 3.14159265358979f / P.rc;
-  const int n_wg = (n + kWaves - 1) / kWaves;
-  for (int wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {   // uniform over the work-group
-    const int i = wg * kWaves + w;
-    const bool act = i < n;
-    // the receiver's whole compact row, one entry per lane (the row holds at most 64)
-    int cnt = 0, zi_s = 0, jl = 0, zl = 0;
-    float4 gl = make_float4(0.f, 0.f, 0.f, 0.f);
-    float gi[16];   // the lane's 16 channels: c = 16 b + 4 gq + r
-    if (act) {
-      cnt = ell_n[i];
-      zi_s = species[i];
-      // every lane loads its slot of the table (within the allocation) and entries past
-      // the row are replaced after: no branch around the loads
-      const int jraw = ell_j[(size_t)i * kCap + lane];
-      const float4 graw = ell_g[(size_t)i * kCap + lane];
-      jl = lane < cnt ? jraw : i;
-      gl = lane < cnt ? graw : make_float4(0.f, 0.f, 0.f, 0.f);
-      zl = species[jl];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const float4 t = *reinterpret_cast<const float4*>(g + (size_t)i * F_S + 16 * b + 4 * gq);
-        gi[4 * b] = t.x;
-        gi[4 * b + 1] = t.y;
-        gi[4 * b + 2] = t.z;
-        gi[4 * b + 3] = t.w;
-      }
+// Forces F_i = sum_j (s_ij + s_ji) d_ij / r_ij over the receiver's list row, s_ji read from
+// the reverse slot rev[p] (one wave per atom).  Entries outside the cutoff hold zeros; the
+// pairs inside it are compacted in row order (a ballot, as in the evaluation kernel) and
+// summed by their position in that order, so the bits do not depend on the list's own
+// cutoff or padding (a list built at the model's cutoff and a longer shared one give the
+// same forces).  The kernel reads no positions, so the integrator program that follows the
+// evaluation runs in its epilogue once F_i is final (a drift there cannot race with
+// another wave).
+__global__ void __launch_bounds__(256)
+k_small_force(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
+              const int32_t* __restrict__ rev, int n, const float4* __restrict__ pw,
+              float* __restrict__ forces, Epilogue E, bool has_ep, bool fresh_small) {
+  __shared__ float4 sC[4][kCap];   // per wave: the pair terms by position in the compact row
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  CoordIn ein{};   // the atom's integrator inputs, coordinate d = lane (lanes 0..2)
+  if (has_ep && lane < 3) ein = prefetch_coord(E, i, n, lane, fresh_small);
+  const int row0 = offs[i], row1 = offs[i + 1];
+  int cnt = 0;
+  for (int base = row0; base < row1; base += 64) {
+    const int p = base + lane;
+    const int j = p < row1 ? nbr[p] : -1;
+    const int q = j >= 0 ? rev[p] : -1;
+    const float4 a = j >= 0 ? pw[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // a pair inside the cutoff has a unit vector; one outside (or past the evaluation's
+    // cap) holds zeros.  A missing reverse entry (an overflowed row) adds nothing.
+    const bool ok = a.x != 0.f || a.y != 0.f || a.z != 0.f;
+    const float sb = ok && q >= 0 ? pw[q].w : 0.f;
+    const uint64_t mask = __ballot(ok);
+    const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+    if (ok && k < kCap) {
+      const float s = a.w + sb;
+      sC[w][k] = make_float4(s * a.x, s * a.y, s * a.z, 0.f);
     }
-    if (!staged) {   // the weights, once per work-group, after the first receivers' loads
-      stage.store(L);
-      __syncthreads();
-      staged = true;
-    }
-    if (!act) continue;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int t0 = 0; t0 < cnt; t0 += kTile) {
-      const int pc = t0 + cl;            // the lane's pair, taken from lane pc
-      const bool vp = pc < cnt;
-      const int j = __shfl(jl, pc, 64);
-      const int zj = __shfl(zl, pc, 64);
-      const float4 gv = make_float4(__shfl(gl.x, pc, 64), __shfl(gl.y, pc, 64),
-                                    __shfl(gl.z, pc, 64), __shfl(gl.w, pc, 64));
-      const float rp = gv.w;
-      float sn, cs;
-      __sincosf(pi_rc * rp, &sn, &cs);
-      const float fc = vp ? 0.5f * (cs + 1.0f) : 0.f;
-      const float dfc = vp ? -0.5f * pi_rc * sn : 0.f;
-      auto bk = [&](int e) {
-        const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
-        const float x = rp - P.sigma * kk;
-        return __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);   // 0 past the row, no branch
-      };
-      auto dbk = [&](int e) {
-        const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
-        const float x = rp - P.sigma * kk;
-        return -x * inv_s2 * __expf(vp ? -0.5f * x * x * inv_s2 : -1e30f);
-      };
-      float S = 0.f;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        auto wk = [&](int e) {
-          const int kk = BF16 ? 4 * gq + e : 4 * e + gq;
-          return L.W[(16 * b + cl) * kLdW + kk];
-        };
-        const f32x4 gb = radial_mfma<BF16>(bk, wk, false);
-        const f32x4 gd = radial_mfma<BF16>(dbk, wk, false);
-        const float4 gj = *reinterpret_cast<const float4*>(g + (size_t)j * F_S + 16 * b + 4 * gq);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int c = 16 * b + 4 * gq + r;
-          const float a1 = gb[r] + L.Td[zi_s][c] + L.Ts[zj][c];   // message j -> i
-          const float a2 = gb[r] + L.Td[zj][c] + L.Ts[zi_s][c];   // message i -> j
-          float s1, ds1, s2, ds2;
-          silu_and_grad(a1, s1, ds1);
-          silu_and_grad(a2, s2, ds2);
-          const float gjr = r == 0 ? gj.x : r == 1 ? gj.y : r == 2 ? gj.z : gj.w;
-          S += gi[4 * b + r] * (dfc * s1 + fc * ds1 * gd[r]) + gjr * (dfc * s2 + fc * ds2 * gd[r]);
-        }
-      }
-      S += __shfl_xor(S, 16, 64);
-      S += __shfl_xor(S, 32, 64);
-      const float ir = vp ? __builtin_amdgcn_rcpf(rp) : 0.f;
-      fx = fmaf(S * ir, gv.x, fx);
-      fy = fmaf(S * ir, gv.y, fy);
-      fz = fmaf(S * ir, gv.z, fz);
-    }
-    CoordIn ein{};   // the atom's integrator inputs, coordinate d = lane (lanes 0..2)
-    if (has_ep && lane < 3) ein = prefetch_coord(E, i, n, lane, fresh_small);
-    // sum over the 16 pair columns (every group holds the same values)
-    fx = row16_sum(fx);
-    fy = row16_sum(fy);
-    fz = row16_sum(fz);
-    if (lane == 0) {
-      forces[i] = fx;
-      forces[n + i] = fy;
-      forces[2 * n + i] = fz;
-    }
-    // F_i is final (every lane holds the sums): the integrator step of atom i
-    if (has_ep)
-      apply_coords(E, i, n, lane, ein, lane == 0 ? fx : lane == 1 ? fy : fz, fresh_small);
+    cnt += __popcll(mask);
+  }
+  wave_sync();
+  const float4 t = lane < cnt ? sC[w][lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float fx = wave_sum(t.x), fy = wave_sum(t.y), fz = wave_sum(t.z);
+  if (lane == 0) {
+    forces[i] = fx;
+    forces[n + i] = fy;
+    forces[2 * n + i] = fz;
+  }
+  if (has_ep) {   // F_i is final (every lane holds the sums): the integrator step of atom i
+    apply_coords(E, i, n, lane, ein, lane == 0 ? fx : lane == 1 ? fy : fz, fresh_small);
   }
 }
 
 }  // namespace
 
-// Workspace of one evaluation: compact pair table [n][kCap] (geometry, senders, counts),
-// adjoint g [n][F], atom energies [n], the energy partial sums.
-size_t small_workspace_bytes(int32_t n) {
+// Workspace of one evaluation: the per-slot pair records (d/r, s) of a list with room for
+// max_pairs entries, atom energies [n], the energy partial sums.
+size_t small_workspace_bytes(int32_t n, int64_t max_pairs) {
   const size_t N = (size_t)(n + 63) / 64 * 64;
-  return sizeof(float4) * N * kCap + sizeof(float) * (N * F_S + N) +
-         sizeof(int32_t) * (N * kCap + N) + sizeof(double) * energy_partials(n) + 256;
+  return sizeof(float4) * (size_t)max_pairs + sizeof(float) * N +
+         sizeof(double) * energy_partials(n) + 256;
 }
 
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
@@ -401,49 +421,52 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
   DMTS_REQUIRE(m->K == K_S && m->F == F_S, DMTS_E_ARG, "small model: unsupported shape");
   const size_t N = (size_t)(n + 63) / 64 * 64;
   if (!ws) {
-    DMTS_REQUIRE(m->atom_ws.reserve(small_workspace_bytes(n), s) == DMTS_OK, DMTS_E_OOM,
-                 "small model: workspace");
+    DMTS_REQUIRE(m->atom_ws.reserve(small_workspace_bytes(n, nl->max_pairs), s) == DMTS_OK,
+                 DMTS_E_OOM, "small model: workspace");
   }
   char* base = ws ? ws : m->atom_ws.as<char>();
-  float4* ell_g = reinterpret_cast<float4*>(base);
-  float* g = reinterpret_cast<float*>(ell_g + N * kCap);
-  float* e_ws = g + N * F_S;
-  int32_t* ell_j = reinterpret_cast<int32_t*>(e_ws + N);
-  int32_t* ell_n = ell_j + N * kCap;
-  double* e_part = reinterpret_cast<double*>(ell_n + N);   // 8-byte aligned: N % 64 == 0
+  float4* pw = reinterpret_cast<float4*>(base);
+  float* e_ws = reinterpret_cast<float*>(pw + nl->max_pairs);
+  double* e_part = reinterpret_cast<double*>(e_ws + N);   // 8-byte aligned: N % 64 == 0
   float* e_atom = atom_energy ? atom_energy : e_ws;
   SmallParams P{m->p(m->bf16 ? m->o_WbR : m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts),
                 m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
                 m->p(m->o_w2), m->rc, m->sigma, m->escale, m->Z};
   if (n > 0) {
     const int natural = ceil_div(n, kWaves);
-    // The integrator program (kicks and drifts) runs in the reverse kernel, per atom once
-    // its force is final: the kernel reads no positions, so a drift cannot race with it.
-    // The forces computed here are the program's F_small or, when this model stands in for
-    // the reference one (single-time-step runs), its F_large.  A program with an O-step
-    // runs as a launch of its own.
+    // The integrator program (kicks and drifts) runs in the force kernel, per atom once its
+    // force is final: the kernel reads no positions, so a drift cannot race with it.  The
+    // forces computed here are the program's F_small or, when this model stands in for the
+    // reference one (single-time-step runs), its F_large.  A program with an O-step runs as
+    // a launch of its own.
     const bool fuse = ep && forces && (forces == ep->Fs || forces == ep->FL) &&
                       !has_thermo(ep->prog);
-    auto run = [&](auto bf_tag) {
+    const TileShape sh = m->shape_for(n);
+    auto run = [&](auto bf_tag, auto keep_tag) {
       constexpr bool BF = decltype(bf_tag)::value;
+      constexpr bool KEEP = decltype(keep_tag)::value;
       {
         ProfScope ps(DMTS_K_SMALL_FORWARD, s, true);
-        const int blocks = m->launch_grid(
-            natural, resident_groups(reinterpret_cast<const void*>(&k_small_fwd<BF>), kWaves * 64));
-        launch_timed(ps, &k_small_fwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, nl->offs,
-                     nl->nbr, pos, species, n, box, e_atom, g, ell_j, ell_g, ell_n, nl->flags);
+        const int blocks = launch_grid(
+            sh.grid, natural,
+            resident_groups(reinterpret_cast<const void*>(&k_small_eval<BF, KEEP>), kWaves * 64));
+        launch_timed(ps, &k_small_eval<BF, KEEP>, dim3(blocks), dim3(kWaves * 64), s, P,
+                     nl->offs, nl->nbr, pos, species, n, box, e_atom, pw, nl->flags);
       }
       if (hipPeekAtLastError() != hipSuccess || !forces) return;
+      if (fuse && ep->wait) (void)hipStreamWaitEvent(s, ep->wait, 0);
       ProfScope ps(DMTS_K_SMALL_BACKWARD, s, true);
-      const int blocks = m->launch_grid(
-          natural, resident_groups(reinterpret_cast<const void*>(&k_small_bwd<BF>), kWaves * 64));
-      launch_timed(ps, &k_small_bwd<BF>, dim3(blocks), dim3(kWaves * 64), s, P, species, n, g,
-                   ell_j, ell_g, ell_n, forces, fuse ? *ep : Epilogue{}, fuse,
+      launch_timed(ps, &k_small_force, dim3(ceil_div(n, 4)), dim3(256), s, nl->offs, nl->nbr,
+                   nl->rev, n, pw, forces, fuse ? *ep : Epilogue{}, fuse,
                    fuse && forces == ep->Fs);
     };
-    if (fuse && ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
-    if (m->bf16) run(std::true_type{});
-    else run(std::false_type{});
+    if (m->bf16) {
+      if (sh.keep) run(std::true_type{}, std::true_type{});
+      else run(std::true_type{}, std::false_type{});
+    } else {
+      if (sh.keep) run(std::false_type{}, std::true_type{});
+      else run(std::false_type{}, std::false_type{});
+    }
     DMTS_CHECK_LAUNCH();
     if (ep && !fuse) {
       if (ep->wait) DMTS_HIP(hipStreamWaitEvent(s, ep->wait, 0));
@@ -457,10 +480,12 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
 
 // ------------------------------------------------------------------ allocation-free variant
 // The workspace of nnp_energy_forces_noalloc: one array per device, kept for the life of the
-// process, sized for kNoAllocMaxAtoms atoms.  Host code never uses the array's name (it is a
-// host-side stand-in for the symbol); it uses the device address from hipGetSymbolAddress.
+// process, sized for kNoAllocMaxAtoms atoms on a list of at most kNoAllocMaxPairs entries.
+// Host code never uses the array's name (it is a host-side stand-in for the symbol); it
+// uses the device address from hipGetSymbolAddress.
 constexpr int32_t kNoAllocMaxAtoms = 8192;
-constexpr size_t kNoAllocBytes = size_t(13) << 20;   // >= small_workspace_bytes(8192)
+constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 20;
+constexpr size_t kNoAllocBytes = size_t(17) << 20;   // >= small_workspace_bytes(both maxima)
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
@@ -501,7 +526,12 @@ extern "C" dmts_status nnp_energy_forces_noalloc(nnp_model* model, nnp_nlist* nl
   DMTS_REQUIRE(n_atoms >= 0 && n_atoms <= kNoAllocMaxAtoms, DMTS_E_CAPACITY,
                "nnp_energy_forces_noalloc: %d atoms, the fixed scratch holds at most %d",
                n_atoms, kNoAllocMaxAtoms);
-  DMTS_REQUIRE(small_workspace_bytes(n_atoms) <= kNoAllocBytes, DMTS_E_CAPACITY,
+  DMTS_REQUIRE(nl, DMTS_E_ARG, "nnp_energy_forces_noalloc: null list");
+  const int64_t cap = reinterpret_cast<NList*>(nl)->max_pairs;
+  DMTS_REQUIRE(cap <= kNoAllocMaxPairs, DMTS_E_CAPACITY,
+               "nnp_energy_forces_noalloc: the list has room for %lld entries, the fixed "
+               "scratch holds at most %lld", (long long)cap, (long long)kNoAllocMaxPairs);
+  DMTS_REQUIRE(small_workspace_bytes(n_atoms, cap) <= kNoAllocBytes, DMTS_E_CAPACITY,
                "nnp_energy_forces_noalloc: workspace exceeds the fixed scratch");
   void* ws = nullptr;
   const dmts_status r = scratch_address(&ws);

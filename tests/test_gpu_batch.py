@@ -53,16 +53,49 @@ def test_persistent_grid_does_not_change_bits(which):
     model.grid = 0
 
 
-def test_autotune_picks_a_candidate_and_keeps_results():
-    say("autotune")
+def _shapes(which):
+    """Every tile shape the model's kernels take (the autotuner's candidates without the
+    grid, plus two persistent grids)."""
+    if which == "large":
+        return [dict(receivers_per_group=nw, atom_tiles=rt, keep_derivatives=1, work_groups=g)
+                for nw in (2, 4, 8) for rt in (1, 2) for g in (0, 300)]
+    return [dict(receivers_per_group=4, atom_tiles=2, keep_derivatives=k, work_groups=g)
+            for k in (0, 1) for g in (0, 300)]
+
+
+@pytest.mark.parametrize("prec", [api.PREC_FP32, api.PREC_BF16])
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_every_tile_shape_gives_the_same_bits_and_parity(which, prec):
+    """batch256 under every tile shape: bit for bit the default shape's result, which
+    matches the oracle per molecule (FP32 1e-5 / BF16 1e-2 force rel. RMSE)."""
+    say(f"tile shapes {which} prec={prec}")
     sy = system("batch256")
     pos, sp, offs = _dev(sy)
-    model = api.Model.from_spec(SPECS["large"], weights("large"), precision=api.PREC_BF16)
+    model = api.Model.from_spec(SPECS[which], weights(which), precision=prec)
     pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
     E0, F0 = pot(pos, sp)
-    g, t = api.autotune(pot, pos, sp, reps=2)
-    assert g in (0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096) and t > 0
-    assert model.grid == g
+    _, Fo, _ = oracle_ef("batch256", which)
+    assert rel_rmse(api.from_soa(F0), Fo) <= (1e-5 if prec == api.PREC_FP32 else 1e-2)
+    for sh in _shapes(which):
+        model.set_shape(0, **sh)
+        assert model.shape(sy.n_atoms) == sh
+        E, F = pot(pos, sp)
+        assert torch.equal(E, E0) and torch.equal(F, F0), sh
+
+
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_autotune_picks_a_shape_per_size_bucket(which):
+    say(f"autotune {which}")
+    sy = system("batch256")
+    pos, sp, offs = _dev(sy)
+    model = api.Model.from_spec(SPECS[which], weights(which), precision=api.PREC_BF16)
+    pot = api.Potential(model, sy.n_atoms, 0.0, 160, offs)
+    E0, F0 = pot(pos, sp)
+    sh, t = api.autotune(pot, pos, sp, reps=2)
+    say(f"  chose {sh} at {t:.3f} ms")
+    assert t > 0 and sh["work_groups"] in (0, 256, 512, 1024, 2048, 4096)
+    assert model.shape(sy.n_atoms) == sh          # cached for this size bucket
+    assert model.shape(100) == model.shape(0)     # other buckets keep the default
     E, F = pot(pos, sp)
     assert torch.equal(E, E0) and torch.equal(F, F0)
 
