@@ -30,7 +30,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DMTS ns/day & atom-steps/s vs 1 fs Verlet, same GPU; force RMSE vs FP64"
-PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 # Algorithmic work per real pair of each pair kernel, at 2 flops per multiply-add and one
 # per add, multiply or transcendental (exp, reciprocal, sine/cosine), counted once per
@@ -68,6 +67,55 @@ PAIR_FLOPS = {"pair2_backward": _ref_bwd(), "pair1_backward": _ref_bwd(),
               "pair2_forward": _ref_fwd(), "pair1_forward": _ref_fwd(),
               "small_backward": 7,
               "small_forward": 64 * (4 * 16 + 17) + 6 * 16 + 34}    # 5,314
+
+# The same work split by the pipe that executes it (per pair):
+#   radial  the dense contraction W_b b (and W_b b'): matrix cores, in FP32 (the FP32 form,
+#           whose exact three-term bfloat16 split issues six bfloat16 products per FP32
+#           one) or in bfloat16 (the BF16 form);
+#   moment  the ten-component moment contractions (M, dm, G): FP32 matrix cores;
+#   valu    the other additions and multiplications, vector units;
+#   trans   exponentials, reciprocals, sines and cosines, vector units at a quarter rate.
+# Reference model (F = 128, K = 32): forward radial 2KF, moment 20F, valu 5F + 3K + 17,
+# trans 2F + K + 2; backward radial 4KF, moment 38F, valu 14F + 5K + 36, trans 2F + K + 2.
+# Fast model evaluation (F = 64, K = 16): radial 4KF, valu 15F + 5K + 32, trans 2F + K + 2.
+def _pipes(kernel, K, F):
+    if kernel.endswith("_forward") and kernel.startswith("pair"):
+        return dict(radial=2 * K * F, moment=20 * F, valu=5 * F + 3 * K + 17, trans=2 * F + K + 2)
+    if kernel.endswith("_backward") and kernel.startswith("pair"):
+        return dict(radial=4 * K * F, moment=38 * F, valu=14 * F + 5 * K + 36,
+                    trans=2 * F + K + 2)
+    if kernel == "small_forward":
+        return dict(radial=4 * K * F, moment=0, valu=15 * F + 5 * K + 32, trans=2 * F + K + 2)
+    return dict(radial=0, moment=0, valu=7, trans=0)
+
+
+# MI355X peaks (published): matrix cores FP32 157.3 TFLOP/s and BF16 2.5 PFLOP/s (dense),
+# FP32 vector 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 lanes x 2 flops, transcendentals a
+# quarter of the 78.6 T lane-instructions/s, HBM3E 8 TB/s.
+PEAKS = {"mfma_f32": 157.3e12, "mfma_bf16": 2500e12, "valu": 157.3e12, "trans": 19.66e12,
+         "hbm": 8e12}
+
+
+def pipe_roofline(kernel, pairs, seconds, precision, traffic):
+    """Per-pipe fractions of one launch of `kernel` and the binding (largest) one.  The
+    FP32 matrix and vector pipes of a SIMD do not issue together (measured), so their sum,
+    "simd_issue", bounds the launch as well."""
+    K, F = (16, 64) if kernel.startswith("small") else (32, 128)
+    w = _pipes(kernel, K, F)
+    bf16 = precision == "bf16"
+    work = {"mfma_f32": pairs * (w["moment"] + (0 if bf16 else w["radial"])),
+            "mfma_bf16": pairs * (w["radial"] if bf16 else 0),
+            "valu": pairs * w["valu"], "trans": pairs * w["trans"]}
+    pipes = {}
+    for p, x in work.items():
+        if x > 0:
+            pipes[p] = {"achieved": x / seconds, "peak": PEAKS[p], "frac": x / seconds / PEAKS[p]}
+    if traffic:
+        pipes["hbm"] = {"achieved": traffic / seconds, "peak": PEAKS["hbm"],
+                        "frac": traffic / seconds / PEAKS["hbm"]}
+    issue = sum(v["frac"] for k, v in pipes.items() if k != "hbm")
+    bound = max(pipes, key=lambda k: pipes[k]["frac"])
+    return bound, pipes, issue
 
 
 def measured_traffic(workload, precision, kernel):
@@ -129,12 +177,17 @@ def parse():
                     help="hydrogen mass repartitioning (3.024 amu hydrogens, mass taken from "
                          "the nearest heavy atom) for every dynamics run")
     ap.add_argument("--distill", action="store_true",
-                    help="fit the fast model's readout vector to the reference forces on "
-                         "four snapshots of a 100 fs reference-model run before timing")
+                    help="fit the fast model's readout vector to the reference energies and "
+                         "forces on frames of a reference-model run before timing, and "
+                         "report the slow force's autocorrelation before and after")
     ap.add_argument("--n-inner", type=int, default=4)
     ap.add_argument("--dt-inner", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
+    ap.add_argument("--distill-frames", type=int, default=16,
+                    help="frames of the reference run the readout is fitted on (50 fs apart)")
+    ap.add_argument("--no-nve", action="store_true",
+                    help="skip the 10 ps NVE drift run of the throughput line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shapes instead of tuning them for the workload")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
@@ -142,31 +195,105 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_oracle(sy, ws, wl, n_inner, dt_inner, spec_s, spec_l):
-    """Time the FP64 oracle on this host: one fast-model and one reference-model
-    evaluation of the workload (the bounded sample), extrapolated to DMTS ns/day."""
+def host_cpu():
+    """(logical CPUs this process may use, the CPU model name of the host)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
+    return n, model
+
+
+def cpu_oracle(sy, ws, wl, n_inner, dt_inner, spec_s, spec_l, synth):
+    """Time the FP64 oracle on this host (the bounded sample): the median of three
+    fast-model and three reference-model evaluations of the workload with every BLAS thread,
+    extrapolated to DMTS ns/day; the same pair of evaluations of the 192-atom box on one
+    thread, scaled per atom to the workload; and the 192-atom box's 20-step velocity-Verlet
+    run (0.5 fs, fast model)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import integrators as OI
     from oracle import potentials as OP
 
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+    cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    nproc, model = host_cpu()
     ms = OP.make_model(spec_s.kind, spec_s.cutoff, spec_s.n_rbf, spec_s.width, ws,
                        energy_scale=spec_s.energy_scale)
     ml = OP.make_model(spec_l.kind, spec_l.cutoff, spec_l.n_rbf, spec_l.width, wl,
                        energy_scale=spec_l.energy_scale)
-    t0 = time.perf_counter()
-    Es, Fs, _ = OP.energy_forces(ms, sy.pos, sy.species, sy.box)
-    t1 = time.perf_counter()
-    El, Fl, _ = OP.energy_forces(ml, sy.pos, sy.species, sy.box)
-    t2 = time.perf_counter()
-    t_s, t_l = t1 - t0, t2 - t1
+
+    def timed(model_, s):
+        t0 = time.perf_counter()
+        r = OP.energy_forces(model_, s.pos, s.species, s.box)
+        return time.perf_counter() - t0, r
+
+    runs_s = [timed(ms, sy) for _ in range(3)]
+    runs_l = [timed(ml, sy) for _ in range(3)]
+    t_s = float(np.median([t for t, _ in runs_s]))
+    t_l = float(np.median([t for t, _ in runs_l]))
+    Es, Fs, _ = runs_s[0][1]
+    El, Fl, _ = runs_l[0][1]
     outer_fs = n_inner * dt_inner
-    wall = n_inner * t_s + t_l
-    return dict(t_small=t_s, t_large=t_l, cores=cores,
-                ns_per_day=0.0864 * outer_fs / wall,
+    small_box = synth.water_192()
+    with threadpool_limits(limits=1):
+        t1_s = timed(ms, small_box)[0]
+        t1_l = timed(ml, small_box)[0]
+    per_atom = (n_inner * t1_s + t1_l) / small_box.n_atoms
+    # the 192-atom box's reference run: 1 evaluation + 20 velocity-Verlet steps at 0.5 fs
+    st = OI.MTSState(x=small_box.pos.copy(), v=synth.maxwell_boltzmann(small_box.species, 300.0, 200),
+                     m=small_box.masses())
+    f = lambda x: (lambda r: (r[0][0], r[1]))(OP.energy_forces(ms, x, small_box.species,  # noqa: E731
+                                                                  small_box.box))
+    t0 = time.perf_counter()
+    OI.sts_step(st, 0.0, f)
+    for _ in range(20):
+        OI.sts_step(st, 0.5, f)
+    t_c0 = time.perf_counter() - t0
+    return dict(t_small=t_s, t_large=t_l, cores=cores, nproc=nproc, cpu_model=model,
+                ns_per_day=0.0864 * outer_fs / (n_inner * t_s + t_l),
+                ns_per_day_1_thread=0.0864 * outer_fs / (per_atom * sy.n_atoms),
+                t1_small_192=t1_s, t1_large_192=t1_l, c0_run_s=t_c0,
                 Es=Es, Fs=Fs, El=El, Fl=Fl)
+
+
+def drift_fit(t_ps, H, n_atoms, span_ps):
+    """Least-squares line through H(t): (drift over span_ps per atom, its standard error,
+    the largest |H - H(0)| per atom)."""
+    A = np.vstack([t_ps, np.ones_like(t_ps)]).T
+    coef = np.linalg.lstsq(A, H, rcond=None)[0]
+    resid = H - A @ coef
+    se = np.sqrt(resid @ resid / max(len(H) - 2, 1) / np.sum((t_ps - t_ps.mean()) ** 2))
+    return (float(coef[0] * span_ps / n_atoms), float(se * span_ps / n_atoms),
+            float(np.max(np.abs(H - H[0])) / n_atoms))
+
+
+def nve_10ps(api, synth, sy, sp, v0, small, large, dt_outer, n_inner, masses=None):
+    """10 ps of NVE DMTS from the workload's start, H = KE + E_reference every ~20 fs: the
+    drift criterion's figures (drift over 10 ps per atom, the fit's standard error, the
+    largest deviation) and the fallback count."""
+    st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_outer, n_inner, 64, 128)
+    if masses is not None:
+        st.set_atom_masses(masses)
+    x, v = api.to_soa(sy.pos), api.to_soa(v0)
+    n_steps = int(round(10000.0 / dt_outer))
+    chunk = max(1, int(round(20.0 / dt_outer)))
+    t, H = [0.0], [st.step(x, v, small, large, 0)[3].item()]
+    done = 0
+    t0 = time.perf_counter()
+    while done < n_steps:
+        k = min(chunk, n_steps - done)
+        H.append(st.step(x, v, small, large, k)[3].item())
+        done += k
+        t.append(done * dt_outer / 1000.0)
+    drift, se, dev = drift_fit(np.array(t), np.array(H), sy.n_atoms, 10.0)
+    return {"drift_eV_per_atom": drift, "drift_se_eV_per_atom": se, "max_dev_eV_per_atom": dev,
+            "samples": len(H), "outer_steps": n_steps, "fallbacks": st.fallbacks,
+            "wall_s": round(time.perf_counter() - t0, 2)}
 
 
 def nve_drift(args, api, synth, sy, sp, v0, small, large):
@@ -298,13 +425,24 @@ def main():
     v0 = synth.maxwell_boltzmann(sy.species, 300.0, 201,
                                  masses=sy.hmr_masses() if args.hmr else None)
     distilled = None
+    atom_masses = sy.hmr_masses() if args.hmr else None
     if args.distill:
         from paper_2510_06562_amd import distill
-        snaps = distill.reference_snapshots(large, sp, sy.box, synth.MASSES, sy.pos, v0, 4, 25)
+        # frames 50 fs apart over 800 fs of reference dynamics (with the run's masses)
+        snaps = distill.reference_snapshots(large, sp, sy.box, synth.MASSES, sy.pos, v0,
+                                            args.distill_frames, 50, atom_masses=atom_masses)
+        acf = lambda w_: distill.slow_force_autocorrelation(  # noqa: E731
+            large, api.Model.from_spec(spec_s, w_, precision=prec), sp, sy.box, synth.MASSES,
+            sy.pos, v0, 400, 1.0, atom_masses)
+        before = acf(ws)
         ws, distilled = distill.fit_readout(spec_s, ws, large, sp, sy.box, snaps,
                                             precision=prec)
+        distilled["slow_force_before"] = before
+        distilled["slow_force_after"] = acf(ws)
         print(f"distilled readout: rms |F_L - F_S| {distilled['rms_before']:.5f} -> "
-              f"{distilled['rms_after']:.5f} eV/A", file=sys.stderr, flush=True)
+              f"{distilled['rms_after']:.5f} eV/A; tau_int {before['tau_int_fs']:.2f} -> "
+              f"{distilled['slow_force_after']['tau_int_fs']:.2f} fs", file=sys.stderr,
+              flush=True)
     small = api.Model.from_spec(spec_s, ws, precision=prec)
     n_inner, dt_in = args.n_inner, args.dt_inner
     dt_out = n_inner * dt_in
@@ -399,6 +537,12 @@ def main():
         ms_vv = max(ev0.elapsed_time(ev1), wall_v * 1e3) / n_vv
         vv = dict(ns_per_day=0.0864 * dt_in / (ms_vv * 1e-3), ms_per_step=ms_vv)
 
+    # ---------------------------------------------------------------- 10 ps NVE drift
+    nve = None
+    if args.gamma <= 0.0 and not args.no_nve:
+        nve = nve_10ps(api, synth, sy, sp, v0, small, large, dt_out, n_inner,
+                       sy.hmr_masses() if args.hmr else None)
+
     # ---------------------------------------------------------------- dominant kernel roofline
     roofline = None
     # (with the message-passing fast model both models launch the pair kernels, whose
@@ -407,13 +551,20 @@ def main():
         tot_ms, launches = prof[dom]
         avg_s = tot_ms / launches * 1e-3
         pairs = pairs_small if dom.startswith("small") else pairs_large
-        flops = PAIR_FLOPS[dom] * pairs
-        achieved = flops / avg_s / 1e12
         traffic = measured_traffic(args.workload, args.precision, dom)
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
-                    "hbm_frac_of_8TBps": (round(traffic / avg_s / 8e12, 4) if traffic else None),
+        bound, pipes, issue = pipe_roofline(dom, pairs, avg_s, args.precision, traffic)
+        b = pipes[bound]
+        tera = 1e12
+        roofline = {"bound": "hbm" if bound == "hbm" else ("mfma" if bound.startswith("mfma")
+                                                           else "alu"),
+                    "pipe": bound, "kernel": dom,
+                    "achieved": round(b["achieved"] / tera, 3), "peak": round(b["peak"] / tera, 2),
+                    "unit": "TB/s" if bound == "hbm" else "TFLOP/s",
+                    "frac": round(b["frac"], 4), "traffic": traffic,
+                    "pipes": {k: {"achieved_T": round(v["achieved"] / tera, 3),
+                                  "peak_T": round(v["peak"] / tera, 2), "frac": round(v["frac"], 4)}
+                              for k, v in pipes.items()},
+                    "simd_issue_frac": round(issue, 4),
                     "avg_launch_us": round(avg_s * 1e6, 2), "pairs_per_launch": pairs,
                     "flops_per_pair": PAIR_FLOPS[dom]}
 
@@ -421,13 +572,19 @@ def main():
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
-        c = cpu_oracle(sy, ws, wl, n_inner, dt_in, spec_s, synth.LARGE)
+        c = cpu_oracle(sy, ws, wl, n_inner, dt_in, spec_s, synth.LARGE, synth)
         cpu = {"value": round(c["ns_per_day"], 6), "unit": "ns/day", "cores": c["cores"],
-               "kind": "oracle",
-               "sample": (f"one fast-model ({c['t_small']:.2f} s) and one reference-model "
-                          f"({c['t_large']:.2f} s) FP64 energy+force evaluation of the "
-                          f"{sy.n_atoms}-atom box, extrapolated to one {dt_out:g} fs outer "
-                          f"step ({n_inner} fast + 1 reference evaluation)")}
+               "kind": "oracle", "nproc": c["nproc"], "cpu_model": c["cpu_model"],
+               "value_1_thread": round(c["ns_per_day_1_thread"], 6),
+               "c0_20_step_run_s": round(c["c0_run_s"], 3),
+               "sample": (f"median of three fast-model ({c['t_small']:.2f} s) and three "
+                          f"reference-model ({c['t_large']:.2f} s) FP64 energy+force "
+                          f"evaluations of the {sy.n_atoms}-atom box on {c['cores']} BLAS "
+                          f"threads, extrapolated to one {dt_out:g} fs outer step ({n_inner} "
+                          f"fast + 1 reference evaluation); value_1_thread: one thread, the "
+                          f"192-atom box ({c['t1_small_192']:.3f} s + {c['t1_large_192']:.3f} s) "
+                          f"scaled per atom; c0_20_step_run_s: the 192-atom box, 1 evaluation "
+                          f"+ 20 velocity-Verlet steps of 0.5 fs with the fast model")}
         Fs_np, Fl_np = api.from_soa(Fs_gpu), api.from_soa(Fl_gpu)
         errors = {
             "force_rel_rmse_small": float(np.linalg.norm(Fs_np - c["Fs"]) / np.linalg.norm(c["Fs"])),
@@ -467,6 +624,7 @@ def main():
         "speedup_vs_verlet": round(ns_day / vv["ns_per_day"], 3) if vv else None,
         "errors_vs_fp64": errors,
         "energy_drift_per_atom": (H_end - H_start) / sy.n_atoms if args.gamma <= 0.0 else None,
+        "nve_10ps": nve,
         "pairs": {"fast": pairs_small, "reference": pairs_large},
         "roofline": roofline,
         "cpu_baseline": cpu,

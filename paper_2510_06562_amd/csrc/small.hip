@@ -4,19 +4,20 @@
 //                                                  W_pair folded with the embedding table)
 //   m_ij = f_c(r_ij) SiLU(a_ij),  h_i = sum_j m_ij,  E_i = s_E w2 . SiLU(W1 h_i)
 //
-// Two kernels, one wavefront per receiver atom, pairs in 16-pair MFMA tiles:
-//   k_small_fwd: walks the receiver's neighbor-list row (which may come from a longer
-//     cutoff), computes the float geometry at the current positions, and compacts the pairs
-//     inside the cutoff with a ballot into LDS (and into a per-atom table for the reverse
-//     pass).  a = b W_r runs on MFMA (16 pairs x 64 channels), the messages are summed in
-//     registers, then the 64 -> 64 -> 1 readout gives E_i and the adjoint g_i = dE/dh_i.
-//   k_small_bwd: per tile of the compact table, the transposed product a^T = W_r b^T (and
-//     W_r b'^T) puts one pair on each lane and 16 channels in its registers; both messages
-//     of the pair (j -> i and i -> j differ only by the swapped species tables) give
-//     s_ij + s_ji = dE/dr_ij as an in-lane channel sum, and F_i = sum_j (s_ij + s_ji) d/r.
-//     Once F_i is final the integrator's kicks and drifts of atom i can run in the same
+// Two kernels, one wavefront per receiver atom:
+//   k_small_eval: walks the receiver's neighbor-list row (which may come from a longer
+//     cutoff), computes the float geometry at the current positions and compacts the pairs
+//     inside the cutoff with a ballot into LDS.  a = b W_r and a' = b' W_r run on MFMA
+//     (16 pairs x 64 channels per tile), the messages are summed in registers, the
+//     64 -> 64 -> 1 readout gives E_i and g_i = dE_i/dh_i, and then, from the tiles' values,
+//     s_ij = dE_i/dr_ij = g_i . dm_ij/dr for every pair, written with the pair's unit vector
+//     to its slot of the list.  Only E_i depends on r_ij through m_ij, so this is the whole
+//     derivative of E_i; no neighbor's adjoint is needed.
+//   k_small_force: F_i = sum_j (s_ij + s_ji) d_ij / r_ij over the row, s_ji from the reverse
+//     slot.  Once F_i is final the integrator's kicks and drifts of atom i run in the same
 //     wave (the program that follows the evaluation, when it has no O-step).
-// Rows are sorted by sender, so the sums do not depend on the list's cutoff or padding.
+// Rows are sorted by sender and both kernels sum in the order of the pairs inside the
+// cutoff, so the results do not depend on the list's cutoff or padding.
 //
 // MFMA 16x16x4 f32:  A operand lane l: A[l%16][k0 + l/16]; B: B[k0 + l/16][l%16];
 //                    D register r: D[4 (l/16) + r][l%16].
@@ -70,8 +71,13 @@ template <bool kReadout>
 struct SmallLds {
   float W[F_S * kLdW];
   float Td[Z_MAX][F_S], Ts[Z_MAX][F_S];
-  float W1[kReadout ? F_S : 1][F_S + 1];
+  // W1 [c][e] at c * F + (e ^ c) (w1_at): a lane per row c (z = W1 h) or per column
+  // (W1^T v) hits 64 distinct banks either way, without padding (the LDS of five
+  // work-groups fits a CU)
+  float W1[kReadout ? F_S * F_S : 1];
 };
+
+__device__ __forceinline__ int w1_at(int c, int e) { return c * F_S + (e ^ c); }
 
 // Staging of the LDS weights in two halves: fetch() issues the thread's global loads into
 // registers, store() writes them to LDS, so that independent work (the reverse kernel's
@@ -102,7 +108,10 @@ struct Stager {
       if (e < kW) L.W[(e % F_S) * kLdW + e / F_S] = v[u];
       else if (e < kW + kT) L.Td[(e - kW) / F_S][(e - kW) % F_S] = v[u];
       else if (e < kW + 2 * kT) L.Ts[(e - kW - kT) / F_S][(e - kW - kT) % F_S] = v[u];
-      else if (kReadout && e < kN) L.W1[(e - kW - 2 * kT) / F_S][(e - kW - 2 * kT) % F_S] = v[u];
+      else if (kReadout && e < kN) {
+        const int rr = (e - kW - 2 * kT) / F_S, cc = (e - kW - 2 * kT) % F_S;
+        L.W1[w1_at(rr, cc)] = v[u];
+      }
     }
   }
 };
@@ -134,10 +143,11 @@ __device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
 // One 16-pair tile of the receiver's compact row (pairs t0 .. t0 + 15 of the wave's LDS
 // table), for the lane's channel block b (channel 16 b + cl) and D rows r (pair t0 + 4 g + r):
 //   m[b][r]  = f_c SiLU(a)                                    the message
-//   dm[b][r] = f_c' SiLU(a) + f_c SiLU'(a) (W_r b')_c          its derivative in r
+//   dm[b][r] = f_c' SiLU(a) + f_c SiLU'(a) (W_r b')_c          its derivative in r (DM only)
 // with a = (W_r b)_c + T_d[z_i][c] + T_s[z_j][c].  Rows past the row give m = dm = 0 (no
-// branches: they read slot 0 and are masked).
-template <bool BF16>
+// branches: they read slot 0 and are masked).  The message alone (DM false) skips the
+// derivative's product; where both are computed, m has the same bits either way.
+template <bool BF16, bool DM>
 __device__ __forceinline__ void small_tile(const SmallLds<true>& L, const float4* sG,
                                            const int* sZ, int t0, int cnt, int zi_s, int g,
                                            int cl, float sigma, float inv_s2, float pi_rc,
@@ -176,14 +186,15 @@ __device__ __forceinline__ void small_tile(const SmallLds<true>& L, const float4
       return L.W[c * kLdW + kk];
     };
     const f32x4 acc = radial_mfma<BF16>([&](int e) { return bv[e]; }, wk, true);
-    const f32x4 accd = radial_mfma<BF16>([&](int e) { return dbv[e]; }, wk, true);
+    f32x4 accd = {0.f, 0.f, 0.f, 0.f};
+    if (DM) accd = radial_mfma<BF16>([&](int e) { return dbv[e]; }, wk, true);
     const float td = L.Td[zi_s][c];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float sv, dsv;
       silu_and_grad(acc[r] + td + L.Ts[zz[r]][c], sv, dsv);
       m[b][r] = fc[r] * sv;
-      dm[b][r] = fmaf(dfc[r], sv, fc[r] * dsv * accd[r]);
+      if (DM) dm[b][r] = fmaf(dfc[r], sv, fc[r] * dsv * accd[r]);
     }
     // one channel block at a time: the products of all four blocks in flight would hold
     // 32 more registers than the kernel can spare at three waves per SIMD
@@ -224,9 +235,9 @@ __device__ __forceinline__ void small_tile_store(const float (&dm)[4][4], const 
 //   4. s_ij = g_i . dm_ij/dr for every pair of the row (kept tiles from registers, the
 //      others recomputed with the same arithmetic), written to the pair's slot.
 // KEEP is a tile shape of the autotuner: registers capped at 168 (three waves per SIMD)
-// with it, at 128 (four) without; LDS holds four work-groups per CU.
+// with it, at 102 (five) without; 32 KiB of LDS lets five work-groups share a CU.
 template <bool BF16, bool KEEP>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KEEP ? 3 : 4)))
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KEEP ? 3 : 5)))
 k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
              const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
              double box, float* __restrict__ atom_e, float4* __restrict__ pw,
@@ -298,16 +309,16 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
     };
     constexpr int kKept = KEEP ? 2 : 0;   // tiles whose factors stay in registers
     if (KEEP) {
-      small_tile<BF16>(L, sg, sz, 0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dm0);
+      small_tile<BF16, true>(L, sg, sz, 0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dm0);
       add_h();
       if (cnt > kTile) {
-        small_tile<BF16>(L, sg, sz, kTile, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dm1);
+        small_tile<BF16, true>(L, sg, sz, kTile, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dm1);
         add_h();
       }
     }
     for (int t0 = kKept * kTile; t0 < cnt; t0 += kTile) {
       float dmx[4][4];
-      small_tile<BF16>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
+      small_tile<BF16, false>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
       add_h();
     }
     // h[c] for c = 16 b + cl: add the four pair groups
@@ -325,7 +336,7 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
     const int c = lane;
     float z = 0.f;
 #pragma unroll 8
-    for (int e = 0; e < F_S; ++e) z = fmaf(L.W1[c][e], sVec[w][e], z);
+    for (int e = 0; e < F_S; ++e) z = fmaf(L.W1[w1_at(c, e)], sVec[w][e], z);
     float y, dy;
     silu_and_grad(z, y, dy);
     const float w2 = P.w2[c];
@@ -335,7 +346,7 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
     wave_sync();
     float gi = 0.f;
 #pragma unroll 8
-    for (int k = 0; k < F_S; ++k) gi = fmaf(L.W1[k][c], sVec[w][k], gi);
+    for (int k = 0; k < F_S; ++k) gi = fmaf(L.W1[w1_at(k, c)], sVec[w][k], gi);
     if (lane == 0) atom_e[i] = e_i;
     // 4. s_ij per pair into the pair's slot
     float gb[4];
@@ -347,7 +358,7 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
     }
     for (int t0 = kKept * kTile; t0 < cnt; t0 += kTile) {
       float dmx[4][4];
-      small_tile<BF16>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
+      small_tile<BF16, true>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
       small_tile_store(dmx, gb, sg, sP[w], t0, cnt, g, cl, pw);
     }
     wave_sync();
