@@ -202,14 +202,15 @@ __device__ __forceinline__ void small_tile(const SmallLds<true>& L, const float4
   }
 }
 
-// s_ij = dE_i/dr_ij = sum_c g_c dm[c] for the tile's pairs, written with the pair's unit
-// vector to its slot of the list: pw[p] = (d_ij / r_ij, s_ij).  gb[b] = g at channel
-// 16 b + cl.  The channel sum of pair t0 + 4 g + r is in-lane over b, then over the 16
-// lanes of group g; lane cl = r of the group writes it.
+// s_ij = dE_i/dr_ij = sum_c g_c dm[c] for the tile's pairs (gb[b] = g at channel 16 b + cl).
+// The channel sum of pair t0 + 4 g + r is in-lane over b, then over the 16 lanes of group g;
+// lane cl = r of the group writes s to the pair's list slot, spar[p], and the pair's record
+// to the receiver's compact row, rec[k] = (d_ij / r_ij, p).
 __device__ __forceinline__ void small_tile_store(const float (&dm)[4][4], const float (&gb)[4],
                                                  const float4* sG, const int* sP, int t0,
                                                  int cnt, int g, int cl,
-                                                 float4* __restrict__ pw) {
+                                                 float4* __restrict__ rec,
+                                                 float* __restrict__ spar) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     float part = 0.f;
@@ -220,27 +221,31 @@ __device__ __forceinline__ void small_tile_store(const float (&dm)[4][4], const 
     if (cl == r && q < cnt) {
       const float4 gv = sG[q];
       const float ir = __builtin_amdgcn_rcpf(gv.w);
-      pw[sP[q]] = make_float4(gv.x * ir, gv.y * ir, gv.z * ir, part);
+      const int p = sP[q];
+      spar[p] = part;
+      rec[q] = make_float4(gv.x * ir, gv.y * ir, gv.z * ir, __int_as_float(p));
     }
   }
 }
 
 // The evaluation kernel, one wavefront per receiver:
 //   1. the receiver's list row (which may come from a longer cutoff) at the current
-//      positions: the pairs inside the cutoff, in row order, go to an LDS table; every
-//      other real entry of the row gets pw[p] = 0 (no force through it);
+//      positions: the pairs inside the cutoff, in row order, go to an LDS table (pairs past
+//      the per-atom cap raise the overflow flag and get s = 0);
 //   2. the messages on MFMA tiles, summed into h_i in registers; with KEEP the derivative
 //      factors dm/dr of the first two tiles stay in registers;
 //   3. the readout: E_i and g_i = dE_i/dh_i;
-//   4. s_ij = g_i . dm_ij/dr for every pair of the row (kept tiles from registers, the
-//      others recomputed with the same arithmetic), written to the pair's slot.
+//   4. s_ij = g_i . dm_ij/dr for every pair inside the cutoff (kept tiles from registers,
+//      the others recomputed with the same arithmetic), written to the pair's list slot,
+//      with the pair's record in the receiver's compact row (rec, cnt) for the force kernel.
 // KEEP is a tile shape of the autotuner: registers capped at 168 (three waves per SIMD)
 // with it, at 102 (five) without; 32 KiB of LDS lets five work-groups share a CU.
 template <bool BF16, bool KEEP>
 __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KEEP ? 3 : 5)))
 k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
              const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
-             double box, float* __restrict__ atom_e, float4* __restrict__ pw,
+             double box, float* __restrict__ atom_e, float4* __restrict__ rec_all,
+             float* __restrict__ spar, int32_t* __restrict__ cnt_all,
              uint32_t* __restrict__ flags) {
   __shared__ SmallLds<true> L;
   __shared__ int sZ[kWaves][kCap];
@@ -284,8 +289,8 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
           sZ[w][k] = zj;
           sG[w][k] = make_float4(dx, dy, dz, r);
           sP[w][k] = p;
-        } else if (j >= 0) {
-          pw[p] = make_float4(0.f, 0.f, 0.f, 0.f);   // outside the cutoff (or past the cap)
+        } else if (ok) {
+          spar[p] = 0.f;   // past the cap: left out of the sums (and flagged below)
         }
         cnt += __popcll(mask);
       }
@@ -293,8 +298,10 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
         if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
         cnt = kCap;
       }
+      if (lane == 0) cnt_all[i] = cnt;
     }
     wave_sync();
+    float4* rec = rec_all + (size_t)i * kCap;
     // 2. messages on MFMA tiles, summed over pairs in registers
     const int zi_s = species[i];
     const float4* sg = sG[w];
@@ -353,57 +360,44 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
 #pragma unroll
     for (int b = 0; b < 4; ++b) gb[b] = __shfl(gi, 16 * b + cl, 64);
     if (KEEP) {
-      small_tile_store(dm0, gb, sg, sP[w], 0, cnt, g, cl, pw);
-      if (cnt > kTile) small_tile_store(dm1, gb, sg, sP[w], kTile, cnt, g, cl, pw);
+      small_tile_store(dm0, gb, sg, sP[w], 0, cnt, g, cl, rec, spar);
+      if (cnt > kTile) small_tile_store(dm1, gb, sg, sP[w], kTile, cnt, g, cl, rec, spar);
     }
     for (int t0 = kKept * kTile; t0 < cnt; t0 += kTile) {
       float dmx[4][4];
       small_tile<BF16, true>(L, sg, sz, t0, cnt, zi_s, g, cl, P.sigma, inv_s2, pi_rc, m, dmx);
-      small_tile_store(dmx, gb, sg, sP[w], t0, cnt, g, cl, pw);
+      small_tile_store(dmx, gb, sg, sP[w], t0, cnt, g, cl, rec, spar);
     }
     wave_sync();
   }
 }
 
-// Forces F_i = sum_j (s_ij + s_ji) d_ij / r_ij over the receiver's list row, s_ji read from
-// the reverse slot rev[p] (one wave per atom).  Entries outside the cutoff hold zeros; the
-// pairs inside it are compacted in row order (a ballot, as in the evaluation kernel) and
-// summed by their position in that order, so the bits do not depend on the list's own
-// cutoff or padding (a list built at the model's cutoff and a longer shared one give the
-// same forces).  The kernel reads no positions, so the integrator program that follows the
-// evaluation runs in its epilogue once F_i is final (a drift there cannot race with
-// another wave).
+// Forces F_i = sum_j (s_ij + s_ji) d_ij / r_ij over the receiver's compact row (the pairs
+// inside the cutoff in row order, one per lane: the row holds at most 64), s_ji read from
+// the reverse list slot rev[p].  The sum runs over the positions in the compact row, so the
+// bits do not depend on the list's own cutoff or padding (a list built at the model's
+// cutoff and a longer shared one give the same forces).  The kernel reads no positions, so
+// the integrator program that follows the evaluation runs in its epilogue once F_i is
+// final (a drift there cannot race with another wave).
 __global__ void __launch_bounds__(256)
-k_small_force(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
-              const int32_t* __restrict__ rev, int n, const float4* __restrict__ pw,
+k_small_force(const int32_t* __restrict__ rev, int n, const float4* __restrict__ rec_all,
+              const float* __restrict__ spar, const int32_t* __restrict__ cnt_all,
               float* __restrict__ forces, Epilogue E, bool has_ep, bool fresh_small) {
-  __shared__ float4 sC[4][kCap];   // per wave: the pair terms by position in the compact row
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
   CoordIn ein{};   // the atom's integrator inputs, coordinate d = lane (lanes 0..2)
   if (has_ep && lane < 3) ein = prefetch_coord(E, i, n, lane, fresh_small);
-  const int row0 = offs[i], row1 = offs[i + 1];
-  int cnt = 0;
-  for (int base = row0; base < row1; base += 64) {
-    const int p = base + lane;
-    const int j = p < row1 ? nbr[p] : -1;
-    const int q = j >= 0 ? rev[p] : -1;
-    const float4 a = j >= 0 ? pw[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-    // a pair inside the cutoff has a unit vector; one outside (or past the evaluation's
-    // cap) holds zeros.  A missing reverse entry (an overflowed row) adds nothing.
-    const bool ok = a.x != 0.f || a.y != 0.f || a.z != 0.f;
-    const float sb = ok && q >= 0 ? pw[q].w : 0.f;
-    const uint64_t mask = __ballot(ok);
-    const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
-    if (ok && k < kCap) {
-      const float s = a.w + sb;
-      sC[w][k] = make_float4(s * a.x, s * a.y, s * a.z, 0.f);
-    }
-    cnt += __popcll(mask);
+  const int cnt = cnt_all[i];
+  float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (lane < cnt) {
+    const float4 a = rec_all[(size_t)i * kCap + lane];
+    const int p = __float_as_int(a.w);
+    const int q = rev[p];
+    // a missing reverse entry (an overflowed row) adds nothing
+    const float s = spar[p] + (q >= 0 ? spar[q] : 0.f);
+    t = make_float4(s * a.x, s * a.y, s * a.z, 0.f);
   }
-  wave_sync();
-  const float4 t = lane < cnt ? sC[w][lane] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float fx = wave_sum(t.x), fy = wave_sum(t.y), fz = wave_sum(t.z);
   if (lane == 0) {
     forces[i] = fx;
@@ -417,12 +411,13 @@ k_small_force(const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
 
 }  // namespace
 
-// Workspace of one evaluation: the per-slot pair records (d/r, s) of a list with room for
-// max_pairs entries, atom energies [n], the energy partial sums.
+// Workspace of one evaluation: the compact rows of pair records [n][kCap] (d/r, list slot),
+// s per list slot (a list with room for max_pairs entries), the rows' lengths [n], atom
+// energies [n], the energy partial sums.
 size_t small_workspace_bytes(int32_t n, int64_t max_pairs) {
   const size_t N = (size_t)(n + 63) / 64 * 64;
-  return sizeof(float4) * (size_t)max_pairs + sizeof(float) * N +
-         sizeof(double) * energy_partials(n) + 256;
+  return sizeof(float4) * N * kCap + sizeof(float) * (size_t)max_pairs +
+         sizeof(int32_t) * N + sizeof(float) * N + sizeof(double) * energy_partials(n) + 256;
 }
 
 dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const int32_t* species,
@@ -436,9 +431,12 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
                  DMTS_E_OOM, "small model: workspace");
   }
   char* base = ws ? ws : m->atom_ws.as<char>();
-  float4* pw = reinterpret_cast<float4*>(base);
-  float* e_ws = reinterpret_cast<float*>(pw + nl->max_pairs);
-  double* e_part = reinterpret_cast<double*>(e_ws + N);   // 8-byte aligned: N % 64 == 0
+  float4* rec = reinterpret_cast<float4*>(base);
+  int32_t* cnt = reinterpret_cast<int32_t*>(rec + N * kCap);
+  float* e_ws = reinterpret_cast<float*>(cnt + N);
+  // 8-byte aligned: N % 64 == 0
+  double* e_part = reinterpret_cast<double*>(e_ws + N);
+  float* spar = reinterpret_cast<float*>(e_part + energy_partials(n));
   float* e_atom = atom_energy ? atom_energy : e_ws;
   SmallParams P{m->p(m->bf16 ? m->o_WbR : m->o_WbT), m->p(m->o_Td), m->p(m->o_Ts),
                 m->p(m->bf16 ? m->o_W1R : m->o_W1), m->p(m->bf16 ? m->o_W1TR : m->o_W1T),
@@ -462,14 +460,14 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
             sh.grid, natural,
             resident_groups(reinterpret_cast<const void*>(&k_small_eval<BF, KEEP>), kWaves * 64));
         launch_timed(ps, &k_small_eval<BF, KEEP>, dim3(blocks), dim3(kWaves * 64), s, P,
-                     nl->offs, nl->nbr, pos, species, n, box, e_atom, pw, nl->flags);
+                     nl->offs, nl->nbr, pos, species, n, box, e_atom, rec, spar, cnt,
+                     nl->flags);
       }
       if (hipPeekAtLastError() != hipSuccess || !forces) return;
       if (fuse && ep->wait) (void)hipStreamWaitEvent(s, ep->wait, 0);
       ProfScope ps(DMTS_K_SMALL_BACKWARD, s, true);
-      launch_timed(ps, &k_small_force, dim3(ceil_div(n, 4)), dim3(256), s, nl->offs, nl->nbr,
-                   nl->rev, n, pw, forces, fuse ? *ep : Epilogue{}, fuse,
-                   fuse && forces == ep->Fs);
+      launch_timed(ps, &k_small_force, dim3(ceil_div(n, 4)), dim3(256), s, nl->rev, n, rec,
+                   spar, cnt, forces, fuse ? *ep : Epilogue{}, fuse, fuse && forces == ep->Fs);
     };
     if (m->bf16) {
       if (sh.keep) run(std::true_type{}, std::true_type{});
@@ -496,7 +494,7 @@ dmts_status small_energy_forces(Model* m, NList* nl, const double* pos, const in
 // uses the device address from hipGetSymbolAddress.
 constexpr int32_t kNoAllocMaxAtoms = 8192;
 constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 20;
-constexpr size_t kNoAllocBytes = size_t(17) << 20;   // >= small_workspace_bytes(both maxima)
+constexpr size_t kNoAllocBytes = size_t(13) << 20;   // >= small_workspace_bytes(both maxima)
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
