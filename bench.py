@@ -188,6 +188,8 @@ def parse():
                     help="frames of the reference run the readout is fitted on (50 fs apart)")
     ap.add_argument("--no-nve", action="store_true",
                     help="skip the 10 ps NVE drift run of the throughput line")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="skin of the reference lists in A (default: the library's)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shapes instead of tuning them for the workload")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
@@ -476,6 +478,8 @@ def main():
 
     # ---------------------------------------------------------------- DMTS timed region
     st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_out, n_inner, 64, 128)
+    if args.skin is not None:
+        st.set_skin(args.skin)
     if args.hmr:
         st.set_atom_masses(sy.hmr_masses())
     if args.gamma > 0.0:
@@ -500,6 +504,7 @@ def main():
     H_start = st.energies[3].item()
     api.prof_enable([dom] if dom else ())
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    builds0 = st.list_builds
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
@@ -507,6 +512,7 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    list_builds = st.list_builds - builds0
     api.prof_enable(())
     prof = api.prof_read()
     gpu_ms = ev0.elapsed_time(ev1)
@@ -520,6 +526,7 @@ def main():
     vv = None
     if not args.no_verlet:
         st_v = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, dt_in, 1, 64, 128)
+        st_v.set_skin(st.skin)
         if args.hmr:
             st_v.set_atom_masses(sy.hmr_masses())
         if args.gamma > 0.0:
@@ -528,6 +535,7 @@ def main():
         st_v.step(xv, vvel, None, large, max(args.warmup, 1))
         torch.cuda.synchronize()
         n_vv = args.steps * n_inner
+        vb0 = st_v.list_builds
         t0 = time.perf_counter()
         ev0.record(stream)
         st_v.step(xv, vvel, None, large, n_vv)
@@ -535,7 +543,8 @@ def main():
         torch.cuda.synchronize()
         wall_v = time.perf_counter() - t0
         ms_vv = max(ev0.elapsed_time(ev1), wall_v * 1e3) / n_vv
-        vv = dict(ns_per_day=0.0864 * dt_in / (ms_vv * 1e-3), ms_per_step=ms_vv)
+        vv = dict(ns_per_day=0.0864 * dt_in / (ms_vv * 1e-3), ms_per_step=ms_vv,
+                  list_builds=st_v.list_builds - vb0, evaluations=n_vv)
 
     # ---------------------------------------------------------------- 10 ps NVE drift
     nve = None
@@ -621,6 +630,12 @@ def main():
         "atom_steps_per_s": round(atom_steps, 1),
         "verlet_ns_per_day": round(vv["ns_per_day"], 4) if vv else None,
         "verlet_ms_per_step": round(vv["ms_per_step"], 5) if vv else None,
+        "list_rebuilds": {"skin_A": st.skin,
+                          "dmts": {"rebuilds": list_builds, "reference_evaluations": args.steps,
+                                   "simulated_fs": args.steps * dt_out},
+                          "verlet": ({"rebuilds": vv["list_builds"],
+                                      "reference_evaluations": vv["evaluations"],
+                                      "simulated_fs": vv["evaluations"] * dt_in} if vv else None)},
         "speedup_vs_verlet": round(ns_day / vv["ns_per_day"], 3) if vv else None,
         "errors_vs_fp64": errors,
         "energy_drift_per_atom": (H_end - H_start) / sy.n_atoms if args.gamma <= 0.0 else None,

@@ -257,8 +257,12 @@ dmts_status nnp_energy_forces_noalloc(nnp_model* model, nnp_nlist* nl, const dou
  * dmts_state_fallbacks: number of dmts_step calls that had to be redone because an atom
  *   moved farther than the shared neighbor list allows (see the neighbor-list note).
  *
- * Neighbor-list note: each reference evaluation builds one list at
- * max(r_c,large, r_c,small + 1 A); the fast model of the next inner steps reuses it, which
+ * Neighbor-list note: each reference evaluation gets one list at
+ * max(r_c,large, r_c,small + 1 A) (at r_c,large for the single-time-step baseline), filtered
+ * at the current positions from rows kept at that cutoff plus a skin (dmts_state_set_skin);
+ * the rows themselves are rebuilt only when some atom has moved half the skin since their
+ * last rebuild, so the list is the one a fresh build would give.  The fast model of the
+ * next inner steps reuses the reference evaluation's list, which
  * is exact while every atom stays within half the gap to the fast cutoff of where the
  * list was built.  The device checks that bound at every drift; when it fails, the call
  * restores its starting x, v and carried forces and repeats with fresh lists for every
@@ -328,6 +332,24 @@ dmts_status dmts_state_set_fdiff_threshold(dmts_state* st, double eV_per_A);
 dmts_status dmts_state_fdiff(dmts_state* st, int64_t* n_sts_redos, double* last_breach);
 dmts_status dmts_state_forces(dmts_state* st, const float** f_large, const float** f_small);
 dmts_status dmts_state_flags(dmts_state* st, void* stream, uint32_t* host_flags);
+
+/* Skin of the reference evaluations' lists (neighbor-list note; not a passage of the paper,
+ * which leaves the neighbor search open: a Verlet-list skin as in any molecular-dynamics
+ * code).
+ * dmts_state_set_skin: skin_A >= 0 (finite; DMTS_E_ARG otherwise), 1.5 A by default; 0
+ *   builds the list afresh at every reference evaluation.  The skin is also dropped (fresh
+ *   builds) for an open box or when cutoff + skin reaches half the box edge.  A change
+ *   takes effect at the next reference evaluation (which rebuilds).  Results do not depend
+ *   on the skin: the lists, and so every sum, are the same.  Rows at cutoff + skin must fit
+ *   the 256-entry row limit; a longer one raises DMTS_FLAG_NBR_OVERFLOW (DMTS_E_CAPACITY
+ *   from dmts_step) as a fresh build's would.
+ * dmts_state_get_skin: the skin in use (A).
+ * dmts_state_list_builds: the number of row rebuilds so far (blocking: synchronizes the
+ *   device).
+ */
+dmts_status dmts_state_set_skin(dmts_state* st, double skin_A);
+dmts_status dmts_state_get_skin(dmts_state* st, double* skin_A);
+dmts_status dmts_state_list_builds(dmts_state* st, int64_t* n_builds);
 
 /* ---------------------------------------------------------------- kernel timing
  * Optional HIP-event timing of individual kernel classes, for measurement harnesses.

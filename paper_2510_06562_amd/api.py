@@ -94,6 +94,9 @@ _SIGS = {
     "dmts_state_fdiff": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_D)], _I32),
     "dmts_state_forces": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I32),
     "dmts_state_flags": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], _I32),
+    "dmts_state_set_skin": ([_P, _D], _I32),
+    "dmts_state_get_skin": ([_P, ctypes.POINTER(_D)], _I32),
+    "dmts_state_list_builds": ([_P, ctypes.POINTER(_I64)], _I32),
     "dmts_prof_enable": ([ctypes.c_uint32], _I32),
     "dmts_prof_reset": ([], _I32),
     "dmts_prof_read": ([_I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I32),
@@ -469,6 +472,23 @@ class DMTS:
         k = ctypes.c_uint64()
         _check(lib().dmts_state_o_steps(self._h, ctypes.byref(k)))
         return k.value
+
+    def set_skin(self, skin_A: float):
+        """Skin of the reference evaluations' lists (A; 0 = a fresh build every time)."""
+        _check(lib().dmts_state_set_skin(self._h, float(skin_A)))
+
+    @property
+    def skin(self) -> float:
+        d = ctypes.c_double()
+        _check(lib().dmts_state_get_skin(self._h, ctypes.byref(d)))
+        return d.value
+
+    @property
+    def list_builds(self) -> int:
+        """Rebuilds of the skin list's rows so far (synchronizes the device)."""
+        n = ctypes.c_int64()
+        _check(lib().dmts_state_list_builds(self._h, ctypes.byref(n)))
+        return n.value
 
     @property
     def fallbacks(self) -> int:

@@ -78,6 +78,23 @@ struct NList {
   int32_t n_cells_cap = 0;
 };
 
+// Skin of the integrator's reference lists (A): the rows are rebuilt once some atom has
+// moved half of it.
+constexpr double kDefaultSkin = 1.5;
+
+// A list kept between the evaluations of an integrator: staging rows (ell, len of `rows`) at
+// cutoff + skin, rebuilt only when an atom has moved at least skin/2 since the last rebuild,
+// and filtered to the cutoff at the current positions at every evaluation.
+struct SkinList {
+  NList* rows = nullptr;       // rows at cutoff + skin (ell, len), cells, overflow flag
+  double* x_build = nullptr;   // [3][n] positions of the last rebuild
+  uint32_t* gate = nullptr;    // [2]: rebuild requested, rebuilds so far
+  double skin = 0.0;
+  // parameters of the current rows; a change forces a rebuild
+  double cutoff = -1.0, box = -1.0;
+  int32_t n = -1;
+};
+
 // pos_copy (optional, float64 [3][n]): receives the positions the list is built from.
 dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
                             const int32_t* sys_offsets, int32_t n_sys, double cutoff,
@@ -85,6 +102,12 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
 // The list at a cutoff <= the parent's, from the parent's rows at the current positions.
 dmts_status filter_neighbors(NList* child, const NList* parent, const double* pos,
                              double cutoff, hipStream_t s);
+// The list at `cutoff` for the current positions through the skin list `sk` (which must
+// hold max_atoms >= n); the same rows as build_neighbors.  Falls back to build_neighbors
+// when the skin is 0, the box is open or cutoff + skin reaches half the box edge.
+dmts_status refresh_neighbors(NList* nl, SkinList* sk, const double* pos, int32_t n,
+                              double box, double cutoff, hipStream_t s,
+                              double* pos_copy = nullptr);
 
 // ------------------------------------------------------------------ models
 // Tile shape of one evaluation (see nnp_tile_shape in the ABI header).

@@ -120,6 +120,7 @@ struct State {
   NList* nl_small = nullptr;
   NList* nl_large = nullptr;
   NList* nl_large2 = nullptr;   // the shared list is double-buffered: nl_large / nl_large2
+  SkinList skin;                // the reference evaluations' lists come from its rows
   int shared_cur = 0;           // which of the two is the fast model's current list
   hipStream_t side = nullptr;   // fast evaluations overlapped with reference evaluations
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -243,9 +244,9 @@ struct Runner {
     // (in shared mode at list_cut into the other buffer of the shared list, recording x_ref
     // for the fast model's displacement check, after which it becomes the current one)
     NList* nl = shared ? shared_list(st->shared_cur ^ 1) : st->nl_large;
-    r = build_neighbors(nl, x, st->n, st->box, nullptr, 1,
-                        shared ? list_cut : (double)large->desc.cutoff, q,
-                        shared ? st->x_ref : nullptr);
+    r = refresh_neighbors(nl, &st->skin, x, st->n, st->box,
+                          shared ? list_cut : (double)large->desc.cutoff, q,
+                          shared ? st->x_ref : nullptr);
     if (r != DMTS_OK) return r;
     if (shared) st->shared_cur ^= 1;
     return energy_forces(large, nl, x, st->species, st->n, st->box, nullptr, 1,
@@ -425,6 +426,10 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
   if (r == DMTS_OK)
     r = nnp_nlist_create(n_atoms, (int64_t)n_atoms * (max_nbrs_large + 16), 16,
                          reinterpret_cast<nnp_nlist**>(&st->nl_large2));
+  // the skin list only uses its staging rows: no CSR capacity
+  if (r == DMTS_OK)
+    r = nnp_nlist_create(n_atoms, 4, 16, reinterpret_cast<nnp_nlist**>(&st->skin.rows));
+  st->skin.skin = dmts::kDefaultSkin;
   double hm[16] = {0}, him[16] = {0};
   for (int z = 0; z < n_species; ++z) {
     hm[z] = host_mass_by_species[z];
@@ -437,6 +442,9 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     e = hipMalloc(&st->FL, sizeof(float) * 3 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->Fs, sizeof(float) * 3 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->x_ref, sizeof(double) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&st->skin.x_build, sizeof(double) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&st->skin.gate, sizeof(uint32_t) * 2);
+    if (e == hipSuccess) e = hipMemset(st->skin.gate, 0, sizeof(uint32_t) * 2);
     if (e == hipSuccess) e = hipMalloc(&st->bak, sizeof(double) * 9 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->mass, sizeof(double) * 16);
     if (e == hipSuccess) e = hipMalloc(&st->inv_mass, sizeof(double) * 16);
@@ -475,6 +483,9 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_small));
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large));
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large2));
+  nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->skin.rows));
+  (void)hipFree(st->skin.x_build);
+  (void)hipFree(st->skin.gate);
   if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
   if (st->ev_join) (void)hipEventDestroy(st->ev_join);
   if (st->side) (void)hipStreamDestroy(st->side);
@@ -580,6 +591,35 @@ extern "C" dmts_status dmts_state_fallbacks(dmts_state* h, int64_t* n_calls) {
   State* st = reinterpret_cast<State*>(h);
   DMTS_REQUIRE(st && n_calls, DMTS_E_ARG, "dmts_state_fallbacks: null argument");
   *n_calls = st->n_fallbacks;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_set_skin(dmts_state* h, double skin_A) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st, DMTS_E_ARG, "dmts_state_set_skin: null state");
+  DMTS_REQUIRE(skin_A >= 0.0 && std::isfinite(skin_A), DMTS_E_ARG,
+               "dmts_state_set_skin: skin %g must be finite and >= 0", skin_A);
+  if (skin_A != st->skin.skin) {
+    st->skin.skin = skin_A;
+    st->skin.n = -1;   // the rows were built for another skin: rebuild at the next use
+  }
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_get_skin(dmts_state* h, double* skin_A) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st && skin_A, DMTS_E_ARG, "dmts_state_get_skin: null argument");
+  *skin_A = st->skin.skin;
+  return DMTS_OK;
+}
+
+extern "C" dmts_status dmts_state_list_builds(dmts_state* h, int64_t* n_builds) {
+  State* st = reinterpret_cast<State*>(h);
+  DMTS_REQUIRE(st && n_builds, DMTS_E_ARG, "dmts_state_list_builds: null argument");
+  uint32_t g[2] = {0u, 0u};
+  DMTS_HIP(hipDeviceSynchronize());
+  DMTS_HIP(hipMemcpy(g, st->skin.gate, sizeof(g), hipMemcpyDeviceToHost));
+  *n_builds = g[1];
   return DMTS_OK;
 }
 

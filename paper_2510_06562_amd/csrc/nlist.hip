@@ -14,6 +14,14 @@
 // into a fixed-width staging table), scan of row lengths, compaction into CSR with the
 // reverse index rev[p] (binary search of i in the sorted row of j).  Rows are padded with
 // -1 to a multiple of the list's row alignment.
+//
+// The integrator's reference evaluations go through a skin list instead (a Verlet list:
+// rows at r_c + skin, valid while no atom has moved skin/2 since they were built).  Per
+// evaluation: the displacement test (inside the one-work-group binning, or a launch of its
+// own), binning only if it failed, then one launch that rebuilds a receiver's skin row
+// when asked and filters it to r_c at the current positions, then the scan and compaction
+// above.  Filtering keeps the ascending order, and a row at r_c + skin holds every pair
+// within r_c while the bound holds, so the list is exactly the one a fresh build gives.
 #include "common.h"
 
 namespace dmts {
@@ -52,8 +60,10 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* red) {
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_sums(const int32_t* __restrict__ in,
                                                            int32_t n,
-                                                           int64_t* __restrict__ part) {
+                                                           int64_t* __restrict__ part,
+                                                           const uint32_t* __restrict__ gate) {
   __shared__ int64_t red[kScanThreads / 64];
+  if (gate && gate[0] == 0u) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   int64_t s = 0;
 #pragma unroll
@@ -72,9 +82,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int32_t* __restrict
                                                             uint32_t* __restrict__ flags,
                                                             bool zero_in,
                                                             const int64_t* __restrict__ part,
-                                                            int n_tiles) {
+                                                            int n_tiles,
+                                                            const uint32_t* __restrict__ gate) {
   __shared__ int64_t red[kScanThreads / 64];
   __shared__ int64_t wsum[kScanThreads / 64];
+  if (gate && gate[0] == 0u) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   // offset of this tile and the grand total
   int64_t before = 0, all = 0;
@@ -134,8 +146,10 @@ __global__ void __launch_bounds__(kScanOneThreads) k_scan_one(int32_t* __restric
                                                              int32_t* __restrict__ copy_to,
                                                              int32_t n, int64_t cap,
                                                              uint32_t* __restrict__ flags,
-                                                             bool zero_in) {
+                                                             bool zero_in,
+                                                             const uint32_t* __restrict__ gate) {
   __shared__ int64_t wsum[kScanOneThreads / 64];
+  if (gate && gate[0] == 0u) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int k0 = t * kScanOnePer;
   int32_t v[kScanOnePer];
@@ -176,17 +190,18 @@ __global__ void __launch_bounds__(kScanOneThreads) k_scan_one(int32_t* __restric
 }
 
 // The scan: one launch up to kScanOne elements, else the two tile launches (`part` holds at
-// least scan_tiles(n) values).
+// least scan_tiles(n) values).  With `gate`, every launch returns at once unless gate[0] is
+// set (the skin list's conditional rebuild).
 void scan(int32_t* in, int32_t* out, int32_t* copy_to, int32_t n, int64_t cap, uint32_t* flags,
-          bool zero_in, int64_t* part, hipStream_t s) {
+          bool zero_in, int64_t* part, hipStream_t s, const uint32_t* gate = nullptr) {
   if (n <= kScanOne) {
-    k_scan_one<<<1, kScanOneThreads, 0, s>>>(in, out, copy_to, n, cap, flags, zero_in);
+    k_scan_one<<<1, kScanOneThreads, 0, s>>>(in, out, copy_to, n, cap, flags, zero_in, gate);
     return;
   }
   const int tiles = scan_tiles(n);
-  k_scan_sums<<<tiles, kScanThreads, 0, s>>>(in, n, part);
+  k_scan_sums<<<tiles, kScanThreads, 0, s>>>(in, n, part, gate);
   k_scan_tiles<<<tiles, kScanThreads, 0, s>>>(in, out, copy_to, n, cap, flags, zero_in, part,
-                                              tiles);
+                                              tiles, gate);
 }
 
 __device__ __forceinline__ int cell_coord(double x, double box, double inv_cell, int nc) {
@@ -198,7 +213,9 @@ __device__ __forceinline__ int cell_coord(double x, double box, double inv_cell,
 
 __global__ void k_cell_assign(const double* __restrict__ pos, int32_t n, double box,
                               double inv_cell, int nc, int32_t* __restrict__ cell_of,
-                              int32_t* __restrict__ cell_count) {
+                              int32_t* __restrict__ cell_count,
+                              const uint32_t* __restrict__ gate) {
+  if (gate && gate[0] == 0u) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int cx = cell_coord(pos[i], box, inv_cell, nc);
@@ -210,7 +227,9 @@ __global__ void k_cell_assign(const double* __restrict__ pos, int32_t n, double 
 }
 
 __global__ void k_cell_scatter(const int32_t* __restrict__ cell_of, int32_t n,
-                               int32_t* __restrict__ cursor, int32_t* __restrict__ cell_atoms) {
+                               int32_t* __restrict__ cursor, int32_t* __restrict__ cell_atoms,
+                               const uint32_t* __restrict__ gate) {
+  if (gate && gate[0] == 0u) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int slot = atomicAdd(&cursor[cell_of[i]], 1);
@@ -223,13 +242,38 @@ __global__ void k_cell_scatter(const int32_t* __restrict__ cell_of, int32_t n,
 constexpr int kBinThreads = 1024;
 constexpr int kBinCells = 4096;
 constexpr int kBinAtoms = 32768;   // above this, the multi-work-group binning is faster
+// With `gate` (the skin list), the work-group first decides whether the rows must be
+// rebuilt: when gate[0] is already set, or some atom lies at least sqrt(half2) (half the
+// skin) from x_build, its position at the last rebuild (minimum image; a non-finite
+// distance counts as moved), it sets gate[0] and bins; otherwise it returns at once and
+// the gated launches after it do nothing.
 __global__ void __launch_bounds__(kBinThreads)
 k_bin_one(const double* __restrict__ pos, int32_t n, double box, double inv_cell, int nc,
           int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_start,
-          int32_t* __restrict__ cell_atoms) {
+          int32_t* __restrict__ cell_atoms, const double* __restrict__ x_build, double half2,
+          uint32_t* __restrict__ gate) {
   __shared__ int32_t cnt[kBinCells];
   __shared__ int32_t part[kBinThreads];
+  __shared__ int32_t s_moved;
   const int t = threadIdx.x, n_cells = nc * nc * nc;
+  if (gate) {
+    if (t == 0) s_moved = 0;
+    __syncthreads();
+    const double inv_box = 1.0 / box;
+    bool moved = false;
+    for (int i = t; i < n; i += kBinThreads) {
+      const double dx = minimage(pos[i] - x_build[i], box, inv_box);
+      const double dy = minimage(pos[n + i] - x_build[n + i], box, inv_box);
+      const double dz = minimage(pos[2 * n + i] - x_build[2 * n + i], box, inv_box);
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      moved = moved || !(d2 < half2);
+    }
+    if (moved) s_moved = 1;
+    __syncthreads();
+    if (!s_moved && gate[0] == 0u) return;   // the same decision in every thread
+    __syncthreads();                         // every thread has read gate[0]
+    if (t == 0) gate[0] = 1u;
+  }
   for (int c = t; c < n_cells; c += kBinThreads) cnt[c] = 0;
   __syncthreads();
   for (int i = t; i < n; i += kBinThreads) {
@@ -263,6 +307,23 @@ k_bin_one(const double* __restrict__ pos, int32_t n, double box, double inv_cell
   if (t == 0) cell_start[n_cells] = n;
   __syncthreads();
   for (int i = t; i < n; i += kBinThreads) cell_atoms[atomicAdd(&cnt[cell_of[i]], 1)] = i;
+}
+
+// The displacement test of k_bin_one for the multi-work-group binning: any atom at least
+// sqrt(half2) from x_build sets gate[0].
+__global__ void k_skin_check(const double* __restrict__ pos, int32_t n, double box,
+                             const double* __restrict__ x_build, double half2,
+                             uint32_t* __restrict__ gate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool moved = false;
+  if (i < n) {
+    const double inv_box = 1.0 / box;
+    const double dx = minimage(pos[i] - x_build[i], box, inv_box);
+    const double dy = minimage(pos[n + i] - x_build[n + i], box, inv_box);
+    const double dz = minimage(pos[2 * n + i] - x_build[2 * n + i], box, inv_box);
+    moved = !(dx * dx + dy * dy + dz * dz < half2);
+  }
+  if (__ballot(moved) != 0ull && (threadIdx.x & 63) == 0) atomicOr(gate, 1u);
 }
 
 struct Geo {
@@ -367,6 +428,42 @@ __device__ __forceinline__ void molecule_range(const int32_t* sys_offsets, int32
 constexpr int kNbWaves = 4;
 constexpr int kRowCap = kNlistRowCap;
 
+// Search of receiver i's row: the accepted senders, in candidate order, into row[] (LDS,
+// at most kRowCap of them).  Returns the full count, which may exceed kRowCap.  Whole wave.
+template <bool kCells>
+__device__ __forceinline__ int search_row(const Geo& g, const CellCtx& cc,
+                                          const int32_t* sys_offsets, int32_t n_sys, int i,
+                                          int32_t* s_pref, int32_t* s_first, int32_t* row) {
+  const int lane = threadIdx.x & 63;
+  const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
+  int lo = 0, hi = 0;
+  if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
+  int run = 0;
+  walk_candidates<kCells>(i, lo, hi, cc, s_pref, s_first, [&](int j, bool ok) {
+    bool acc = ok && within(g, xi, yi, zi, j);
+    uint64_t mask = __ballot(acc);
+    int p = run + __popcll(mask & ((1ull << lane) - 1ull));
+    if (acc && p < kRowCap) row[p] = j;
+    run += __popcll(mask);
+  });
+  wave_sync();
+  return run;
+}
+
+// Rank sort (senders are distinct: rank = number of smaller entries) of row[0 .. run) into
+// out, and into out2 when given.  Whole wave.
+__device__ __forceinline__ void sort_row(const int32_t* row, int run, int32_t* out,
+                                         int32_t* out2) {
+  const int lane = threadIdx.x & 63;
+  for (int e = lane; e < run; e += 64) {
+    const int v = row[e];
+    int rank = 0;
+    for (int k = 0; k < run; ++k) rank += row[k] < v;
+    out[rank] = v;
+    if (out2) out2[rank] = v;
+  }
+}
+
 // Search + sort of one receiver's row into ell[i][0 .. kRowCap); the row length goes to
 // len[i] and, padded to `align`, to cnt[i].  A row longer than kRowCap raises the
 // overflow flag and is cut.
@@ -380,57 +477,34 @@ k_rows(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNbWaves + w;
   if (i >= g.n) return;
-  const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
-  if (pos_copy && lane < 3) pos_copy[(size_t)lane * g.n + i] = lane == 0 ? xi : lane == 1 ? yi : zi;
-  int lo = 0, hi = 0;
-  if (!kCells) molecule_range(sys_offsets, n_sys, i, g.n, lo, hi);
-  int run = 0;
-  int32_t* row = s_row[w];
-  walk_candidates<kCells>(i, lo, hi, cc, s_pref[w], s_first[w], [&](int j, bool ok) {
-    bool acc = ok && within(g, xi, yi, zi, j);
-    uint64_t mask = __ballot(acc);
-    int p = run + __popcll(mask & ((1ull << lane) - 1ull));
-    if (acc && p < kRowCap) row[p] = j;
-    run += __popcll(mask);
-  });
+  if (pos_copy && lane < 3) pos_copy[(size_t)lane * g.n + i] = g.pos[(size_t)lane * g.n + i];
+  int run = search_row<kCells>(g, cc, sys_offsets, n_sys, i, s_pref[w], s_first[w], s_row[w]);
   if (run > kRowCap) {
     if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
     run = kRowCap;
   }
-  wave_sync();
-  // rank sort (senders are distinct): rank = number of smaller entries
-  int32_t* out = ell + (size_t)i * kRowCap;
-  for (int e = lane; e < run; e += 64) {
-    const int v = row[e];
-    int rank = 0;
-    for (int k = 0; k < run; ++k) rank += row[k] < v;
-    out[rank] = v;
-  }
+  sort_row(s_row[w], run, ell + (size_t)i * kRowCap, nullptr);
   if (lane == 0) {
     len[i] = run;
     cnt[i] = (run + align - 1) / align * align;
   }
 }
 
-// Rows of a list at a shorter cutoff from a parent list: the parent row of i (ascending
+// Row i of a list at a shorter cutoff from a parent row src[0 .. r_len) (ascending
 // senders, -1 padding) filtered to |d_ij| < r_c at the current positions.  Kept entries
 // stay in the parent's order, so the rows are sorted, and they are those of a list built
 // at r_c whenever the parent holds every such pair.  Same outputs and overflow rule as
-// k_rows.
-__global__ void __launch_bounds__(kNbWaves * 64)
-k_sub_rows(Geo g, const int32_t* __restrict__ p_offs, const int32_t* __restrict__ p_nbr,
-           int32_t align, int32_t* __restrict__ ell, int32_t* __restrict__ len,
-           int32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * kNbWaves + w;
-  if (i >= g.n) return;
+// k_rows.  Called by a whole wave.
+__device__ __forceinline__ void filter_row(const Geo& g, int i, const int32_t* src, int r_len,
+                                           int32_t align, int32_t* ell, int32_t* len,
+                                           int32_t* cnt, uint32_t* flags) {
+  const int lane = threadIdx.x & 63;
   const double xi = g.pos[i], yi = g.pos[g.n + i], zi = g.pos[2 * g.n + i];
-  const int r0 = p_offs[i], r1 = p_offs[i + 1];
   int32_t* out = ell + (size_t)i * kRowCap;
   int run = 0;
-  for (int base = r0; base < r1; base += 64) {   // wave-uniform trip count
+  for (int base = 0; base < r_len; base += 64) {   // wave-uniform trip count
     const int q = base + lane;
-    const int j = q < r1 ? p_nbr[q] : -1;
+    const int j = q < r_len ? src[q] : -1;
     const bool acc = j >= 0 && within(g, xi, yi, zi, j);
     const uint64_t mask = __ballot(acc);
     const int slot = run + __popcll(mask & ((1ull << lane) - 1ull));
@@ -447,13 +521,78 @@ k_sub_rows(Geo g, const int32_t* __restrict__ p_offs, const int32_t* __restrict_
   }
 }
 
+// The filtered rows from a CSR parent list.
+__global__ void __launch_bounds__(kNbWaves * 64)
+k_sub_rows(Geo g, const int32_t* __restrict__ p_offs, const int32_t* __restrict__ p_nbr,
+           int32_t align, int32_t* __restrict__ ell, int32_t* __restrict__ len,
+           int32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
+  const int i = blockIdx.x * kNbWaves + (threadIdx.x >> 6);
+  if (i >= g.n) return;
+  const int r0 = p_offs[i];
+  filter_row(g, i, p_nbr + r0, p_offs[i + 1] - r0, align, ell, len, cnt, flags);
+}
+
+// One evaluation's rows from the skin list.  When gate[0] is set (the displacement test
+// or a forced rebuild asked for it), each wave first rebuilds its receiver's skin row at
+// cutoff + skin (g_out: search, sort, x_build) into sk_ell/sk_len, keeping the sorted row
+// in LDS; a skin row longer than kRowCap raises the overflow flag of both lists.  Then the
+// row, from LDS or from the kept skin row, is filtered to the cutoff at the current
+// positions (g_in) into this list's staging table, and pos_copy receives the positions.
+// gate[1] counts the rebuilds.
+template <bool kCells>
+__global__ void __launch_bounds__(kNbWaves * 64)
+k_rows_filter(Geo g_out, CellCtx cc, int32_t* __restrict__ sk_ell, int32_t* __restrict__ sk_len,
+              uint32_t* __restrict__ sk_flags, double* __restrict__ x_build,
+              uint32_t* __restrict__ gate, Geo g_in, int32_t align, int32_t* __restrict__ ell,
+              int32_t* __restrict__ len, int32_t* __restrict__ cnt,
+              uint32_t* __restrict__ flags, double* __restrict__ pos_copy) {
+  __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
+  __shared__ int32_t s_row[kNbWaves][kRowCap];
+  __shared__ int32_t s_sorted[kNbWaves][kRowCap];
+  const bool rebuild = gate[0] != 0u;
+  if (rebuild && blockIdx.x == 0 && threadIdx.x == 0) gate[1] += 1u;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNbWaves + w;
+  if (i >= g_in.n) return;
+  const int32_t* src;
+  int r_len;
+  if (rebuild) {
+    int run = search_row<kCells>(g_out, cc, nullptr, 1, i, s_pref[w], s_first[w], s_row[w]);
+    if (run > kRowCap) {
+      if (lane == 0) {
+        atomicOr(sk_flags, DMTS_FLAG_NBR_OVERFLOW);
+        atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
+      }
+      run = kRowCap;
+    }
+    sort_row(s_row[w], run, s_sorted[w], sk_ell + (size_t)i * kRowCap);
+    if (lane == 0) sk_len[i] = run;
+    if (lane < 3) x_build[(size_t)lane * g_in.n + i] = g_in.pos[(size_t)lane * g_in.n + i];
+    wave_sync();
+    src = s_sorted[w];
+    r_len = run;
+  } else {
+    src = sk_ell + (size_t)i * kRowCap;
+    r_len = sk_len[i];
+  }
+  filter_row(g_in, i, src, r_len, align, ell, len, cnt, flags);
+  if (pos_copy && lane < 3) pos_copy[(size_t)lane * g_in.n + i] = g_in.pos[(size_t)lane * g_in.n + i];
+}
+
 // CSR rows (padded with -1) from the staging table, the reverse index
 // rev[p] = offs[j] + (position of i in the sorted row of j), and the pair geometry at the
 // build positions: geo[p] = (d_ij as float, |d_ij|), zero for padding.
 __global__ void __launch_bounds__(kNbWaves * 64)
 k_compact(Geo gm, const int32_t* __restrict__ ell, const int32_t* __restrict__ len,
           const int32_t* __restrict__ offs, int32_t* __restrict__ nbr,
-          int32_t* __restrict__ rev, float4* __restrict__ geo) {
+          int32_t* __restrict__ rev, float4* __restrict__ geo, uint32_t* __restrict__ gate,
+          uint32_t* __restrict__ sk_flags) {
+  // skin list (gate given): the rows are current unless one overflowed, in which case the
+  // next evaluation rebuilds them (the overflow was raised on this list already)
+  if (gate && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (sk_flags[0] & DMTS_FLAG_NBR_OVERFLOW) sk_flags[0] = 0u;
+    else gate[0] = 0u;
+  }
   const int32_t n = gm.n;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNbWaves + w;
@@ -506,6 +645,64 @@ dmts_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   return DMTS_OK;
 }
 
+namespace {
+
+// Cell binning of a build at `cutoff` into nl's cell arrays; cc and cells describe the
+// result (cells false: fewer than three cells per edge, rows scan all atoms).  With `gate`
+// (the skin list), the displacement test against x_build runs first and every binning
+// launch is conditional on its outcome.
+dmts_status bin_cells(NList* nl, const double* pos, int32_t n, double box, double cutoff,
+                      hipStream_t s, uint32_t* gate, const double* x_build, double half2,
+                      CellCtx& cc, bool& cells) {
+  cc = CellCtx{nullptr, nullptr, nullptr, 0};
+  int nc = box > 0.0 ? static_cast<int>(floor(box / cutoff)) : 0;
+  cells = nc >= 3;
+  if (!cells) {
+    if (gate) {
+      k_skin_check<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, x_build, half2, gate);
+      DMTS_CHECK_LAUNCH();
+    }
+    return DMTS_OK;
+  }
+  nc = nc > kMaxCellsPerDim ? kMaxCellsPerDim : nc;
+  const int n_cells = nc * nc * nc;
+  if (n_cells > nl->n_cells_cap) {
+    DMTS_REQUIRE(nl->cell_buf.reserve(sizeof(int32_t) * (3 * (size_t)n_cells + 2), s) == DMTS_OK,
+                 DMTS_E_OOM, "build_neighbors: cell buffer allocation failed");
+    // counters start at zero; every scan clears them again after reading
+    dmts_status st = fill_u32(nl->cell_buf.as<uint32_t>(), 0u, n_cells, s);
+    if (st != DMTS_OK) return st;
+    nl->n_cells_cap = n_cells;
+  }
+  int32_t* cell_count = nl->cell_buf.as<int32_t>();
+  int32_t* cell_start = cell_count + nl->n_cells_cap;
+  int32_t* cursor = cell_start + nl->n_cells_cap + 1;
+  const double inv_cell = nc / box;
+  if (n_cells <= kBinCells && n <= kBinAtoms) {
+    k_bin_one<<<1, kBinThreads, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of, cell_start,
+                                        nl->cell_atoms, x_build, half2, gate);
+    DMTS_CHECK_LAUNCH();
+  } else {
+    if (gate) {
+      k_skin_check<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, x_build, half2, gate);
+      DMTS_CHECK_LAUNCH();
+    }
+    k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
+                                                   cell_count, gate);
+    DMTS_CHECK_LAUNCH();
+    scan(cell_count, cell_start, cursor, n_cells, INT64_MAX, nullptr, true, nl->scan_part, s,
+         gate);
+    DMTS_CHECK_LAUNCH();
+    k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms,
+                                                    gate);
+    DMTS_CHECK_LAUNCH();
+  }
+  cc = CellCtx{cell_start, nl->cell_atoms, nl->cell_of, nc};
+  return DMTS_OK;
+}
+
+}  // namespace
+
 dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
                             const int32_t* sys_offsets, int32_t n_sys, double cutoff,
                             hipStream_t s, double* pos_copy) {
@@ -527,40 +724,11 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
   if (n == 0) {
     return fill_u32(reinterpret_cast<uint32_t*>(nl->offs), 0u, 1, s);
   }
+  CellCtx cc;
+  bool cells;
+  dmts_status r = bin_cells(nl, pos, n, box, cutoff, s, nullptr, nullptr, 0.0, cc, cells);
+  if (r != DMTS_OK) return r;
   Geo g{pos, n, box, box > 0.0 ? 1.0 / box : 0.0, cutoff * cutoff};
-  CellCtx cc{nullptr, nullptr, nullptr, 0};
-  int nc = box > 0.0 ? static_cast<int>(floor(box / cutoff)) : 0;
-  const bool cells = nc >= 3;
-  if (cells) {
-    nc = nc > kMaxCellsPerDim ? kMaxCellsPerDim : nc;
-    const int n_cells = nc * nc * nc;
-    if (n_cells > nl->n_cells_cap) {
-      DMTS_REQUIRE(nl->cell_buf.reserve(sizeof(int32_t) * (3 * (size_t)n_cells + 2), s) == DMTS_OK,
-                   DMTS_E_OOM, "build_neighbors: cell buffer allocation failed");
-      // counters start at zero; every scan clears them again after reading
-      dmts_status st = fill_u32(nl->cell_buf.as<uint32_t>(), 0u, n_cells, s);
-      if (st != DMTS_OK) return st;
-      nl->n_cells_cap = n_cells;
-    }
-    int32_t* cell_count = nl->cell_buf.as<int32_t>();
-    int32_t* cell_start = cell_count + nl->n_cells_cap;
-    int32_t* cursor = cell_start + nl->n_cells_cap + 1;
-    const double inv_cell = nc / box;
-    if (n_cells <= kBinCells && n <= kBinAtoms) {
-      k_bin_one<<<1, kBinThreads, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of, cell_start,
-                                          nl->cell_atoms);
-      DMTS_CHECK_LAUNCH();
-    } else {
-      k_cell_assign<<<ceil_div(n, 256), 256, 0, s>>>(pos, n, box, inv_cell, nc, nl->cell_of,
-                                                     cell_count);
-      DMTS_CHECK_LAUNCH();
-      scan(cell_count, cell_start, cursor, n_cells, INT64_MAX, nullptr, true, nl->scan_part, s);
-      DMTS_CHECK_LAUNCH();
-      k_cell_scatter<<<ceil_div(n, 256), 256, 0, s>>>(nl->cell_of, n, cursor, nl->cell_atoms);
-      DMTS_CHECK_LAUNCH();
-    }
-    cc = CellCtx{cell_start, nl->cell_atoms, nl->cell_of, nc};
-  }
   const int blocks = ceil_div(n, kNbWaves);
   if (cells)
     k_rows<true><<<blocks, kNbWaves * 64, 0, s>>>(g, cc, sys_offsets, n_sys, nl->row_align,
@@ -574,7 +742,59 @@ dmts_status build_neighbors(NList* nl, const double* pos, int32_t n, double box,
   scan(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags, false, nl->scan_part, s);
   DMTS_CHECK_LAUNCH();
   k_compact<<<blocks, kNbWaves * 64, 0, s>>>(g, nl->ell, nl->len, nl->offs, nl->nbr, nl->rev,
-                                             nl->geo);
+                                             nl->geo, nullptr, nullptr);
+  DMTS_CHECK_LAUNCH();
+  return DMTS_OK;
+}
+
+dmts_status refresh_neighbors(NList* nl, SkinList* sk, const double* pos, int32_t n, double box,
+                              double cutoff, hipStream_t s, double* pos_copy) {
+  DMTS_REQUIRE(nl && sk && pos, DMTS_E_ARG, "refresh_neighbors: null argument");
+  const double outer = cutoff + sk->skin;
+  if (!(sk->skin > 0.0) || !(box > 0.0) || !(outer < 0.5 * box) || n < 1 || !sk->rows ||
+      n > sk->rows->max_atoms)
+    return build_neighbors(nl, pos, n, box, nullptr, 1, cutoff, s, pos_copy);
+  DMTS_REQUIRE(n <= nl->max_atoms, DMTS_E_ARG,
+               "refresh_neighbors: n_atoms %d above the list's %d", n, nl->max_atoms);
+  nl->n_atoms = n;
+  nl->box = box;
+  nl->cutoff = cutoff;
+  ProfScope ps(DMTS_K_NEIGHBORS, s);
+  NList* rows = sk->rows;
+  if (sk->cutoff != cutoff || sk->box != box || sk->n != n) {
+    // rows built for other parameters (or none yet): rebuild unconditionally
+    dmts_status r = fill_u32(sk->gate, 1u, 1, s);
+    if (r != DMTS_OK) return r;
+    sk->cutoff = cutoff;
+    sk->box = box;
+    sk->n = n;
+    rows->n_atoms = n;
+    rows->box = box;
+    rows->cutoff = outer;
+  }
+  // a hair below skin/2, so that rounding in the distance tests cannot lose a pair
+  const double half = 0.5 * sk->skin - 1e-9;
+  CellCtx cc;
+  bool cells;
+  dmts_status r = bin_cells(rows, pos, n, box, outer, s, sk->gate, sk->x_build, half * half, cc,
+                            cells);
+  if (r != DMTS_OK) return r;
+  const Geo g_out{pos, n, box, 1.0 / box, outer * outer};
+  const Geo g_in{pos, n, box, 1.0 / box, cutoff * cutoff};
+  const int blocks = ceil_div(n, kNbWaves);
+  if (cells)
+    k_rows_filter<true><<<blocks, kNbWaves * 64, 0, s>>>(
+        g_out, cc, rows->ell, rows->len, rows->flags, sk->x_build, sk->gate, g_in,
+        nl->row_align, nl->ell, nl->len, nl->cnt, nl->flags, pos_copy);
+  else
+    k_rows_filter<false><<<blocks, kNbWaves * 64, 0, s>>>(
+        g_out, cc, rows->ell, rows->len, rows->flags, sk->x_build, sk->gate, g_in,
+        nl->row_align, nl->ell, nl->len, nl->cnt, nl->flags, pos_copy);
+  DMTS_CHECK_LAUNCH();
+  scan(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags, false, nl->scan_part, s);
+  DMTS_CHECK_LAUNCH();
+  k_compact<<<blocks, kNbWaves * 64, 0, s>>>(g_in, nl->ell, nl->len, nl->offs, nl->nbr, nl->rev,
+                                             nl->geo, sk->gate, rows->flags);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
@@ -605,7 +825,7 @@ dmts_status filter_neighbors(NList* child, const NList* parent, const double* po
        child->scan_part, s);
   DMTS_CHECK_LAUNCH();
   k_compact<<<blocks, kNbWaves * 64, 0, s>>>(g, child->ell, child->len, child->offs, child->nbr,
-                                             child->rev, child->geo);
+                                             child->rev, child->geo, nullptr, nullptr);
   DMTS_CHECK_LAUNCH();
   return DMTS_OK;
 }
