@@ -104,3 +104,33 @@ def test_skin_argument_checks(models):
             st.set_skin(bad)
     st.set_skin(0.0)
     st.set_skin(2.0)
+
+
+def test_skin_with_monitor_and_fallbacks_equals_fresh_builds(models):
+    """The skin list under the other paths that roll a call back: a force-difference
+    threshold low enough that steps breach (rolled back and redone as single-time-step
+    steps), and one fast atom that outruns the shared list's margin (the call is redone
+    with exact lists).  Both redo paths see the same lists with the skin as without."""
+    say("skin with monitor and fallbacks, water4500")
+    sy = system("water4500")
+    sp = torch.as_tensor(sy.species, dtype=torch.int32, device="cuda")
+    for case, thr, fast in (("monitor", 0.02, False), ("fallback", 0.0, True)):
+        v0 = synth.maxwell_boltzmann(sy.species, 300.0, 200)
+        if fast:
+            v0[10] = [0.35, 0.0, 0.0]   # ~1.4 A per 4 fs outer step: past the 0.85 A margin
+        out = {}
+        for skin in (0.0, 1.5):
+            st = api.DMTS(sy.n_atoms, sy.box, sp, synth.MASSES, 4.0, 4, 48, 128)
+            st.set_skin(skin)
+            st.set_fdiff_threshold(thr)
+            x, v = api.to_soa(sy.pos), api.to_soa(v0)
+            st.step(x, v, models["small"], models["large"], 3)
+            torch.cuda.synchronize()
+            out[skin] = (x, v, st.fdiff[0], st.fallbacks, st.list_builds)
+        x0, v0_, redo0, fb0, _ = out[0.0]
+        x1, v1, redo1, fb1, b1 = out[1.5]
+        say(f"  {case}: single-time-step redos {redo1}, exact-list fallbacks {fb1}, "
+            f"row rebuilds {b1}")
+        assert redo0 == redo1 and fb0 == fb1
+        assert (redo1 >= 1) if case == "monitor" else (fb1 >= 1)
+        assert torch.equal(x0, x1) and torch.equal(v0_, v1)
