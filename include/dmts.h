@@ -357,6 +357,10 @@ dmts_status dmts_state_list_builds(dmts_state* st, int64_t* n_builds);
  * of an enabled class is bracketed by two hipEventRecord calls on its stream (a few
  * microseconds of overhead per launch); disabled classes cost nothing.  dmts_prof_read synchronizes on the recorded events and returns the summed
  * duration in milliseconds and the number of launches of one class since the last reset.
+ * dmts_prof_sample(every): time only the first of every `every` launches of each enabled
+ * class (counted from the last reset; 1, the default, times all), so that a harness can
+ * time a kernel inside a throughput measurement while adding the events' cost to a
+ * fraction of its launches.  DMTS_E_ARG for 0.
  */
 enum {
   DMTS_K_SMALL_FORWARD = 0,
@@ -372,6 +376,7 @@ enum {
   DMTS_K_COUNT = 10
 };
 dmts_status dmts_prof_enable(uint32_t class_mask);
+dmts_status dmts_prof_sample(uint32_t every);
 dmts_status dmts_prof_reset(void);
 dmts_status dmts_prof_read(int32_t kernel_class, double* total_ms, int64_t* launches);
 

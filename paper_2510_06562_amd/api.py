@@ -99,6 +99,7 @@ _SIGS = {
     "dmts_state_list_builds": ([_P, ctypes.POINTER(_I64)], _I32),
     "dmts_prof_enable": ([ctypes.c_uint32], _I32),
     "dmts_prof_reset": ([], _I32),
+    "dmts_prof_sample": ([ctypes.c_uint32], _I32),
     "dmts_prof_read": ([_I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I32),
 }
 
@@ -522,6 +523,11 @@ def prof_enable(classes=None):
 
 def prof_reset():
     _check(lib().dmts_prof_reset())
+
+
+def prof_sample(every: int = 1):
+    """Time one launch in `every` of each enabled class (1 = all)."""
+    _check(lib().dmts_prof_sample(int(every)))
 
 
 def prof_read() -> dict:

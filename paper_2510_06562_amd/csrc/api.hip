@@ -50,6 +50,8 @@ void DevBuf::release() {
 // ------------------------------------------------------------------ kernel timing
 namespace {
 uint32_t g_prof_mask = 0;
+uint32_t g_prof_every = 1;                 // time one launch in this many of a class
+uint64_t g_prof_seen[DMTS_K_COUNT] = {};   // launches of each enabled class since reset
 struct ProfRec {
   hipEvent_t a, b;
 };
@@ -71,6 +73,7 @@ hipEvent_t get_event() {
 ProfScope::ProfScope(int kernel_class, hipStream_t stream, bool packet_launch)
     : kid(kernel_class), s(stream) {
   if (!((g_prof_mask >> kid) & 1u)) return;
+  if (g_prof_seen[kid]++ % g_prof_every != 0) return;
   a = get_event();
   if (a && !packet_launch) {
     (void)hipEventRecord(a, s);
@@ -511,7 +514,14 @@ extern "C" dmts_status dmts_prof_enable(uint32_t class_mask) {
   return DMTS_OK;
 }
 
+extern "C" dmts_status dmts_prof_sample(uint32_t every) {
+  DMTS_REQUIRE(every >= 1, DMTS_E_ARG, "dmts_prof_sample: every must be >= 1");
+  dmts::g_prof_every = every;
+  return DMTS_OK;
+}
+
 extern "C" dmts_status dmts_prof_reset(void) {
+  for (auto& c : dmts::g_prof_seen) c = 0;
   for (auto& v : dmts::g_prof) {
     for (auto& r : v) {
       (void)hipEventSynchronize(r.b);
