@@ -43,6 +43,7 @@ constexpr int Z_MAX = 8;
 constexpr int kCap = kSmallPairCap;   // most pairs one receiver may have inside the cutoff
 constexpr int kTile = 16;
 constexpr int kLdW = 20;   // LDS stride of W_r rows [c][k]
+constexpr int kLdW1 = 65;  // LDS stride of W1 rows [c][e]
 
 struct SmallParams {
   const float* WbT;  // [K][F]  (bfloat16-valued in the BF16 form)
@@ -71,13 +72,13 @@ template <bool kReadout>
 struct SmallLds {
   float W[F_S * kLdW];
   float Td[Z_MAX][F_S], Ts[Z_MAX][F_S];
-  // W1 [c][e] at c * F + (e ^ c) (w1_at): a lane per row c (z = W1 h) or per column
-  // (W1^T v) hits 64 distinct banks either way, without padding (the LDS of five
-  // work-groups fits a CU)
-  float W1[kReadout ? F_S * F_S : 1];
+  // W1 [c][e] at c * (F + 1) + e (w1_at): a lane per row c (z = W1 h) or per column
+  // (W1^T v) hits 64 distinct banks either way, and in both loops the address is the
+  // lane's base plus a constant, so the reads need no address arithmetic
+  float W1[kReadout ? F_S * kLdW1 : 1];
 };
 
-__device__ __forceinline__ int w1_at(int c, int e) { return c * F_S + (e ^ c); }
+__device__ __forceinline__ int w1_at(int c, int e) { return c * kLdW1 + e; }
 
 // Staging of the LDS weights in two halves: fetch() issues the thread's global loads into
 // registers, store() writes them to LDS, so that independent work (the reverse kernel's
@@ -342,7 +343,7 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
     // 3. readout, channel c = lane: z = W1 h, E_i = s_E w2 . SiLU(z), g = W1^T (s_E w2 SiLU'(z))
     const int c = lane;
     float z = 0.f;
-#pragma unroll 8
+#pragma unroll 16
     for (int e = 0; e < F_S; ++e) z = fmaf(L.W1[w1_at(c, e)], sVec[w][e], z);
     float y, dy;
     silu_and_grad(z, y, dy);
@@ -352,7 +353,7 @@ k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __r
     sVec[w][c] = BF16 ? bf16r(P.escale * w2 * dy) : P.escale * w2 * dy;
     wave_sync();
     float gi = 0.f;
-#pragma unroll 8
+#pragma unroll 16
     for (int k = 0; k < F_S; ++k) gi = fmaf(L.W1[w1_at(k, c)], sVec[w][k], gi);
     if (lane == 0) atom_e[i] = e_i;
     // 4. s_ij per pair into the pair's slot
