@@ -119,10 +119,9 @@ struct Stager {
 
 // 16 x 16 tile over K = 16 radial functions.  bk(e) / wk(e) give the lane's radial and
 // weight operands for k = 4 e + g (FP32, e = step) or k = 4 g + e (BF16, e = element);
-// b_is_a selects which of the two is the A operand.
+// b_is_a selects which of the two is the A operand; the products accumulate onto acc.
 template <bool BF16, class BK, class WK>
-__device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a) {
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+__device__ __forceinline__ f32x4 radial_mfma(BK&& bk, WK&& wk, bool b_is_a, f32x4 acc) {
   if (BF16) {
     s16x4 x, y;
 #pragma unroll
@@ -186,14 +185,16 @@ __device__ __forceinline__ void small_tile(const SmallLds<true>& L, const float4
       const int kk = BF16 ? 4 * g + e : 4 * e + g;
       return L.W[c * kLdW + kk];
     };
-    const f32x4 acc = radial_mfma<BF16>([&](int e) { return bv[e]; }, wk, true);
-    f32x4 accd = {0.f, 0.f, 0.f, 0.f};
-    if (DM) accd = radial_mfma<BF16>([&](int e) { return dbv[e]; }, wk, true);
+    // the receiver's table term starts the accumulator (the same for the block's rows)
     const float td = L.Td[zi_s][c];
+    const f32x4 acc = radial_mfma<BF16>([&](int e) { return bv[e]; }, wk, true,
+                                        f32x4{td, td, td, td});
+    f32x4 accd = {0.f, 0.f, 0.f, 0.f};
+    if (DM) accd = radial_mfma<BF16>([&](int e) { return dbv[e]; }, wk, true, accd);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float sv, dsv;
-      silu_and_grad(acc[r] + td + L.Ts[zz[r]][c], sv, dsv);
+      silu_and_grad(acc[r] + L.Ts[zz[r]][c], sv, dsv);
       m[b][r] = fc[r] * sv;
       if (DM) dm[b][r] = fmaf(dfc[r], sv, fc[r] * dsv * accd[r]);
     }
