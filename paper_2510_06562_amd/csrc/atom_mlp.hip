@@ -5,9 +5,12 @@
 // 16 atoms (each weight load feeds both tiles), keeps the activations of its atoms in LDS
 // between layers and streams the weights (at most 384 x 384, L2-resident) from global
 // memory.  The weight stream, not the products, bounds a 16-atom work-group in the FP32
-// form, so both forms take 32 atoms.  Contractions use
-// v_mfma_f32_16x16x4_f32; the eight waves of the work-group split the output columns in
-// blocks of 16.  A row's result does not depend on its tile or work-group.
+// form, so both forms take 32 atoms.  Contractions use v_mfma_f32_16x16x4_f32; the
+// sixteen waves of the work-group take eight 16-column blocks at a time, each block in two
+// halves of K (waves w and w + 8): the second half's accumulators go through LDS and the
+// first half adds them (a fixed order) and runs the layer's epilogue.  Four waves per SIMD
+// hide the latency of the weight stream that two could not, and each weight is still
+// loaded once per work-group.  A row's result does not depend on its tile or work-group.
 //
 //   chain 1 (after interaction 1):  z1 = U1 q1, h1 = SiLU(z1), [A|B] = [W_s|W_r] h1
 //   chain 2 (after interaction 2):  z2 = U2 q2, h2 = h1 + SiLU(z2), y = W_o h2,
@@ -31,7 +34,8 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 512;   // eight waves: one or more 16-column blocks each
+constexpr int kThreads = 1024;  // sixteen waves: two K halves of eight column blocks
+constexpr int kHalfWaves = kThreads / 128;
 constexpr int kRT = 2;       // 16-atom tiles per work-group
 constexpr int kLd = 388;     // LDS row stride (floats) for activations up to 384 wide
 
@@ -45,7 +49,7 @@ struct AccT {
 // slice of K, step s of group g takes k = 8 g + s (both operands agree), so a lane reads
 // its eight X and eight W values as two 16-byte loads each.
 template <int RT>
-__device__ __forceinline__ AccT<RT> mfma_block(const float* X, int K,
+__device__ __forceinline__ AccT<RT> mfma_block(const float* X, int K, int kb, int ke,
                                                const float* __restrict__ W, int n0, int lane) {
   AccT<RT> acc;
 #pragma unroll
@@ -54,7 +58,7 @@ __device__ __forceinline__ AccT<RT> mfma_block(const float* X, int K,
   const float* xp = X + r * kLd + 8 * g;
   const float* wp = W + (size_t)(n0 + r) * K + 8 * g;
 #pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     const float4 w0 = *reinterpret_cast<const float4*>(wp + k0);
     const float4 w1 = *reinterpret_cast<const float4*>(wp + k0 + 4);
     const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
@@ -79,7 +83,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 //   B operand: lane l holds B[k0 + 8 (l / 16) + e][l % 16]
 // X is rounded to bfloat16 (nearest even) as it is read; accumulation is FP32.
 template <int RT>
-__device__ __forceinline__ AccT<RT> mfma_block_bf16(const float* X, int K,
+__device__ __forceinline__ AccT<RT> mfma_block_bf16(const float* X, int K, int kb, int ke,
                                                     const __bf16* __restrict__ W, int n0,
                                                     int lane) {
   AccT<RT> acc;
@@ -89,7 +93,7 @@ __device__ __forceinline__ AccT<RT> mfma_block_bf16(const float* X, int K,
   const float* xp = X + r * kLd + 8 * g;
   const __bf16* wp = W + (size_t)(n0 + r) * K + 8 * g;
 #pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     const bf16x8 b = *reinterpret_cast<const bf16x8*>(wp + k0);
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -110,19 +114,35 @@ struct LayerW {
   const __bf16* b16;
 };
 
-// Runs one layer: for every 16-column block of N assigned to this wave, calls
-// epi(row, col, value) for the lane's four outputs.
+// Runs one layer: for every 16-column block of N, in rounds of eight blocks, the two
+// waves of the block sum their K halves and the first calls epi(row, col, value) for the
+// lane's four outputs.  `part` (LDS, 8 RT 64 f32x4) holds the second halves of a round.
 template <int RT, class Epi>
-__device__ __forceinline__ void layer(const float* X, int K, LayerW Wt, int N, Epi&& epi) {
+__device__ __forceinline__ void layer(f32x4* part, const float* X, int K, LayerW Wt, int N,
+                                      Epi&& epi) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int nb = wave; nb < N / 16; nb += kThreads / 64) {
-    const AccT<RT> acc = Wt.b16 ? mfma_block_bf16<RT>(X, K, Wt.b16, nb * 16, lane)
-                                : mfma_block<RT>(X, K, Wt.f32, nb * 16, lane);
+  const int kh = wave / kHalfWaves, wl = wave % kHalfWaves;
+  const int kb = kh * (K / 2), ke = kb + K / 2;
+  for (int base = 0; base < N / 16; base += kHalfWaves) {   // uniform over the work-group
+    const int nb = base + wl;
+    AccT<RT> acc;
+    if (nb < N / 16)
+      acc = Wt.b16 ? mfma_block_bf16<RT>(X, K, kb, ke, Wt.b16, nb * 16, lane)
+                   : mfma_block<RT>(X, K, kb, ke, Wt.f32, nb * 16, lane);
+    if (kh == 1 && nb < N / 16)
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t) part[(wl * RT + t) * 64 + lane] = acc.v[t];
+    __syncthreads();
+    if (kh == 0 && nb < N / 16) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        epi(16 * t + 4 * (lane >> 4) + r, nb * 16 + (lane & 15), acc.v[t][r]);
+      for (int t = 0; t < RT; ++t) {
+        const f32x4 o = part[(wl * RT + t) * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          epi(16 * t + 4 * (lane >> 4) + r, nb * 16 + (lane & 15), acc.v[t][r] + o[r]);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -157,6 +177,7 @@ __global__ void __launch_bounds__(kThreads)
 k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict__ z1,
          float* __restrict__ h1, float* __restrict__ P2) {
   constexpr int kRows = 16 * RT;
+  __shared__ f32x4 part[kHalfWaves * RT * 64];   // K-half partial sums of a layer
   __shared__ float X[kRows * kLd];
   __shared__ float H[kRows * kLd];
   const int m0 = blockIdx.x * kRows;
@@ -166,7 +187,7 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
     a.store(X, kLd);
   }
   __syncthreads();
-  layer<RT>(X, 384, LayerW{P.U1, P.h_U1}, 128, [&](int r, int c, float v) {
+  layer<RT>(part, X, 384, LayerW{P.U1, P.h_U1}, 128, [&](int r, int c, float v) {
     const float h = silu_f(v);
     H[r * kLd + c] = h;
     if (m0 + r < M) {
@@ -175,7 +196,7 @@ k_chain1(AtomMlpParams P, int M, const float* __restrict__ q1, float* __restrict
     }
   });
   __syncthreads();
-  layer<RT>(H, 128, LayerW{P.W2h, P.h_W2h}, 256, [&](int r, int c, float v) {
+  layer<RT>(part, H, 128, LayerW{P.W2h, P.h_W2h}, 256, [&](int r, int c, float v) {
     if (m0 + r < M) P2[(size_t)(m0 + r) * 256 + c] = v;
   });
 }
@@ -186,6 +207,7 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
          float escale, float* __restrict__ atom_e, float* __restrict__ dh2_out,
          float* __restrict__ dq2, bool backward) {
   constexpr int kRows = 16 * RT;
+  __shared__ f32x4 part[kHalfWaves * RT * 64];   // K-half partial sums of a layer
   __shared__ float X[kRows * kLd];     // q2, later dz2
   __shared__ float H[kRows * kLd];     // h2, later dy
   __shared__ float Z[kRows * 128];     // z2
@@ -200,14 +222,14 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
     b.store(E, 128);
   }
   __syncthreads();
-  layer<RT>(X, 384, LayerW{P.U2, P.h_U2}, 128, [&](int r, int c, float v) {
+  layer<RT>(part, X, 384, LayerW{P.U2, P.h_U2}, 128, [&](int r, int c, float v) {
     Z[r * 128 + c] = v;
     H[r * kLd + c] = E[r * 128 + c] + silu_f(v);
   });
   __syncthreads();   // E (h1) is overwritten by the next layer
   __syncthreads();
   // y = W_o h2; energy terms and dy (dy overwrites the X buffer)
-  layer<RT>(H, 128, LayerW{P.Wo, P.h_Wo}, 128, [&](int r, int c, float v) {
+  layer<RT>(part, H, 128, LayerW{P.Wo, P.h_Wo}, 128, [&](int r, int c, float v) {
     float s, ds;
     silu_and_grad(v, s, ds);
     const float w = P.wo[c];
@@ -226,12 +248,12 @@ k_chain2(AtomMlpParams P, int M, const float* __restrict__ q2, const float* __re
   }
   if (!backward) return;
   // dh2 = W_o^T dy, dz2 = dh2 SiLU'(z2)   (dz2 goes to H)
-  layer<RT>(X, 128, LayerW{P.WoT, P.h_WoT}, 128, [&](int r, int c, float v) {
+  layer<RT>(part, X, 128, LayerW{P.WoT, P.h_WoT}, 128, [&](int r, int c, float v) {
     if (m0 + r < M) dh2_out[(size_t)(m0 + r) * 128 + c] = v;
     H[r * kLd + c] = v * dsilu_f(Z[r * 128 + c]);
   });
   __syncthreads();
-  layer<RT>(H, 128, LayerW{P.U2T, P.h_U2T}, 384, [&](int r, int c, float v) {
+  layer<RT>(part, H, 128, LayerW{P.U2T, P.h_U2T}, 384, [&](int r, int c, float v) {
     if (m0 + r < M) dq2[(size_t)(m0 + r) * 384 + c] = v;
   });
 }
@@ -241,6 +263,7 @@ __global__ void __launch_bounds__(kThreads)
 k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __restrict__ dh2,
          const float* __restrict__ z1, float* __restrict__ dq1) {
   constexpr int kRows = 16 * RT;
+  __shared__ f32x4 part[kHalfWaves * RT * 64];   // K-half partial sums of a layer
   __shared__ float X[kRows * kLd];
   __shared__ float H[kRows * kLd];
   __shared__ float D2[kRows * 128], Z1[kRows * 128];   // dh2, z1 rows
@@ -256,12 +279,12 @@ k_chain3(AtomMlpParams P, int M, const float* __restrict__ RS, const float* __re
     c.store(Z1, 128);
   }
   __syncthreads();
-  layer<RT>(X, 256, LayerW{P.W2hs, P.h_W2hs}, 128, [&](int r, int c, float v) {
+  layer<RT>(part, X, 256, LayerW{P.W2hs, P.h_W2hs}, 128, [&](int r, int c, float v) {
     const int o = r * 128 + c;
     H[r * kLd + c] = m0 + r < M ? (v + D2[o]) * dsilu_f(Z1[o]) : 0.f;
   });
   __syncthreads();
-  layer<RT>(H, 128, LayerW{P.U1T, P.h_U1T}, 384, [&](int r, int c, float v) {
+  layer<RT>(part, H, 128, LayerW{P.U1T, P.h_U1T}, 384, [&](int r, int c, float v) {
     if (m0 + r < M) dq1[(size_t)(m0 + r) * 384 + c] = v;
   });
 }
