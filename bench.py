@@ -268,11 +268,17 @@ def cpu_oracle(sy, ws, wl, n_inner, dt_inner, spec_s, spec_l, synth):
 
 def drift_fit(t_ps, H, n_atoms, span_ps):
     """Least-squares line through H(t): (drift over span_ps per atom, its standard error,
-    the largest |H - H(0)| per atom)."""
+    the largest |H - H(0)| per atom).  The residuals of H are serially correlated (its
+    fluctuations last longer than the sampling interval), so the ordinary least-squares
+    error is widened by the AR(1) factor sqrt((1 + rho) / (1 - rho)), rho the lag-one
+    autocorrelation of the residuals (kept >= 0)."""
     A = np.vstack([t_ps, np.ones_like(t_ps)]).T
     coef = np.linalg.lstsq(A, H, rcond=None)[0]
     resid = H - A @ coef
     se = np.sqrt(resid @ resid / max(len(H) - 2, 1) / np.sum((t_ps - t_ps.mean()) ** 2))
+    rho = float(resid[1:] @ resid[:-1] / max(resid @ resid, 1e-300)) if len(H) > 2 else 0.0
+    rho = min(max(rho, 0.0), 0.99)
+    se *= np.sqrt((1.0 + rho) / (1.0 - rho))
     return (float(coef[0] * span_ps / n_atoms), float(se * span_ps / n_atoms),
             float(np.max(np.abs(H - H[0])) / n_atoms))
 
