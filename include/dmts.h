@@ -340,9 +340,10 @@ dmts_status dmts_state_flags(dmts_state* st, void* stream, uint32_t* host_flags)
  *   builds the list afresh at every reference evaluation.  The skin is also dropped (fresh
  *   builds) for an open box or when cutoff + skin reaches half the box edge.  A change
  *   takes effect at the next reference evaluation (which rebuilds).  Results do not depend
- *   on the skin: the lists, and so every sum, are the same.  Rows at cutoff + skin must fit
- *   the 256-entry row limit; a longer one raises DMTS_FLAG_NBR_OVERFLOW (DMTS_E_CAPACITY
- *   from dmts_step) as a fresh build's would.
+ *   on the skin: the lists, and so every sum, are the same.  Rows at cutoff + skin may hold
+ *   up to 512 entries (twice a list row's 256, so that a skin does not lower the density a
+ *   state can run at); a longer one raises DMTS_FLAG_NBR_OVERFLOW (DMTS_E_CAPACITY from
+ *   dmts_step) as an overlong row of a fresh build does.
  * dmts_state_get_skin: the skin in use (A).
  * dmts_state_list_builds: the number of row rebuilds so far (blocking: synchronizes the
  *   device).

@@ -52,6 +52,7 @@ inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) 
 
 // ------------------------------------------------------------------ neighbor list
 constexpr int kNlistRowCap = 256;   // most neighbors one atom may have
+constexpr int kSkinRowCap = 512;    // most neighbors within cutoff + skin (skin lists)
 constexpr int kSmallPairCap = 64;   // most pairs one atom may have inside the fast cutoff
 struct NList {
   int32_t max_atoms = 0;
@@ -86,7 +87,8 @@ constexpr double kDefaultSkin = 1.5;
 // cutoff + skin, rebuilt only when an atom has moved at least skin/2 since the last rebuild,
 // and filtered to the cutoff at the current positions at every evaluation.
 struct SkinList {
-  NList* rows = nullptr;       // rows at cutoff + skin (ell, len), cells, overflow flag
+  NList* rows = nullptr;       // row lengths (len), cells and overflow flag of the rows
+  int32_t* ell = nullptr;      // [n][kSkinRowCap] sorted rows at cutoff + skin
   double* x_build = nullptr;   // [3][n] positions of the last rebuild
   uint32_t* gate = nullptr;    // [2]: rebuild requested, rebuilds so far
   double skin = 0.0;

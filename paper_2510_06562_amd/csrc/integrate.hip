@@ -443,6 +443,8 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     if (e == hipSuccess) e = hipMalloc(&st->Fs, sizeof(float) * 3 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->x_ref, sizeof(double) * 3 * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->skin.x_build, sizeof(double) * 3 * (size_t)n_atoms);
+    if (e == hipSuccess)
+      e = hipMalloc(&st->skin.ell, sizeof(int32_t) * dmts::kSkinRowCap * (size_t)n_atoms);
     if (e == hipSuccess) e = hipMalloc(&st->skin.gate, sizeof(uint32_t) * 2);
     if (e == hipSuccess) e = hipMemset(st->skin.gate, 0, sizeof(uint32_t) * 2);
     if (e == hipSuccess) e = hipMalloc(&st->bak, sizeof(double) * 9 * (size_t)n_atoms);
@@ -485,6 +487,7 @@ extern "C" void dmts_state_destroy(dmts_state* h) {
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->nl_large2));
   nnp_nlist_destroy(reinterpret_cast<nnp_nlist*>(st->skin.rows));
   (void)hipFree(st->skin.x_build);
+  (void)hipFree(st->skin.ell);
   (void)hipFree(st->skin.gate);
   if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
   if (st->ev_join) (void)hipEventDestroy(st->ev_join);

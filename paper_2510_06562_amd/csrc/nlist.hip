@@ -427,10 +427,11 @@ __device__ __forceinline__ void molecule_range(const int32_t* sys_offsets, int32
 
 constexpr int kNbWaves = 4;
 constexpr int kRowCap = kNlistRowCap;
+constexpr int kSkinCap = kSkinRowCap;
 
 // Search of receiver i's row: the accepted senders, in candidate order, into row[] (LDS,
-// at most kRowCap of them).  Returns the full count, which may exceed kRowCap.  Whole wave.
-template <bool kCells>
+// at most CAP of them).  Returns the full count, which may exceed CAP.  Whole wave.
+template <bool kCells, int CAP>
 __device__ __forceinline__ int search_row(const Geo& g, const CellCtx& cc,
                                           const int32_t* sys_offsets, int32_t n_sys, int i,
                                           int32_t* s_pref, int32_t* s_first, int32_t* row) {
@@ -443,7 +444,7 @@ __device__ __forceinline__ int search_row(const Geo& g, const CellCtx& cc,
     bool acc = ok && within(g, xi, yi, zi, j);
     uint64_t mask = __ballot(acc);
     int p = run + __popcll(mask & ((1ull << lane) - 1ull));
-    if (acc && p < kRowCap) row[p] = j;
+    if (acc && p < CAP) row[p] = j;
     run += __popcll(mask);
   });
   wave_sync();
@@ -478,7 +479,8 @@ k_rows(Geo g, CellCtx cc, const int32_t* __restrict__ sys_offsets, int32_t n_sys
   const int i = blockIdx.x * kNbWaves + w;
   if (i >= g.n) return;
   if (pos_copy && lane < 3) pos_copy[(size_t)lane * g.n + i] = g.pos[(size_t)lane * g.n + i];
-  int run = search_row<kCells>(g, cc, sys_offsets, n_sys, i, s_pref[w], s_first[w], s_row[w]);
+  int run = search_row<kCells, kRowCap>(g, cc, sys_offsets, n_sys, i, s_pref[w], s_first[w],
+                                        s_row[w]);
   if (run > kRowCap) {
     if (lane == 0) atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
     run = kRowCap;
@@ -535,7 +537,7 @@ k_sub_rows(Geo g, const int32_t* __restrict__ p_offs, const int32_t* __restrict_
 // One evaluation's rows from the skin list.  When gate[0] is set (the displacement test
 // or a forced rebuild asked for it), each wave first rebuilds its receiver's skin row at
 // cutoff + skin (g_out: search, sort, x_build) into sk_ell/sk_len, keeping the sorted row
-// in LDS; a skin row longer than kRowCap raises the overflow flag of both lists.  Then the
+// in LDS; a skin row longer than kSkinCap raises the overflow flag of both lists.  Then the
 // row, from LDS or from the kept skin row, is filtered to the cutoff at the current
 // positions (g_in) into this list's staging table, and pos_copy receives the positions.
 // gate[1] counts the rebuilds.
@@ -547,8 +549,8 @@ k_rows_filter(Geo g_out, CellCtx cc, int32_t* __restrict__ sk_ell, int32_t* __re
               int32_t* __restrict__ len, int32_t* __restrict__ cnt,
               uint32_t* __restrict__ flags, double* __restrict__ pos_copy) {
   __shared__ int32_t s_pref[kNbWaves][32], s_first[kNbWaves][32];
-  __shared__ int32_t s_row[kNbWaves][kRowCap];
-  __shared__ int32_t s_sorted[kNbWaves][kRowCap];
+  __shared__ int32_t s_row[kNbWaves][kSkinCap];
+  __shared__ int32_t s_sorted[kNbWaves][kSkinCap];
   const bool rebuild = gate[0] != 0u;
   if (rebuild && blockIdx.x == 0 && threadIdx.x == 0) gate[1] += 1u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -557,22 +559,23 @@ k_rows_filter(Geo g_out, CellCtx cc, int32_t* __restrict__ sk_ell, int32_t* __re
   const int32_t* src;
   int r_len;
   if (rebuild) {
-    int run = search_row<kCells>(g_out, cc, nullptr, 1, i, s_pref[w], s_first[w], s_row[w]);
-    if (run > kRowCap) {
+    int run = search_row<kCells, kSkinCap>(g_out, cc, nullptr, 1, i, s_pref[w], s_first[w],
+                                           s_row[w]);
+    if (run > kSkinCap) {
       if (lane == 0) {
         atomicOr(sk_flags, DMTS_FLAG_NBR_OVERFLOW);
         atomicOr(flags, DMTS_FLAG_NBR_OVERFLOW);
       }
-      run = kRowCap;
+      run = kSkinCap;
     }
-    sort_row(s_row[w], run, s_sorted[w], sk_ell + (size_t)i * kRowCap);
+    sort_row(s_row[w], run, s_sorted[w], sk_ell + (size_t)i * kSkinCap);
     if (lane == 0) sk_len[i] = run;
     if (lane < 3) x_build[(size_t)lane * g_in.n + i] = g_in.pos[(size_t)lane * g_in.n + i];
     wave_sync();
     src = s_sorted[w];
     r_len = run;
   } else {
-    src = sk_ell + (size_t)i * kRowCap;
+    src = sk_ell + (size_t)i * kSkinCap;
     r_len = sk_len[i];
   }
   filter_row(g_in, i, src, r_len, align, ell, len, cnt, flags);
@@ -752,7 +755,7 @@ dmts_status refresh_neighbors(NList* nl, SkinList* sk, const double* pos, int32_
   DMTS_REQUIRE(nl && sk && pos, DMTS_E_ARG, "refresh_neighbors: null argument");
   const double outer = cutoff + sk->skin;
   if (!(sk->skin > 0.0) || !(box > 0.0) || !(outer < 0.5 * box) || n < 1 || !sk->rows ||
-      n > sk->rows->max_atoms)
+      !sk->ell || n > sk->rows->max_atoms)
     return build_neighbors(nl, pos, n, box, nullptr, 1, cutoff, s, pos_copy);
   DMTS_REQUIRE(n <= nl->max_atoms, DMTS_E_ARG,
                "refresh_neighbors: n_atoms %d above the list's %d", n, nl->max_atoms);
@@ -784,11 +787,11 @@ dmts_status refresh_neighbors(NList* nl, SkinList* sk, const double* pos, int32_
   const int blocks = ceil_div(n, kNbWaves);
   if (cells)
     k_rows_filter<true><<<blocks, kNbWaves * 64, 0, s>>>(
-        g_out, cc, rows->ell, rows->len, rows->flags, sk->x_build, sk->gate, g_in,
+        g_out, cc, sk->ell, rows->len, rows->flags, sk->x_build, sk->gate, g_in,
         nl->row_align, nl->ell, nl->len, nl->cnt, nl->flags, pos_copy);
   else
     k_rows_filter<false><<<blocks, kNbWaves * 64, 0, s>>>(
-        g_out, cc, rows->ell, rows->len, rows->flags, sk->x_build, sk->gate, g_in,
+        g_out, cc, sk->ell, rows->len, rows->flags, sk->x_build, sk->gate, g_in,
         nl->row_align, nl->ell, nl->len, nl->cnt, nl->flags, pos_copy);
   DMTS_CHECK_LAUNCH();
   scan(nl->cnt, nl->offs, nullptr, n, nl->max_pairs, nl->flags, false, nl->scan_part, s);

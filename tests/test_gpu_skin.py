@@ -5,6 +5,7 @@ run that builds afresh at every evaluation (skin 0) bit for bit, while rebuildin
 only now and then.  The oracle comparisons of the other dynamics tests run with the default
 skin as well."""
 
+import numpy as np
 import pytest
 import torch
 
@@ -134,3 +135,28 @@ def test_skin_with_monitor_and_fallbacks_equals_fresh_builds(models):
         assert redo0 == redo1 and fb0 == fb1
         assert (redo1 >= 1) if case == "monitor" else (fb1 >= 1)
         assert torch.equal(x0, x1) and torch.equal(v0_, v1)
+
+
+def test_dense_box_skin_rows_past_the_list_row_limit(models):
+    """A jittered lattice at 0.25 atoms/A^3 (2.5 times water, 6,859 atoms): rows hold ~150
+    entries at 5.2 A but ~320 at 6.7 A, past a list row's 256 entries.  The skin rows hold
+    up to 512, so the run neither overflows nor differs from the fresh-build one."""
+    say("skin rows past 256 entries, dense lattice")
+    n_side, box = 19, 30.0
+    rng = np.random.default_rng(41)
+    g = (np.arange(n_side) + 0.5) * (box / n_side)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    pos = pos + rng.normal(0.0, 0.1, pos.shape)
+    species = rng.choice(5, size=len(pos)).astype(np.int32)
+    sp = torch.as_tensor(species, dtype=torch.int32, device="cuda")
+    v0 = synth.maxwell_boltzmann(species, 300.0, 7)
+    out = {}
+    for skin in (0.0, 1.5):
+        st = api.DMTS(len(pos), box, sp, synth.MASSES, 4.0, 4, 64, 200)
+        st.set_skin(skin)
+        x, v = api.to_soa(pos), api.to_soa(v0)
+        st.step(x, v, models["small"], models["large"], 2)
+        torch.cuda.synchronize()
+        out[skin] = (x, v, st.list_builds)
+    assert out[1.5][2] >= 1
+    assert torch.equal(out[0.0][0], out[1.5][0]) and torch.equal(out[0.0][1], out[1.5][1])
