@@ -193,6 +193,9 @@ def parse():
                     help="skip the 10 ps NVE drift run of the throughput line")
     ap.add_argument("--skin", type=float, default=None,
                     help="skin of the reference lists in A (default: the library's)")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the 100,001-atom BF16 DMTS and 256-molecule BF16 batch lines "
+                         "that the default water4500 run adds (child processes)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shapes instead of tuning them for the workload")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
@@ -662,7 +665,45 @@ def main():
         "tile_shapes": shapes,
         "kernels": kernels,
     }
+    if (args.workload == "water4500" and not args.no_other_configs and args.fast_model == "one"
+            and not (args.hmr or args.distill or args.gamma > 0.0)):
+        out["other_configs"] = other_configs(args.precision)
     print(json.dumps(out), flush=True)
+
+
+def other_configs(precision):
+    """The two other workloads of the benchmark set, each run by a child process of this
+    script: DMTS 1 fs / 6 fs against 1 fs Verlet on the 100,001-atom solvated chain, and
+    one batched evaluation of 256 molecules against a per-molecule loop, both with BF16
+    MLP operands (the forms those workloads are specified in).  Returns a summary of each
+    child's JSON line (or the error it ended with)."""
+    import subprocess
+
+    def child(extra, keys):
+        cmd = [sys.executable, os.path.abspath(__file__), "--no-other-configs", *extra]
+        try:
+            r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        except subprocess.TimeoutExpired:
+            return {"error": "timed out", "command": " ".join(extra)}
+        lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+        if r.returncode != 0 or not lines:
+            return {"error": f"exit {r.returncode}", "command": " ".join(extra),
+                    "stderr_tail": r.stderr[-400:]}
+        d = json.loads(lines[-1])
+        o = {k: d.get(k) for k in keys}
+        o["command"] = "bench.py " + " ".join(extra)
+        return o
+
+    c4 = child(["--workload", "solvated100k", "--precision", "bf16", "--n-inner", "6",
+                "--steps", "5", "--warmup", "2", "--no-cpu-baseline", "--no-nve"],
+               ("metric", "value", "unit", "ms_per_step", "dtype", "config", "atom_steps_per_s",
+                "verlet_ns_per_day", "verlet_ms_per_step", "speedup_vs_verlet", "list_rebuilds",
+                "roofline"))
+    c3 = child(["--batch", "--precision", "bf16"],
+               ("molecules", "n_atoms", "precision", "tuned_shapes", "batched_ms",
+                "per_molecule_loop_ms", "batched_molecules_per_s", "loop_molecules_per_s",
+                "batched_atom_evals_per_s", "speedup"))
+    return {"solvated100k_bf16_dmts": c4, "batch256_bf16": c3}
 
 
 if __name__ == "__main__":
