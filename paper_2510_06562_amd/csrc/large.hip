@@ -445,14 +445,9 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
                        : *reinterpret_cast<const float4*>(Tj + c0);
       bf16x8 wt[NP];
       load_w<NP>(sW, 16 * bb4 + cl, g, wt);
-      // the BF16 form starts the accumulator from the receiver term of its four channels;
-      // the FP32 form adds it afterwards (fewer registers live across its 12 products)
-      f32x4 init = {0.f, 0.f, 0.f, 0.f};
-      if (NP == 1) {
-        const float4 br = *reinterpret_cast<const float4*>(&sB[w][16 * bb4 + 4 * g]);
-        init = f32x4{br.x, br.y, br.z, br.w};
-      }
-      ga = radial_block<NP>(wt, bt, init, true);
+      // the receiver term of the lane's four channels starts the accumulator
+      const float4 br = *reinterpret_cast<const float4*>(&sB[w][16 * bb4 + 4 * g]);
+      ga = radial_block<NP>(wt, bt, f32x4{br.x, br.y, br.z, br.w}, true);
       gd = radial_block<NP>(wt, dbt, f32x4{0.f, 0.f, 0.f, 0.f}, true);
       dmv = f32x4{0.f, 0.f, 0.f, 0.f};
       // K index 4 s + g = y runs over the ten components; rows 12..15 (s = 3) are left
@@ -477,15 +472,12 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       const int b = hb + bb4;
       const int c0 = 16 * b + 4 * g;   // the lane's four channels c0 .. c0+3
       const int l0 = 16 * bb4 + 4 * g;  // their index within the half
-      const float4 bb = NP == 1 ? make_float4(0.f, 0.f, 0.f, 0.f)
-                                : *reinterpret_cast<const float4*>(&sB[w][l0]);
       f32x4 mv;
       float4 dav;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float addr = r == 0 ? add.x : r == 1 ? add.y : r == 2 ? add.z : add.w;
-        const float br = r == 0 ? bb.x : r == 1 ? bb.y : r == 2 ? bb.z : bb.w;
-        const float a = NP == 1 ? ga[r] + addr : ga[r] + br + addr;
+        const float a = ga[r] + addr;
         float sv, dsv;
         silu_and_grad(a, sv, dsv);
         const float m = fc * sv;
