@@ -123,14 +123,17 @@ __device__ __forceinline__ void split_terms(const float (&x)[8], bf16x8 (&t)[NP]
   }
 }
 
-// b_k(r) = exp(-(r - k sigma)^2 / (2 sigma^2)) at k = k0 .. k0 + 7 (zero for an invalid
-// pair).  NP = 3: eight exponentials.  NP = 1: the centres are sigma apart, so
-// b_{k+1} = b_k rho_k with rho_k = exp((r - k sigma) / sigma - 1/2) = rho_{k-1} / e; two
-// exponentials, at a relative error of a few 1e-6, far below the bfloat16 rounding of the
-// operand.  With r < r_c = (K - 1) sigma the ratio stays below e^K.
+// b_k(r) = exp(-(r - k sigma)^2 / (2 sigma^2)) and x_k = r - k sigma at k = k0 .. k0 + 7
+// (b zero for an invalid pair).  NP = 3: eight exponentials, each 2^(c x^2) with
+// c = -log2(e) / (2 sigma^2); an invalid pair is moved to r = 1e18, where c x^2 is below
+// -2^126 (or -inf) and the power exactly 0, so that no select per exponential is needed.
+// NP = 1: the centres are sigma apart, so b_{k+1} = b_k rho_k with
+// rho_k = exp((r - k sigma) / sigma - 1/2) = rho_{k-1} / e; two exponentials, at a relative
+// error of a few 1e-6, far below the bfloat16 rounding of the operand.  With
+// r < r_c = (K - 1) sigma the ratio stays below e^K.
 template <int NP>
 __device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float sigma,
-                                             float inv_s2, float (&bk)[8]) {
+                                             float inv_s2, float (&bk)[8], float (&xk)[8]) {
   if (NP == 1) {
     const float x0 = r - sigma * k0;
     // invalid pairs: exponent -1e30 gives 0 without a branch around the exponential
@@ -143,12 +146,16 @@ __device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float 
       rho *= 0.36787944117144233f;   // e^-1
       bk[e] = b;
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xk[e] = r - sigma * (k0 + e);
     return;
   }
+  const float c = -0.72134752044448170f * inv_s2;   // -log2(e) / 2 / sigma^2
+  const float re = valid ? r : 1e18f;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const float x = r - sigma * (k0 + e);
-    bk[e] = __expf(valid ? -0.5f * x * x * inv_s2 : -1e30f);
+    xk[e] = re - sigma * (k0 + e);
+    bk[e] = __builtin_amdgcn_exp2f(c * (xk[e] * xk[e]));
   }
 }
 
@@ -256,8 +263,8 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     // A operand of a = b W_b: b_k of pair cl at k = 8 g + e, as NP bfloat16 terms
     const float rp = geo[t0 + cl].w;
     const bool vp = nbr[t0 + cl] >= 0 && rp < P.rc;
-    float bk[8];
-    radial_basis<NP>(rp, vp, 8 * g, P.sigma, inv_s2, bk);
+    float bk[8], xk[8];
+    radial_basis<NP>(rp, vp, 8 * g, P.sigma, inv_s2, bk, xk);
     bf16x8 bt[NP];
     split_terms<NP>(bk, bt);
     // the lane's four pairs of the D layout: 4 g + r
@@ -278,7 +285,9 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       // an invalid pair has u = 0, whose components are Y = (1, 0, ..., 0)
       const float ux = v ? gv.x * irc : 0.f, uy = v ? gv.y * irc : 0.f;
       const float uz = v ? gv.z * irc : 0.f;
-      yop[r] = ycomp(cl, ux, uy, uz);
+      // f_c of the pair is folded into its Y components (the A operand of M^T), so the
+      // m operand below is SiLU(a) alone
+      yop[r] = fc[r] * ycomp(cl, ux, uy, uz);
     }
     // sender terms of the lane's sixteen (pair, channel) values, all requested before the
     // products so that their latencies overlap
@@ -304,8 +313,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       f32x4 mv;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float a = acc[b][r] + snd[b][r];   // f_c = 0 if invalid
-        mv[r] = fc[r] * silu_f(a);
+        mv[r] = silu_f(acc[b][r] + snd[b][r]);   // f_c (0 if invalid) sits in Y
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
@@ -396,10 +404,10 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
   const float pi_rc = 3.14159265358979f * irc;
-  // row of D read by lane (cl, g) for the angular sums: k + 1 = cl + 1, clamped to row 9
-  // for cl >= 9, whose output rows k >= 9 are not used (an MFMA output row depends only on
-  // the A row of the same index, so any finite value will do there)
-  const int kr = cl < 9 ? cl + 1 : 9;
+  // row of D read by lane (cl, g) for the angular sums: y = cl, clamped to row 9 for
+  // cl >= 10, whose output rows are not used (an MFMA output row depends only on the A row
+  // of the same index, so any finite value will do there)
+  const int kr = cl < NMOM ? cl : NMOM - 1;
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
     // the lane's pair
@@ -411,32 +419,33 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float fc, dfc;
     cutoff_fn(gv.w, pi_rc, vp, fc, dfc);
     const float ux = vp ? gv.x * irc : 0.f, uy = vp ? gv.y * irc : 0.f, uz = vp ? gv.z * irc : 0.f;
-    // radial operands b_k(r), b'_k(r) at k = 8 g + e, as NP bfloat16 terms
+    // radial operands b_k(r), x_k b_k(r) at k = 8 g + e, as NP bfloat16 terms
     bf16x8 bt[NP], dbt[NP];
     {
-      float bk[8], dbk[8];
-      radial_basis<NP>(gv.w, vp, 8 * g, P.sigma, inv_s2, bk);
+      // b'_k = -x_k b_k / sigma^2: the operand holds x_k b_k, and the factor -1/sigma^2
+      // is applied once to the pair's sum S2
+      float bk[8], xk[8], dbk[8];
+      radial_basis<NP>(gv.w, vp, 8 * g, P.sigma, inv_s2, bk, xk);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float x = gv.w - P.sigma * (8 * g + e);
-        dbk[e] = -x * inv_s2 * bk[e];
-      }
+      for (int e = 0; e < 8; ++e) dbk[e] = xk[e] * bk[e];
       split_terms<NP>(bk, bt);
       split_terms<NP>(dbk, dbt);
     }
-    float yop[3];   // B operand of dm^T: Y^T[4 s + g][pair cl]
+    // B operand of dm^T: f_c Y^T[4 s + g][pair cl].  With f_c folded in, the product is
+    // f_c dm, the factor that dE/da = f_c dm SiLU'(a) needs.
+    float yop[3];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) yop[s] = ycomp(4 * s + g, ux, uy, uz);
+    for (int s = 0; s < 3; ++s) yop[s] = fc * ycomp(4 * s + g, ux, uy, uz);
     // invalid pairs have f_c = 0, so any finite sender term will do: use the receiver's
     const float* Aj = LAYER == 2 ? P2 + (size_t)(j >= 0 ? j : i) * 2 * F_L : nullptr;
     const float* Tj = LAYER == 1 ? sTs + species[j >= 0 ? j : i] * F_L : nullptr;
-    float S1 = 0.f, S2 = 0.f;
-    // G^T[k][pair] = sum_c D[c][k + 1] m[c][pair] on MFMA: K runs over the lane group's
-    // channels (index g <-> channel 16 b + 4 g + s, register s of m^T), the A operand is
-    // D[16 b + 4 g + s][k + 1] for row k = cl < 9.
+    float S2 = 0.f;
+    // G^T[y][pair] = sum_c D[c][y] SiLU(a)[c][pair] on MFMA: K runs over the lane group's
+    // channels (index g <-> channel 16 b + 4 g + s, register s of the SiLU operand), the A
+    // operand is D[16 b + 4 g + s][y] for row y = cl < 10.
     f32x4 Gt = {0.f, 0.f, 0.f, 0.f};
-    // The three products of channel block bb4: a^T and a'^T = W_b b^T, W_b b'^T and
-    // dm^T = D^T Y^T.  They are issued one block ahead, so that the matrix cores work on
+    // The three products of channel block bb4: a^T = W_b b^T, W_b (x b)^T (a'^T up to the
+    // factor -1/sigma^2) and dm^T = D^T Y^T.  They are issued one block ahead, so that the matrix cores work on
     // block bb4 + 1 while the vector units finish bb4.
     auto issue = [&](int bb4, f32x4& ga, f32x4& gd, f32x4& dmv, float4& add) {
       // sender term of the lane's four channels 16 b + 4 g .. + 3
@@ -480,12 +489,9 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         const float a = ga[r] + addr;
         float sv, dsv;
         silu_and_grad(a, sv, dsv);
-        const float m = fc * sv;
-        const float dm = dmv[r];
-        const float da = dm * fc * dsv;
-        S1 = fmaf(dm, sv, S1);
+        const float da = dmv[r] * dsv;   // dmv holds f_c dm
         S2 = fmaf(da, gd[r], S2);
-        mv[r] = m;
+        mv[r] = sv;
         if (r == 0) dav.x = da; else if (r == 1) dav.y = da; else if (r == 2) dav.z = da; else dav.w = da;
       }
 #pragma unroll
@@ -517,30 +523,35 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       // one region per block: the live products are those of two blocks
       __builtin_amdgcn_sched_barrier(0);
     }
-    // channel sums of the pair: in-lane above, then across the four groups
-    S1 += __shfl_xor(S1, 16, 64);
-    S1 += __shfl_xor(S1, 32, 64);
+    // channel sum of the pair: in-lane above, then across the four groups
     S2 += __shfl_xor(S2, 16, 64);
     S2 += __shfl_xor(S2, 32, 64);
-    // Gt register r of group g holds component 4 g + r of pair cl: collect all nine
-    float G[9];
+    // Gt register r of group g holds row 4 g + r of pair cl: collect rows 0..9
+    float G[NMOM];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       G[r] = Gt[r];
       G[4 + r] = __shfl_xor(Gt[r], 16, 64);
     }
     G[8] = __shfl_xor(Gt[0], 32, 64);
+    G[9] = __shfl_xor(Gt[1], 32, 64);
     if (g == 0) {
-      // G[0..2] = sum m dM1, G[3..5] = sum m dM2_aa, G[6..8] = sum m 2 dM2_ab (xy, xz, yz)
-      const float t23 = (2.0f / 3.0f) * (G[3] + G[4] + G[5]);
-      const float ax = G[0] + 2.0f * G[3] * ux + G[6] * uy + G[7] * uz - t23 * ux;
-      const float ay = G[1] + G[6] * ux + 2.0f * G[4] * uy + G[8] * uz - t23 * uy;
-      const float az = G[2] + G[7] * ux + G[8] * uy + 2.0f * G[5] * uz - t23 * uz;
-      const float rho = dfc * S1 + S2;
+      // S1 = sum_c dm_c SiLU(a_c) = sum_y Y[y] G[y]; the sums of m = f_c SiLU(a) against
+      // dM1, dM2_aa and 2 dM2_ab (xy, xz, yz) are f_c G[1..3], f_c G[4..6], f_c G[7..9]
+      const float t3 = (ux * ux + uy * uy + uz * uz) * (1.0f / 3.0f);
+      const float S1 = G[0] + ux * G[1] + uy * G[2] + uz * G[3] + (ux * ux - t3) * G[4] +
+                       (uy * uy - t3) * G[5] + (uz * uz - t3) * G[6] + ux * uy * G[7] +
+                       ux * uz * G[8] + uy * uz * G[9];
+      const float t23 = (2.0f / 3.0f) * (G[4] + G[5] + G[6]);
+      const float ax = G[1] + 2.0f * G[4] * ux + G[7] * uy + G[8] * uz - t23 * ux;
+      const float ay = G[2] + G[7] * ux + 2.0f * G[5] * uy + G[9] * uz - t23 * uy;
+      const float az = G[3] + G[8] * ux + G[9] * uy + 2.0f * G[6] * uz - t23 * uz;
+      const float rho = fmaf(-inv_s2, S2, dfc * S1);
       const float ir = vp ? __builtin_amdgcn_rcpf(gv.w) : 0.f;
-      const float vx = rho * gv.x * ir + irc * ax;
-      const float vy = rho * gv.y * ir + irc * ay;
-      const float vz = rho * gv.z * ir + irc * az;
+      const float fi = irc * fc;
+      const float vx = rho * gv.x * ir + fi * ax;
+      const float vy = rho * gv.y * ir + fi * ay;
+      const float vz = rho * gv.z * ir + fi * az;
       // this half's share of v_ij: slot [p][half] of the [cap][2] float4 array
       float4* vh = reinterpret_cast<float4*>(v) + 2 * (size_t)p + half;
       if (LAYER == 2) {
