@@ -213,6 +213,31 @@ __device__ __forceinline__ float ycomp(int y, float ux, float uy, float uz) {
   return v;
 }
 
+// Component y of Y(u) as p_a p_b - d |u|^2 for a fixed row y: p_0 = 1, p_1..3 = u_x, u_y,
+// u_z, and d = 1/3 on the diagonal rows 4..6 of the traceless second moment.  Rows past 9
+// give 1 (any finite value will do there).  For a lane-constant row the choices of p_a, p_b
+// are lane masks set once, and a component costs two selects per factor.
+struct YRow {
+  bool ax, ay, az, bx, by, bz;   // p_a, p_b = u_x, u_y, u_z (else 1)
+  float d;
+  __device__ explicit YRow(int y) {
+    const int a = y >= 1 && y <= 3 ? y : y >= 4 && y <= 6 ? y - 3 : y == 7 || y == 8 ? 1 : y == 9 ? 2 : 0;
+    const int b = y >= 4 && y <= 6 ? y - 3 : y == 7 ? 2 : y == 8 || y == 9 ? 3 : 0;
+    ax = a == 1;
+    ay = a == 2;
+    az = a == 3;
+    bx = b == 1;
+    by = b == 2;
+    bz = b == 3;
+    d = y >= 4 && y <= 6 ? 1.0f / 3.0f : 0.f;
+  }
+  __device__ float operator()(float ux, float uy, float uz, float uu) const {
+    const float pa = ax ? ux : ay ? uy : az ? uz : 1.0f;
+    const float pb = bx ? ux : by ? uy : bz ? uz : 1.0f;
+    return fmaf(-d, uu, pa * pb);
+  }
+};
+
 // Cosine cutoff and its derivative (zero outside); pi_rc = pi / r_c.
 __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, float& fc,
                                           float& dfc) {
@@ -258,6 +283,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
   const float pi_rc = 3.14159265358979f * irc;
+  const YRow yrow(cl);   // the lane's row of M^T
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
     // A operand of a = b W_b: b_k of pair cl at k = 8 g + e, as NP bfloat16 terms
@@ -282,12 +308,11 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       cutoff_fn(gv.w, pi_rc, v, fc[r], dfc);
       jj[r] = v ? j : -1;
       zz[r] = LAYER == 1 ? species[v ? j : i] : 0;
-      // an invalid pair has u = 0, whose components are Y = (1, 0, ..., 0)
-      const float ux = v ? gv.x * irc : 0.f, uy = v ? gv.y * irc : 0.f;
-      const float uz = v ? gv.z * irc : 0.f;
       // f_c of the pair is folded into its Y components (the A operand of M^T), so the
-      // m operand below is SiLU(a) alone
-      yop[r] = fc[r] * ycomp(cl, ux, uy, uz);
+      // m operand below is SiLU(a) alone; an invalid pair has f_c = 0 and finite
+      // (zero-padded) geometry, so its Y needs no select
+      const float ur = gv.w * irc;
+      yop[r] = fc[r] * yrow(gv.x * irc, gv.y * irc, gv.z * irc, ur * ur);
     }
     // sender terms of the lane's sixteen (pair, channel) values, all requested before the
     // products so that their latencies overlap
