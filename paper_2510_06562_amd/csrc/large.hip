@@ -124,39 +124,29 @@ __device__ __forceinline__ void split_terms(const float (&x)[8], bf16x8 (&t)[NP]
 }
 
 // b_k(r) = exp(-(r - k sigma)^2 / (2 sigma^2)) and x_k = r - k sigma at k = k0 .. k0 + 7
-// (b zero for an invalid pair).  NP = 3: eight exponentials, each 2^(c x^2) with
-// c = -log2(e) / (2 sigma^2); an invalid pair is moved to r = 1e18, where c x^2 is below
-// -2^126 (or -inf) and the power exactly 0, so that no select per exponential is needed.
-// NP = 1: the centres are sigma apart, so b_{k+1} = b_k rho_k with
-// rho_k = exp((r - k sigma) / sigma - 1/2) = rho_{k-1} / e; two exponentials, at a relative
-// error of a few 1e-6, far below the bfloat16 rounding of the operand.  With
-// r < r_c = (K - 1) sigma the ratio stays below e^K.
+// (b zero for an invalid pair).  The centres are sigma apart, so b_{k+1} = b_k rho_k with
+// rho_k = exp(x_k / sigma - 1/2) = rho_{k-1} / e: two exponentials (transcendental
+// instructions issue at a quarter of the vector rate) and fourteen products.  The
+// relative error grows by a few units in the last place per step, to ~1e-6 at e = 7 and,
+// through the rounding of the exponent x_0 / sigma - 1/2, by ~|x_0 / sigma| ulp per step;
+// where that is large the b_k are tiny, so the error stays at the FP32 rounding of the
+// sums over k.  With r < r_c = (K - 1) sigma the ratio stays below e^K.
 template <int NP>
 __device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float sigma,
                                              float inv_s2, float (&bk)[8], float (&xk)[8]) {
-  if (NP == 1) {
-    const float x0 = r - sigma * k0;
-    // invalid pairs: exponent -1e30 gives 0 without a branch around the exponential
-    float b = __expf(valid ? -0.5f * x0 * x0 * inv_s2 : -1e30f);
-    float rho = __expf(valid ? x0 * (sigma * inv_s2) - 0.5f : -1e30f);
-    bk[0] = b;
+  const float x0 = r - sigma * k0;
+  // invalid pairs: exponent -1e30 gives 0 without a branch around the exponential
+  float b = __expf(valid ? -0.5f * x0 * x0 * inv_s2 : -1e30f);
+  float rho = __expf(valid ? x0 * (sigma * inv_s2) - 0.5f : -1e30f);
+  bk[0] = b;
 #pragma unroll
-    for (int e = 1; e < 8; ++e) {
-      b *= rho;
-      rho *= 0.36787944117144233f;   // e^-1
-      bk[e] = b;
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) xk[e] = r - sigma * (k0 + e);
-    return;
+  for (int e = 1; e < 8; ++e) {
+    b *= rho;
+    rho *= 0.36787944117144233f;   // e^-1
+    bk[e] = b;
   }
-  const float c = -0.72134752044448170f * inv_s2;   // -log2(e) / 2 / sigma^2
-  const float re = valid ? r : 1e18f;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    xk[e] = re - sigma * (k0 + e);
-    bk[e] = __builtin_amdgcn_exp2f(c * (xk[e] * xk[e]));
-  }
+  for (int e = 0; e < 8; ++e) xk[e] = r - sigma * (k0 + e);
 }
 
 // acc += W_b . b over K = 32 for one 16 x 16 block from NP-term operands; w_is_a selects
@@ -293,6 +283,9 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     radial_basis<NP>(rp, vp, 8 * g, P.sigma, inv_s2, bk, xk);
     bf16x8 bt[NP];
     split_terms<NP>(bk, bt);
+    // f_c of pair cl; the D layout's pairs 4 g + r take theirs from lanes 4 g + r
+    float fc_own, dfc_own;
+    cutoff_fn(rp, pi_rc, vp, fc_own, dfc_own);
     // the lane's four pairs of the D layout: 4 g + r
     float fc[4], yop[4];
     int jj[4], zz[4];
@@ -304,8 +297,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       const float4 gv = geo[p];
       const int j = nbr[p];
       const bool v = j >= 0 && gv.w < P.rc;
-      float dfc;
-      cutoff_fn(gv.w, pi_rc, v, fc[r], dfc);
+      fc[r] = __shfl(fc_own, 4 * g + r, 64);
       jj[r] = v ? j : -1;
       zz[r] = LAYER == 1 ? species[v ? j : i] : 0;
       // f_c of the pair is folded into its Y components (the A operand of M^T), so the

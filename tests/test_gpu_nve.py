@@ -64,12 +64,15 @@ def test_water4500_fp32_10ps_conserves_energy():
     drift, se, dev, _ = out["dmts_4fs"]
     # first clause: no visible drift over 10 ps
     assert abs(drift) <= 1e-5 and dev <= 2e-5
-    # second clause ("no more than the FP64 path's"), as evaluated here: FP32 rounding
-    # adds little to the DMTS drift (the same kernels under 1 fs Verlet, where the
-    # splitting is gone, drift by at most a tenth of it), and the DMTS drift is the
-    # splitting's: it falls more than eightfold from a 4 fs to a 2 fs outer step, which
-    # rounding would not do
-    v_drift = out["verlet_1fs"][0]
-    assert abs(v_drift) <= 0.1 * abs(drift)
-    assert abs(out["dmts_2fs"][0]) * 8.0 <= abs(drift)
+    # second clause ("no more than the FP64 path's"), as evaluated here: the DMTS energy
+    # error is the splitting's and FP32 rounding adds little to it.  Its size is the
+    # largest deviation of H from H(0); the fitted 10 ps slope of one chaotic trajectory
+    # is not a stable measure of it (runs that differ only in rounding order gave
+    # +2.3e-6, +2.9e-6, -3.6e-6 and +0.1e-6 eV/atom, with deviations of 2.6-4.4e-6).  The
+    # splitting's shadow-energy offset goes as the step squared, so the deviation falls
+    # more than fourfold from a 4 fs to a 2 fs outer step, which rounding would not do;
+    # the same kernels under 1 fs Verlet, where the splitting is gone, drift by at most
+    # a tenth of it over the 10 ps
+    assert out["dmts_2fs"][2] * 4.0 <= dev
+    assert abs(out["verlet_1fs"][0]) <= 0.1 * dev
     assert all(v[3] == 0 for v in out.values())
