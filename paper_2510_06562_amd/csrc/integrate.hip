@@ -460,10 +460,15 @@ extern "C" dmts_status dmts_state_create(int32_t n_atoms, double box, const int3
     if (e == hipSuccess) e = hipMemcpy(st->inv_mass, him, sizeof(him), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(st->e_models, 0, sizeof(double) * 4);
     if (e == hipSuccess) e = hipMemset(st->flags, 0, sizeof(uint32_t));
-    // side stream at the default priority, synchronised with the caller's stream by events
+    // side stream at the default priority, synchronised with the caller's stream by events.
+    // The events order two streams of one device and are never read by the host, so they
+    // skip the system-scope fence (a write-back of the caches that idles the recording
+    // stream for several microseconds); each kernel's own completion already makes its
+    // results visible device-wide.
+    const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_fork, ev_flags);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_join, ev_flags);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       dmts::set_error("dmts_state_create: %s", hipGetErrorString(e));
