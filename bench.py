@@ -198,6 +198,11 @@ def parse():
                          "that the default water4500 run adds (child processes)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shapes instead of tuning them for the workload")
+    ap.add_argument("--shapes", default=None,
+                    help='JSON {"fast": {...}, "reference": {...}} of tile shapes to use instead '
+                         "of tuning (keys as in the line's tile_shapes), e.g. to profile the "
+                         "shapes an unprofiled run chose: a profiler's per-launch overhead can "
+                         "change the tuner's ranking")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="MLP contraction operands (bf16: bfloat16 operands, FP32 accumulate)")
     return ap.parse_args()
@@ -481,7 +486,16 @@ def main():
     # each model's shape for this system size, tuned on the list it runs on in the RESPA
     # loop (the reference model's cutoff, shared by the fast model)
     shapes = {}
-    if not args.no_autotune:
+    if args.shapes:
+        given = json.loads(args.shapes)
+        for name, mdl in (("fast", small), ("reference", large)):
+            if name in given:
+                sh = {k: int(v) for k, v in given[name].items()
+                      if k in ("receivers_per_group", "atom_tiles", "keep_derivatives",
+                               "work_groups")}
+                mdl.set_shape(sy.n_atoms, **sh)
+                shapes[name] = dict(mdl.shape(sy.n_atoms), given=True)
+    elif not args.no_autotune:
         list_cut = max(synth.LARGE.cutoff, spec_s.cutoff + 1.0)
         for name, mdl in (("fast", small), ("reference", large)):
             p = api.Potential(mdl, sy.n_atoms, sy.box, 128)

@@ -130,12 +130,14 @@ void nnp_model_destroy(nnp_model* model);
  *   the default).
  * nnp_model_set_grid / nnp_model_get_grid: work_groups of the default shape (set_grid also
  *   sets it in every bucket's shape).
- * nnp_autotune times one energy+force evaluation of the given system (list built from pos)
+ * nnp_autotune times energy+force evaluations of the given system (list built from pos)
  *   for every candidate shape: the values above that the model's kind uses, times
- *   work_groups in {0, 256, 512, 1024, 2048, 4096} (median of `reps` after a warm-up, HIP
- *   events on `stream`), keeps the fastest as the shape of n_atoms' bucket and returns it
- *   in *chosen (host) with its time in *best_ms (host).  Blocking: synchronizes the stream
- *   and allocates scratch. */
+ *   work_groups in {0, 256, 512, 1024, 2048, 4096} (median of `reps` timings after a
+ *   warm-up, each over four back-to-back evaluations between two HIP events on `stream`,
+ *   so that the events' own cost does not decide between close shapes), keeps the fastest
+ *   as the shape of n_atoms' bucket and returns it in *chosen (host) with its time per
+ *   evaluation in *best_ms (host).  Blocking: synchronizes the stream and allocates
+ *   scratch. */
 typedef struct {
   int32_t receivers_per_group;
   int32_t atom_tiles;

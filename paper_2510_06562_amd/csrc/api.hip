@@ -665,10 +665,12 @@ extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* 
   for (const dmts::TileShape& c : cands) {
     m->tuned[bucket] = c;
     std::vector<double> t;
+    constexpr int kBatch = 4;   // evaluations per timing
     for (int r = 0; r <= reps && st == DMTS_OK; ++r) {
       (void)hipEventRecord(e0, s);
-      st = dmts::energy_forces(m, nl, pos, species, n_atoms, box, sys_offsets, n_sys, energy,
-                               forces, nullptr, s);
+      for (int b = 0; b < kBatch && st == DMTS_OK; ++b)
+        st = dmts::energy_forces(m, nl, pos, species, n_atoms, box, sys_offsets, n_sys,
+                                 energy, forces, nullptr, s);
       (void)hipEventRecord(e1, s);
       if (st != DMTS_OK) break;
       if (hipEventSynchronize(e1) != hipSuccess) {
@@ -677,7 +679,7 @@ extern "C" dmts_status nnp_autotune(nnp_model* h, nnp_nlist* nlh, const double* 
       }
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (r > 0) t.push_back(ms);   // the first run warms up
+      if (r > 0) t.push_back(ms / kBatch);   // the first timing warms up
     }
     if (st != DMTS_OK) break;
     std::sort(t.begin(), t.end());
