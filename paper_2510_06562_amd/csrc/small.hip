@@ -241,9 +241,11 @@ __device__ __forceinline__ void small_tile_store(const float (&dm)[4][4], const 
 //      the others recomputed with the same arithmetic), written to the pair's list slot,
 //      with the pair's record in the receiver's compact row (rec, cnt) for the force kernel.
 // KEEP is a tile shape of the autotuner: registers capped at 168 (three waves per SIMD)
-// with it, at 102 (five) without; 32 KiB of LDS lets five work-groups share a CU.
+// with it, at 128 (four) without (asked for five, the compiler moves values into the
+// accumulation registers and ends at three); 33 KiB of LDS lets four work-groups share a
+// CU.
 template <bool BF16, bool KEEP>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KEEP ? 3 : 5)))
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KEEP ? 3 : 4)))
 k_small_eval(SmallParams P, const int32_t* __restrict__ offs, const int32_t* __restrict__ nbr,
              const double* __restrict__ pos, const int32_t* __restrict__ species, int n,
              double box, float* __restrict__ atom_e, float4* __restrict__ rec_all,
