@@ -131,7 +131,6 @@ __device__ __forceinline__ void split_terms(const float (&x)[8], bf16x8 (&t)[NP]
 // through the rounding of the exponent x_0 / sigma - 1/2, by ~|x_0 / sigma| ulp per step;
 // where that is large the b_k are tiny, so the error stays at the FP32 rounding of the
 // sums over k.  With r < r_c = (K - 1) sigma the ratio stays below e^K.
-template <int NP>
 __device__ __forceinline__ void radial_basis(float r, bool valid, int k0, float sigma,
                                              float inv_s2, float (&bk)[8], float (&xk)[8]) {
   const float x0 = r - sigma * k0;
@@ -237,10 +236,12 @@ __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, floa
   dfc = valid ? -0.5f * pi_rc * sn : 0.f;
 }
 
-// Both pair kernels are latency bound at low occupancy: the registers of the forward kernel
-// are capped so that four waves share a SIMD (five in the BF16 form, at the cost of a few
-// spilled registers outside the tile loop, measured faster), those of the reverse kernel
-// for three (four for the BF16 form of interaction 1, which fits 128 registers).
+// The FP32 forms of both pair kernels are bound by instruction issue (FP32 MFMA, vector and
+// transcendental instructions share a SIMD's issue and overlap little), the BF16 forms by
+// latency at low occupancy: the registers of the forward kernel are capped so that four
+// waves share a SIMD (five in the BF16 form of interaction 1, at the cost of a few spilled
+// registers outside the tile loop, measured faster), those of the reverse kernel for three
+// (four for the BF16 form of interaction 1, which fits 128 registers).
 // NW: receivers (one wave each) per work-group, a tile shape the autotuner chooses.
 template <int LAYER, int NP, int NW>
 __global__ void __launch_bounds__(NW * 64)
@@ -280,7 +281,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     const float rp = geo[t0 + cl].w;
     const bool vp = nbr[t0 + cl] >= 0 && rp < P.rc;
     float bk[8], xk[8];
-    radial_basis<NP>(rp, vp, 8 * g, P.sigma, inv_s2, bk, xk);
+    radial_basis(rp, vp, 8 * g, P.sigma, inv_s2, bk, xk);
     bf16x8 bt[NP];
     split_terms<NP>(bk, bt);
     // f_c of pair cl; the D layout's pairs 4 g + r take theirs from lanes 4 g + r
@@ -442,7 +443,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       // b'_k = -x_k b_k / sigma^2: the operand holds x_k b_k, and the factor -1/sigma^2
       // is applied once to the pair's sum S2
       float bk[8], xk[8], dbk[8];
-      radial_basis<NP>(gv.w, vp, 8 * g, P.sigma, inv_s2, bk, xk);
+      radial_basis(gv.w, vp, 8 * g, P.sigma, inv_s2, bk, xk);
 #pragma unroll
       for (int e = 0; e < 8; ++e) dbk[e] = xk[e] * bk[e];
       split_terms<NP>(bk, bt);
