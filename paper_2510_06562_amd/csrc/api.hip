@@ -277,17 +277,28 @@ std::vector<float> transpose_block(const float* W, int rows, int cols, int c0, i
   return t;
 }
 
-// Species tables: T[z][c] = sum_e W[c][c0 + e] emb[z][e]  (float64 accumulation)
+// Species tables: T[z][c] = scale sum_e W[c][c0 + e] emb[z][e]  (float64 accumulation)
 std::vector<float> species_table(const float* W, int F, int cols, int c0, const float* emb,
-                                 int Z, int D) {
+                                 int Z, int D, double scale = 1.0) {
   std::vector<float> t((size_t)Z * F);
   for (int z = 0; z < Z; ++z)
     for (int c = 0; c < F; ++c) {
       double acc = 0.0;
       for (int e = 0; e < D; ++e) acc += (double)W[(size_t)c * cols + c0 + e] * emb[z * D + e];
-      t[(size_t)z * F + c] = (float)acc;
+      t[(size_t)z * F + c] = (float)(scale * acc);
     }
   return t;
+}
+
+// The two-interaction model's pair kernels take every term of the message pre-activation
+// a_ij (the radial weights W_b, the species tables of interaction 1 and the [A | B]
+// projection of interaction 2) multiplied by -log2(e), so that e^-a is one exp2 of what
+// they accumulate; they undo the factor where SiLU(a) leaves the kernel.
+constexpr double kNegLog2e = -1.4426950408889634;
+
+std::vector<float> scaled(std::vector<float> v, double k) {
+  for (auto& x : v) x = (float)(k * (double)x);
+  return v;
 }
 
 }  // namespace
@@ -358,8 +369,8 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
     const float* U2 = b.take((size_t)F * Q);
     const float* Wo = b.take((size_t)F * F);
     const float* wo = b.take(F);
-    append(P, m->o_Td, species_table(Wp1, F, cols1, K, emb, Z, D));
-    append(P, m->o_Ts, species_table(Wp1, F, cols1, K + D, emb, Z, D));
+    append(P, m->o_Td, species_table(Wp1, F, cols1, K, emb, Z, D, kNegLog2e));
+    append(P, m->o_Ts, species_table(Wp1, F, cols1, K + D, emb, Z, D, kNegLog2e));
     append(P, m->o_U1T, transpose_block(U1, F, Q, 0, Q));
     append(P, m->o_U1, std::vector<float>(U1, U1 + (size_t)F * Q));
     append(P, m->o_U2T, transpose_block(U2, F, Q, 0, Q));
@@ -376,7 +387,7 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
       for (int k = 0; k < 2 * F; ++k)
         W2hs[(size_t)e * 2 * F + k] = k < F ? Wp2[(size_t)k * cols2 + K + e]
                                             : Wp2[(size_t)(k - F) * cols2 + K + F + e];
-    append(P, m->o_W2h, W2h);
+    append(P, m->o_W2h, scaled(W2h, kNegLog2e));
     append(P, m->o_W2hs, W2hs);
     append(P, m->o_WoT, transpose_block(Wo, F, F, 0, F));
     append(P, m->o_Wo, std::vector<float>(Wo, Wo + (size_t)F * F));
@@ -405,8 +416,8 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
           for (int c = 0; c < nc; ++c) t[(size_t)r * nc + c] = W[(size_t)r * cols + c0 + c];
         return t;
       };
-      append16(H, m->h_Wb1, block(Wp1, F, cols1, 0, K));
-      append16(H, m->h_Wb2, block(Wp2, F, cols2, 0, K));
+      append16(H, m->h_Wb1, scaled(block(Wp1, F, cols1, 0, K), kNegLog2e));
+      append16(H, m->h_Wb2, scaled(block(Wp2, F, cols2, 0, K), kNegLog2e));
       append16(H, m->h_U1, std::vector<float>(U1, U1 + (size_t)F * Q));            // [F][3F]
       std::vector<float> W2h((size_t)2 * F * F), W2hs((size_t)F * 2 * F);
       for (int nn = 0; nn < 2 * F; ++nn)                                              // [2F][F]
@@ -417,7 +428,7 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
         for (int k = 0; k < 2 * F; ++k)
           W2hs[(size_t)e * 2 * F + k] = k < F ? Wp2[(size_t)k * cols2 + K + e]
                                               : Wp2[(size_t)(k - F) * cols2 + K + F + e];
-      append16(H, m->h_W2h, W2h);
+      append16(H, m->h_W2h, scaled(W2h, kNegLog2e));
       append16(H, m->h_U2, std::vector<float>(U2, U2 + (size_t)F * Q));
       append16(H, m->h_Wo, std::vector<float>(Wo, Wo + (size_t)F * F));
       append16(H, m->h_WoT, transpose_block(Wo, F, F, 0, F));
@@ -437,8 +448,8 @@ extern "C" dmts_status nnp_model_create(const nnp_model_desc* desc, const float*
         b1[(size_t)c * K + k] = Wp1[(size_t)c * cols1 + k];
         b2[(size_t)c * K + k] = Wp2[(size_t)c * cols2 + k];
       }
-    append16_terms3(H, m->h_Wb1, b1);
-    append16_terms3(H, m->h_Wb2, b2);
+    append16_terms3(H, m->h_Wb1, scaled(b1, kNegLog2e));
+    append16_terms3(H, m->h_Wb2, scaled(b2, kNegLog2e));
   }
   if (m->params.reserve(P.size() * sizeof(float), nullptr) != DMTS_OK) {
     delete m;

@@ -227,6 +227,20 @@ struct YRow {
   }
 };
 
+// The pair kernels accumulate a' = -log2(e) a (every term of the pre-activation is stored
+// with that factor), so that e^-a = 2^a' costs no product: logistic(a) = 1 / (1 + 2^a'),
+// and a' logistic(a) = -log2(e) SiLU(a), whose factor the kernels undo where SiLU(a) leaves
+// them (the moments M, the angular sums G and S1).
+constexpr float kLn2 = 0.69314718055994531f;
+__device__ __forceinline__ float silu_pre(float ap) {   // -log2(e) SiLU(a)
+  return ap * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(ap));
+}
+__device__ __forceinline__ void silu_pre_grad(float ap, float& yp, float& dy) {
+  const float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(ap));
+  yp = ap * s;                                 // -log2(e) SiLU(a)
+  dy = fmaf(yp, fmaf(s, kLn2, -kLn2), s);      // SiLU'(a) = s + SiLU(a) (1 - s)
+}
+
 // Cosine cutoff and its derivative (zero outside); pi_rc = pi / r_c.
 __device__ __forceinline__ void cutoff_fn(float r, float pi_rc, bool valid, float& fc,
                                           float& dfc) {
@@ -331,7 +345,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       f32x4 mv;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        mv[r] = silu_f(acc[b][r] + snd[b][r]);   // f_c (0 if invalid) sits in Y
+        mv[r] = silu_pre(acc[b][r] + snd[b][r]);   // f_c (0 if invalid) sits in Y
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
@@ -353,7 +367,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
     float mm[NMOM];
 #pragma unroll
     for (int y = 0; y < NMOM; ++y) {
-      mm[y] = sm[y * kLdM + lane];
+      mm[y] = -kLn2 * sm[y * kLdM + lane];   // undo the -log2(e) of SiLU
       Mi[y * F_L + c] = mm[y];
     }
     qi[c] = mm[0];
@@ -506,7 +520,7 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
         const float addr = r == 0 ? add.x : r == 1 ? add.y : r == 2 ? add.z : add.w;
         const float a = ga[r] + addr;
         float sv, dsv;
-        silu_and_grad(a, sv, dsv);
+        silu_pre_grad(a, sv, dsv);   // sv = -log2(e) SiLU(a)
         const float da = dmv[r] * dsv;   // dmv holds f_c dm
         S2 = fmaf(da, gd[r], S2);
         mv[r] = sv;
@@ -557,16 +571,19 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       // S1 = sum_c dm_c SiLU(a_c) = sum_y Y[y] G[y]; the sums of m = f_c SiLU(a) against
       // dM1, dM2_aa and 2 dM2_ab (xy, xz, yz) are f_c G[1..3], f_c G[4..6], f_c G[7..9]
       const float t3 = (ux * ux + uy * uy + uz * uz) * (1.0f / 3.0f);
-      const float S1 = G[0] + ux * G[1] + uy * G[2] + uz * G[3] + (ux * ux - t3) * G[4] +
-                       (uy * uy - t3) * G[5] + (uz * uz - t3) * G[6] + ux * uy * G[7] +
-                       ux * uz * G[8] + uy * uz * G[9];
+      // (G carries the -log2(e) of the SiLU operand: the -ln 2 below undoes it)
+      const float S1 = -kLn2 * (G[0] + ux * G[1] + uy * G[2] + uz * G[3] + (ux * ux - t3) * G[4] +
+                                (uy * uy - t3) * G[5] + (uz * uz - t3) * G[6] + ux * uy * G[7] +
+                                ux * uz * G[8] + uy * uz * G[9]);
       const float t23 = (2.0f / 3.0f) * (G[4] + G[5] + G[6]);
       const float ax = G[1] + 2.0f * G[4] * ux + G[7] * uy + G[8] * uz - t23 * ux;
       const float ay = G[2] + G[7] * ux + 2.0f * G[5] * uy + G[9] * uz - t23 * uy;
       const float az = G[3] + G[8] * ux + G[9] * uy + 2.0f * G[6] * uz - t23 * uz;
-      const float rho = fmaf(-inv_s2, S2, dfc * S1);
+      // S2 holds sum_c dE/da_c (W_b' x b)_c with the -log2(e)-scaled W_b' = -log2(e) W_b:
+      // dE/dr's radial part is -S2 / (sigma^2 (-log2 e)) = ln 2 S2 / sigma^2
+      const float rho = fmaf(kLn2 * inv_s2, S2, dfc * S1);
       const float ir = vp ? __builtin_amdgcn_rcpf(gv.w) : 0.f;
-      const float fi = irc * fc;
+      const float fi = -kLn2 * irc * fc;
       const float vx = rho * gv.x * ir + fi * ax;
       const float vy = rho * gv.y * ir + fi * ay;
       const float vz = rho * gv.z * ir + fi * az;
