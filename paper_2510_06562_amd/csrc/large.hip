@@ -205,11 +205,13 @@ __device__ __forceinline__ float ycomp(int y, float ux, float uy, float uz) {
 // Component y of Y(u) as p_a p_b - d |u|^2 for a fixed row y: p_0 = 1, p_1..3 = u_x, u_y,
 // u_z, and d = 1/3 on the diagonal rows 4..6 of the traceless second moment.  Rows past 9
 // give 1 (any finite value will do there).  For a lane-constant row the choices of p_a, p_b
-// are lane masks set once, and a component costs two selects per factor.
+// are lane masks set once, and a component costs two selects per factor.  It is formed
+// from d_ij itself (u = d_ij / r_c): `s` = r_c^-degree of the row scales it.
 struct YRow {
   bool ax, ay, az, bx, by, bz;   // p_a, p_b = u_x, u_y, u_z (else 1)
-  float d;
-  __device__ explicit YRow(int y) {
+  float d, s;
+  __device__ YRow(int y, float irc) {
+    s = y >= 1 && y <= 3 ? irc : y >= 4 && y <= 9 ? irc * irc : 1.0f;
     const int a = y >= 1 && y <= 3 ? y : y >= 4 && y <= 6 ? y - 3 : y == 7 || y == 8 ? 1 : y == 9 ? 2 : 0;
     const int b = y >= 4 && y <= 6 ? y - 3 : y == 7 ? 2 : y == 8 || y == 9 ? 3 : 0;
     ax = a == 1;
@@ -288,7 +290,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   const float inv_s2 = 1.0f / (P.sigma * P.sigma);
   const float irc = 1.0f / P.rc;
   const float pi_rc = 3.14159265358979f * irc;
-  const YRow yrow(cl);   // the lane's row of M^T
+  const YRow yrow(cl, irc);   // the lane's row of M^T
   const int row0 = offs[i], row1 = offs[i + 1];
   for (int t0 = row0; t0 < row1; t0 += kTile) {
     // A operand of a = b W_b: b_k of pair cl at k = 8 g + e, as NP bfloat16 terms
@@ -318,8 +320,7 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
       // f_c of the pair is folded into its Y components (the A operand of M^T), so the
       // m operand below is SiLU(a) alone; an invalid pair has f_c = 0 and finite
       // (zero-padded) geometry, so its Y needs no select
-      const float ur = gv.w * irc;
-      yop[r] = fc[r] * yrow(gv.x * irc, gv.y * irc, gv.z * irc, ur * ur);
+      yop[r] = (fc[r] * yrow.s) * yrow(gv.x, gv.y, gv.z, gv.w * gv.w);
     }
     // sender terms of the lane's sixteen (pair, channel) values, all requested before the
     // products so that their latencies overlap
