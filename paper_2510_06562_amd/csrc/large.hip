@@ -229,6 +229,28 @@ struct YRow {
   }
 };
 
+// Work-groups go to the eight XCDs (each with its own L2) round-robin: work-group b runs on
+// XCD b mod 8.  The pair kernels give work-group b the channel half (b >> 3) & 1 and a
+// sequence of receiver groups from chunks of kXcdChunk consecutive groups dealt to the
+// XCDs in turn, so that both halves of a receiver group, and runs of neighbouring
+// receivers (which share senders), read their rows, geometry and features through one
+// L2.  The grid is a multiple of 16; item j of the XCD's list is group
+// (j / kXcdChunk * 8 + xcd) * kXcdChunk + j % kXcdChunk, visited by slot j mod slots.
+constexpr int kXcdChunk = 8;
+struct XcdWalk {
+  int half, xcd, slot, slots;
+  __device__ XcdWalk() {
+    const int b = blockIdx.x, k = b >> 3;
+    xcd = b & 7;
+    half = k & 1;
+    slot = k >> 1;
+    slots = gridDim.x >> 4;
+  }
+  __device__ int group(int j) const {
+    return (j / kXcdChunk * 8 + xcd) * kXcdChunk + j % kXcdChunk;
+  }
+};
+
 // The pair kernels accumulate a' = -log2(e) a (every term of the pre-activation is stored
 // with that factor), so that e^-a = 2^a' costs no product: logistic(a) = 1 / (1 + 2^a'),
 // and a' logistic(a) = -log2(e) SiLU(a), whose factor the kernels undo where SiLU(a) leaves
@@ -268,14 +290,15 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   __shared__ __bf16 sW[NP * (F_L / 2) * K_L];   // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   __shared__ float sM[NW][16 * kLdM];   // rows 10..15 (zero moments) unused
-  const int half = blockIdx.x & 1, hb = 4 * half;   // hb: first channel block of the half
+  const XcdWalk xw;
+  const int half = xw.half, hb = 4 * half;   // hb: first channel block of the half
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const int n_ag = (n + NW - 1) / NW;
-  for (int ag = blockIdx.x >> 1; ag < n_ag; ag += gridDim.x >> 1) {
+  for (int j = xw.slot, ag = xw.group(j); ag < n_ag; j += xw.slots, ag = xw.group(j)) {
   const int i = ag * NW + w;
   if (i >= n) continue;
   const int zi_s = species[i];
@@ -398,14 +421,15 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   __shared__ float sD[NW][NMOM * kLdH];          // D[y][cc] of the receiver (dswz)
   __shared__ __align__(16) float sB[NW][F_L / 2];   // receiver term S_i of a_ij
   __shared__ float sR[LAYER == 2 ? NW : 1][LAYER == 2 ? kTile * kLdR : 1];
-  const int half = blockIdx.x & 1, hb = 4 * half;
+  const XcdWalk xw;
+  const int half = xw.half, hb = 4 * half;
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const int n_ag = (n + NW - 1) / NW;
-  for (int ag = blockIdx.x >> 1; ag < n_ag; ag += gridDim.x >> 1) {
+  for (int j = xw.slot, ag = xw.group(j); ag < n_ag; j += xw.slots, ag = xw.group(j)) {
   const int i = ag * NW + w;
   if (i >= n) continue;
   float* sd = sD[w];
@@ -762,7 +786,7 @@ dmts_status large_energy_forces(Model* m, NList* nl, const double* pos, const in
       auto grid_of = [&](auto kernel) {
         const int b = launch_grid(sh.grid, 2 * ceil_div(n, NW),
                                   resident_groups(reinterpret_cast<const void*>(kernel), NW * 64));
-        return dim3(b < 2 ? 2 : b + (b & 1));
+        return dim3(b < 16 ? 16 : (b + 15) & ~15);   // whole XCD-halves quads (XcdWalk)
       };
       const dim3 wg(NW * 64);
       {
