@@ -231,24 +231,25 @@ struct YRow {
 
 // Work-groups go to the eight XCDs (each with its own L2) round-robin: work-group b runs on
 // XCD b mod 8.  The pair kernels give work-group b the channel half (b >> 3) & 1 and a
-// sequence of receiver groups from chunks of kXcdChunk consecutive groups dealt to the
-// XCDs in turn, so that both halves of a receiver group, and runs of neighbouring
-// receivers (which share senders), read their rows, geometry and features through one
-// L2.  The grid is a multiple of 16; item j of the XCD's list is group
-// (j / kXcdChunk * 8 + xcd) * kXcdChunk + j % kXcdChunk, visited by slot j mod slots.
+// sequence of receiver groups from chunks of `chunk` consecutive groups dealt to the XCDs
+// in turn, so that both halves of a receiver group, and runs of neighbouring receivers
+// (which share senders), read their rows, geometry and features through one L2.  The
+// chunk is kXcdChunk, or fewer where the XCD's slots would otherwise outnumber its groups
+// (a small system still spreads over every XCD).  The grid is a multiple of 16; item j of
+// the XCD's list is group (j / chunk * 8 + xcd) * chunk + j % chunk, visited by slot
+// j mod slots.
 constexpr int kXcdChunk = 8;
 struct XcdWalk {
-  int half, xcd, slot, slots;
-  __device__ XcdWalk() {
+  int half, xcd, slot, slots, chunk;
+  __device__ explicit XcdWalk(int n_ag) {
     const int b = blockIdx.x, k = b >> 3;
     xcd = b & 7;
     half = k & 1;
     slot = k >> 1;
     slots = gridDim.x >> 4;
+    chunk = min(kXcdChunk, max(1, n_ag / (8 * slots)));
   }
-  __device__ int group(int j) const {
-    return (j / kXcdChunk * 8 + xcd) * kXcdChunk + j % kXcdChunk;
-  }
+  __device__ int group(int j) const { return (j / chunk * 8 + xcd) * chunk + j % chunk; }
 };
 
 // The pair kernels accumulate a' = -log2(e) a (every term of the pre-activation is stored
@@ -290,14 +291,14 @@ k_pair_fwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   __shared__ __bf16 sW[NP * (F_L / 2) * K_L];   // W_b [c][k] terms of the half
   __shared__ float sTs[LAYER == 1 ? Z_MAX * F_L : 1];
   __shared__ float sM[NW][16 * kLdM];   // rows 10..15 (zero moments) unused
-  const XcdWalk xw;
+  const int n_ag = (n + NW - 1) / NW;
+  const XcdWalk xw(n_ag);
   const int half = xw.half, hb = 4 * half;   // hb: first channel block of the half
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int n_ag = (n + NW - 1) / NW;
   for (int j = xw.slot, ag = xw.group(j); ag < n_ag; j += xw.slots, ag = xw.group(j)) {
   const int i = ag * NW + w;
   if (i >= n) continue;
@@ -421,14 +422,14 @@ k_pair_bwd_mfma(LargeParams P, const int32_t* __restrict__ offs, const int32_t* 
   __shared__ float sD[NW][NMOM * kLdH];          // D[y][cc] of the receiver (dswz)
   __shared__ __align__(16) float sB[NW][F_L / 2];   // receiver term S_i of a_ij
   __shared__ float sR[LAYER == 2 ? NW : 1][LAYER == 2 ? kTile * kLdR : 1];
-  const XcdWalk xw;
+  const int n_ag = (n + NW - 1) / NW;
+  const XcdWalk xw(n_ag);
   const int half = xw.half, hb = 4 * half;
   stage_w<NP>(sW, P.Wb, half);
   if (LAYER == 1)
     for (int e = threadIdx.x; e < P.Z * F_L; e += blockDim.x) sTs[e] = P.Ts[e];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int n_ag = (n + NW - 1) / NW;
   for (int j = xw.slot, ag = xw.group(j); ag < n_ag; j += xw.slots, ag = xw.group(j)) {
   const int i = ag * NW + w;
   if (i >= n) continue;
