@@ -29,8 +29,8 @@ namespace {
 
 constexpr int kWaves = 4;
 // Pair kernels: a work-group owns one channel half (64 channels) of kWaves receivers, one
-// wave each; work-group b takes half b & 1, so the grid is even and a work-group keeps its
-// half (and the staged weights of that half) over its grid-stride loop.
+// wave each, and keeps its half (and the staged weights of that half) over its grid-stride
+// loop; which half and which receivers follow the XCD-aware walk below (XcdWalk).
 constexpr int K_L = 32;
 constexpr int F_L = 128;
 constexpr int Z_MAX = 8;
